@@ -1,0 +1,308 @@
+"""Homomorphic programs of the workloads, on the oracle's BFV (test infrastructure only).
+
+The programs follow the appendix "Implementation Details":
+  * batch packing: slot b holds image b; one ciphertext per input pixel, and
+    a conv or dense layer is a multiply-accumulate of ciphertexts with scalar
+    weights (Mult(c,u) by a constant, Add(c1,c2));
+  * HW packing: one ciphertext per input channel, pixel (y, x) at slot
+    row*y + x of slot row 0; a convolution rotates the channel ciphertext by
+    each kernel offset, multiplies by the scalar kernel weight, sums, and
+    multiplies by a mask that keeps the valid output slots;
+  * sum pooling ("Homomorphic pooling layer") and the HW dense layer end with
+    a rotate-and-sum S <- S + Rot(S, r), r = span/2 ... 1, leaving the sum of
+    the first ``span`` slots in slot 0;
+  * plaintext-branch features are added after the convolution (and its mask)
+    as encoded plaintexts (section "The unidirectional connections");
+  * each square activation is followed by relinearisation and, while at least
+    two primes remain, a modulus switch.
+Rotations of one ciphertext by several kernel offsets share one digit
+decomposition (hoisting), which is bit-identical to rotating one at a time.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import synthetic
+from synthetic import workloads as W
+
+from . import bfv, network, params
+from .encoder import BatchEncoder
+
+RELIN_KEY_ID = 0
+
+
+def galois_key_id(r: int) -> int:
+    return 1000 + r
+
+
+def _span(max_slot: int) -> int:
+    s = 1
+    while s < max_slot + 1:
+        s *= 2
+    return s
+
+
+def plan(name: str):
+    """Static layout of a workload: per-layer geometry and the rotation steps it needs."""
+    wl = W.WORKLOADS[name]
+    shapes = W.layer_shapes(name)
+    row = wl["crop"][1]
+    ps = 1                      # spacing of valid positions (HW packing)
+    steps = set()
+    layers = []
+    spatial = True
+    for li, lay in enumerate(wl["layers"]):
+        (cin, *hw_in), out = shapes[li]
+        info = dict(lay)
+        info["in_shape"], info["out_shape"] = shapes[li][0], out
+        if wl["packing"] == "hw":
+            if lay["kind"] == "conv":
+                offs = [ps * (row * di + dj) for di in range(lay["k"]) for dj in range(lay["k"])]
+                info["offsets"] = offs
+                steps.update(o for o in offs if o)
+                ps_out = ps * lay["stride"]
+                oh, ow = out[1], out[2]
+                info["out_slots"] = [ps_out * (row * i + j) for i in range(oh) for j in range(ow)]
+                ps = ps_out
+                if lay.get("sum"):
+                    span = _span(max(info["out_slots"]))
+                    info["sum_span"] = span
+                    steps.update(span >> (k + 1) for k in range(span.bit_length() - 1))
+                    spatial = False
+            elif spatial:
+                # dense over spatially laid out channels: weight vectors + rotate-and-sum
+                prev = layers[-1]
+                info["in_slots"] = prev["out_slots"]
+                span = _span(max(prev["out_slots"]))
+                info["sum_span"] = span
+                steps.update(span >> (k + 1) for k in range(span.bit_length() - 1))
+                spatial = False
+        layers.append(info)
+    return dict(row=row, layers=layers, steps=sorted(steps))
+
+
+class OracleSession:
+    """Keys, encryptions and evaluation of one workload on the oracle."""
+
+    def __init__(self, name: str, seeds=None, with_galois=True):
+        self.name = name
+        self.wl = W.WORKLOADS[name]
+        self.prm = params.get(self.wl["params"])
+        self.seeds = dict(W.SEEDS if seeds is None else seeds)
+        self.enc = BatchEncoder(self.prm.n, self.prm.t)
+        self.plan = plan(name)
+        prm, n = self.prm, self.prm.n
+        self.s = [int(x) for x in synthetic.ternary_secret(self.seeds["keys"], n)]
+        moduli = list(prm.q) + list(prm.p)
+        a_r, e_r = self.key_randomness(RELIN_KEY_ID)
+        self.rk = bfv.relin_key(prm, self.s, a_r, e_r)
+        self.gk = {}
+        if with_galois:
+            for r in self.plan["steps"]:
+                self.gk[r] = self.galois(r)
+        self.inputs = W.make_inputs(name, self.seeds)
+
+    def key_randomness(self, key_id: int):
+        prm = self.prm
+        moduli = list(prm.q) + list(prm.p)
+        d = prm.dnum(prm.L)
+        a = [synthetic.uniform_residues(self.seeds["keys"], "ksk_a", (key_id, j), moduli, prm.n) for j in range(d)]
+        e = [synthetic.gaussian_error(self.seeds["keys"], "ksk_e", (key_id, j), prm.n) for j in range(d)]
+        return a, e
+
+    def galois(self, r: int):
+        if r not in self.gk:
+            a_r, e_r = self.key_randomness(galois_key_id(r))
+            self.gk[r] = bfv.galois_key(self.prm, self.s, r, a_r, e_r)
+        return self.gk[r]
+
+    # ------------------------------------------------------------ inputs
+
+    def input_slots(self) -> np.ndarray:
+        """Slot vectors of the input ciphertexts, [n_ct][N] int64."""
+        wl, n = self.wl, self.prm.n
+        y0, size = wl["crop"]
+        crop = self.inputs["images"][:, :, y0:y0 + size, y0:y0 + size].astype(np.int64)
+        if wl["packing"] == "batch":
+            b = crop.shape[0]
+            flat = crop.reshape(b, -1).T               # [C*H*W][batch], (c, y, x) order
+            out = np.zeros((flat.shape[0], n), dtype=np.int64)
+            out[:, :b] = flat
+            return out
+        c = crop.shape[1]
+        out = np.zeros((c, n), dtype=np.int64)
+        for ch in range(c):
+            for y in range(size):
+                out[ch, size * y:size * y + size] = crop[0, ch, y]
+        return out
+
+    def encrypt_slots(self, slots, index: int, level=None) -> bfv.Ct:
+        prm = self.prm
+        level = prm.L if level is None else level
+        a = synthetic.uniform_residues(self.seeds["enc"], "enc_a", (index,), prm.q[:level], prm.n)
+        e = synthetic.gaussian_error(self.seeds["enc"], "enc_e", (index,), prm.n)
+        return bfv.encrypt(prm, self.s, self.enc.encode(slots), a, e, level)
+
+    def encrypt_inputs(self, indices=None):
+        slots = self.input_slots()
+        idx = range(len(slots)) if indices is None else indices
+        return {i: self.encrypt_slots(slots[i], i) for i in idx}
+
+    def decrypt_slots(self, ct: bfv.Ct) -> np.ndarray:
+        return self.enc.centered(self.enc.decode(bfv.decrypt(self.prm, self.s, ct)))
+
+    # ------------------------------------------------------------ plaintexts
+
+    def feature_slots(self, li: int, o: int) -> np.ndarray:
+        """Slot vector of the features added to output map o of layer li (per position)."""
+        wl, n = self.wl, self.prm.n
+        f = network.quantise(self.inputs["features"][li])
+        info = self.plan["layers"][li]
+        out = np.zeros(n, dtype=np.int64)
+        if wl["packing"] == "batch":
+            return f[:, o]                             # [batch][oh][ow]; caller picks (i, j)
+        for pos, slot in enumerate(info["out_slots"]):
+            i, j = divmod(pos, info["out_shape"][2])
+            out[slot] = f[o, i, j]
+        return out
+
+    def mask_slots(self, li: int) -> np.ndarray:
+        out = np.zeros(self.prm.n, dtype=np.int64)
+        out[self.plan["layers"][li]["out_slots"]] = 1
+        return out
+
+    # ------------------------------------------------------------ layers
+
+    def conv_batch(self, li: int, cts: dict, outputs=None) -> dict:
+        """Batch-packed conv (+features, square, modswitch) for output indices ``outputs``.
+
+        cts maps input index (c*H*W + y*W + x) -> Ct; outputs are (o*oh + i)*ow + j.
+        """
+        prm, info = self.prm, self.plan["layers"][li]
+        w = self.inputs["weights"][li]
+        cin, h, wd = info["in_shape"]
+        O, oh, ow = info["out_shape"]
+        k, s, p = info["k"], info["stride"], info["pad"]
+        outputs = range(O * oh * ow) if outputs is None else outputs
+        res = {}
+        for idx in outputs:
+            o, rem = divmod(idx, oh * ow)
+            i, j = divmod(rem, ow)
+            terms, ws = [], []
+            for c in range(cin):
+                for di in range(k):
+                    for dj in range(k):
+                        y, x = s * i + di - p, s * j + dj - p
+                        if 0 <= y < h and 0 <= x < wd:
+                            terms.append(cts[(c * h + y) * wd + x])
+                            ws.append(int(w[o, c, di, dj]))
+            ct = bfv.mac(prm, terms, ws)
+            if info.get("features"):
+                fq = network.quantise(self.inputs["features"][li])[:, o, i, j]
+                slots = np.zeros(prm.n, dtype=np.int64)
+                slots[:len(fq)] = fq
+                ct = bfv.add_plain(prm, ct, self.enc.encode(slots))
+            res[idx] = self._activation(ct, info)
+        return res
+
+    def dense_scalar(self, li: int, cts: dict, outputs=None) -> dict:
+        prm, info = self.prm, self.plan["layers"][li]
+        w = self.inputs["weights"][li]
+        n_out, n_in = w.shape
+        outputs = range(n_out) if outputs is None else outputs
+        res = {}
+        for o in outputs:
+            ct = bfv.mac(prm, [cts[i] for i in range(n_in)], [int(x) for x in w[o]])
+            res[o] = self._activation(ct, info)
+        return res
+
+    def conv_hw(self, li: int, cts: dict, outputs=None) -> dict:
+        prm, info = self.prm, self.plan["layers"][li]
+        w = self.inputs["weights"][li]
+        O, cin, k, _ = w.shape
+        rot = {}
+        for c in range(cin):
+            offs = info["offsets"]
+            nz = [o for o in offs if o]
+            rots = bfv.rotate_hoisted(prm, cts[c], nz, [self.gk[o] for o in nz])
+            table = dict(zip(nz, rots))
+            table[0] = cts[c]
+            rot[c] = [table[o] for o in offs]
+        mask = self.enc.encode(self.mask_slots(li))
+        outputs = range(O) if outputs is None else outputs
+        res = {}
+        for o in outputs:
+            terms, ws = [], []
+            for c in range(cin):
+                for t_i, ct in enumerate(rot[c]):
+                    di, dj = divmod(t_i, k)
+                    terms.append(ct)
+                    ws.append(int(w[o, c, di, dj]))
+            ct = bfv.mac(prm, terms, ws)
+            ct = bfv.mul_plain(prm, ct, mask)
+            if info.get("features"):
+                ct = bfv.add_plain(prm, ct, self.enc.encode(self.feature_slots(li, o)))
+            ct = self._activation(ct, info)
+            if info.get("sum_span"):
+                ct = self.rotate_sum(ct, info["sum_span"])
+            res[o] = ct
+        return res
+
+    def dense_hw(self, li: int, cts: dict, outputs=None) -> dict:
+        prm, info = self.prm, self.plan["layers"][li]
+        w = self.inputs["weights"][li]
+        n_out = w.shape[0]
+        cin = len(cts)
+        slots_in = info["in_slots"]
+        per = len(slots_in)
+        outputs = range(n_out) if outputs is None else outputs
+        res = {}
+        for kk in outputs:
+            acc = None
+            for c in range(cin):
+                v = np.zeros(prm.n, dtype=np.int64)
+                v[slots_in] = w[kk, c * per:(c + 1) * per]
+                term = bfv.mul_plain(prm, cts[c], self.enc.encode(v))
+                acc = term if acc is None else bfv.add(prm, acc, term)
+            acc = self.rotate_sum(acc, info["sum_span"])
+            res[kk] = self._activation(acc, info)
+        return res
+
+    def rotate_sum(self, ct, span: int):
+        r = span // 2
+        while r >= 1:
+            ct = bfv.add(self.prm, ct, bfv.rotate(self.prm, ct, r, self.gk[r]))
+            r //= 2
+        return ct
+
+    def _activation(self, ct, info):
+        if info.get("square"):
+            ct = bfv.square(self.prm, ct, self.rk)
+            if ct.level >= 2:
+                ct = bfv.modswitch(self.prm, ct)
+        return ct
+
+    # ------------------------------------------------------------ whole program
+
+    def run(self, cts: dict) -> dict:
+        hw = self.wl["packing"] == "hw"
+        spatial = True
+        for li, info in enumerate(self.plan["layers"]):
+            if info["kind"] == "conv":
+                cts = self.conv_hw(li, cts) if hw else self.conv_batch(li, cts)
+                if info.get("sum_span"):
+                    spatial = False
+            elif hw and spatial:
+                cts = self.dense_hw(li, cts)
+                spatial = False
+            else:
+                cts = self.dense_scalar(li, cts)
+        return cts
+
+    def output_values(self, outs: dict) -> np.ndarray:
+        """Decrypted network outputs: batch -> [batch][n_out]; HW -> [1][n_out] (slot 0)."""
+        vals = [self.decrypt_slots(outs[k]) for k in sorted(outs)]
+        if self.wl["packing"] == "batch":
+            b = self.wl["batch"]
+            return np.stack([v[:b] for v in vals], axis=1)
+        return np.array([[v[0] for v in vals]])

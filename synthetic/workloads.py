@@ -1,0 +1,113 @@
+"""Workload recipes: shapes, crops, value ranges and seeds of the synthetic inputs.
+
+Descriptive data only (no scheme arithmetic).  The sensitive segment is the
+central crop of each image (the paper's experiments encrypt the central part
+of the image; section "Our bi-CryptoNets", Experiments section).  Images stand
+in for MNIST (28x28x1) and CIFAR (32x32x3): uniform uint8 of the same shape,
+never dataset items.
+
+Layer entries:
+  conv  : out channels, kernel k, stride, pad, weight bound, features?, square?
+  dense : out units, weight bound, square?
+  For 'hw' packing a conv output (y, x) lives at the slot of its top-left tap,
+  so a strided conv leaves its outputs spread at the stride; 'sum' on a layer
+  asks for a global sum of each output map (sum pooling over all positions).
+"""
+from __future__ import annotations
+
+SEEDS = dict(keys=1, enc=2, weights=3, images=4, features=5)
+
+WORKLOADS = {
+    # one 28x28 image, HW packing, central 12x12 crop
+    "cfg1": dict(params="cfg1", packing="hw", batch=1, image=(1, 28, 28), crop=(8, 12),
+                 layers=[dict(kind="conv", out=5, k=5, stride=2, pad=0, bound=7, features=False, square=True),
+                         dict(kind="dense", out=10, bound=7, square=False)]),
+    # same network on five limbs, so the output still decrypts (insecure, test only)
+    "cfg1d": dict(params="cfg1d", packing="hw", batch=1, image=(1, 28, 28), crop=(8, 12),
+                  layers=[dict(kind="conv", out=5, k=5, stride=2, pad=0, bound=7, features=False, square=True),
+                          dict(kind="dense", out=10, bound=7, square=False)]),
+    # 8192 28x28 images, one image per slot, central 16x16 crop
+    "cfg2": dict(params="cfg2", packing="batch", batch=8192, image=(1, 28, 28), crop=(6, 16),
+                 layers=[dict(kind="conv", out=5, k=5, stride=2, pad=1, bound=15, features=True, square=True),
+                         dict(kind="dense", out=100, bound=15, square=True),
+                         dict(kind="dense", out=10, bound=15, square=False)]),
+    # one 32x32x3 image, HW packing (one channel per ciphertext), central 16x16 crop
+    "cfg3": dict(params="cfg3", packing="hw", batch=1, image=(3, 32, 32), crop=(8, 16),
+                 layers=[dict(kind="conv", out=32, k=3, stride=1, pad=0, bound=31, features=True, square=True),
+                         dict(kind="conv", out=64, k=3, stride=2, pad=0, bound=31, features=True, square=True,
+                              sum=True),
+                         dict(kind="dense", out=10, bound=31, square=False)]),
+    # reduced variants the oracle finishes in seconds (same layer kinds)
+    "cfg2_small": dict(params="t1k", packing="batch", batch=1024, image=(1, 28, 28), crop=(6, 16),
+                       layers=[dict(kind="conv", out=2, k=5, stride=2, pad=1, bound=15, features=True, square=True),
+                               dict(kind="dense", out=7, bound=15, square=True),
+                               dict(kind="dense", out=3, bound=15, square=False)]),
+    "cfg1_small": dict(params="t1k5", packing="hw", batch=1, image=(1, 28, 28), crop=(8, 12),
+                       layers=[dict(kind="conv", out=2, k=5, stride=2, pad=0, bound=7, features=False, square=True),
+                               dict(kind="dense", out=3, bound=7, square=False)]),
+    "cfg3_small": dict(params="t2k3", packing="hw", batch=1, image=(3, 32, 32), crop=(8, 16),
+                       layers=[dict(kind="conv", out=3, k=3, stride=1, pad=0, bound=31, features=True, square=True),
+                               dict(kind="conv", out=2, k=3, stride=2, pad=0, bound=31, features=True, square=True,
+                                    sum=True),
+                               dict(kind="dense", out=3, bound=31, square=False)]),
+}
+
+
+def layer_shapes(name: str):
+    """(in_shape, out_shape) per layer as (channels, height, width) or (units,)."""
+    w = WORKLOADS[name]
+    c = w["image"][0]
+    h = wd = w["crop"][1]
+    shapes = []
+    cur = (c, h, wd)
+    for lay in w["layers"]:
+        if lay["kind"] == "conv":
+            ci, hi, wi = cur
+            oh = (hi + 2 * lay["pad"] - lay["k"]) // lay["stride"] + 1
+            ow = (wi + 2 * lay["pad"] - lay["k"]) // lay["stride"] + 1
+            out = (lay["out"], oh, ow)
+            if lay.get("sum"):
+                out_after = (lay["out"],)
+            else:
+                out_after = out
+            shapes.append((cur, out))
+            cur = out_after
+        else:
+            n_in = 1
+            for d in cur:
+                n_in *= d
+            out = (lay["out"],)
+            shapes.append(((n_in,), out))
+            cur = out
+    return shapes
+
+
+def weight_shape(name: str, li: int):
+    lay = WORKLOADS[name]["layers"][li]
+    (cin, *rest), out = layer_shapes(name)[li]
+    if lay["kind"] == "conv":
+        return (lay["out"], cin, lay["k"], lay["k"])
+    return (lay["out"], cin if not rest else cin * rest[0] * rest[1])
+
+
+def feature_shape(name: str, li: int):
+    """Per-image feature map shape (out channels, out h, out w) of a conv layer with features."""
+    return layer_shapes(name)[li][1]
+
+
+def make_inputs(name: str, seeds=SEEDS):
+    """All raw inputs of a workload: images, weights and features."""
+    from . import images as _images, int_weights, features as _features
+    w = WORKLOADS[name]
+    c, h, wd = w["image"]
+    imgs = _images(seeds["images"], w["batch"], h, wd, c)
+    weights, feats = [], []
+    for li, lay in enumerate(w["layers"]):
+        weights.append(int_weights(seeds["weights"], li, weight_shape(name, li), lay["bound"]))
+        if lay.get("features"):
+            fs = feature_shape(name, li)
+            shape = (w["batch"],) + fs if w["packing"] == "batch" else fs
+            feats.append(_features(seeds["features"], li, shape))
+        else:
+            feats.append(None)
+    return dict(images=imgs, weights=weights, features=feats)

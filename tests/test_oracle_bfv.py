@@ -1,0 +1,224 @@
+"""Pins of the oracle's BFV against the appendix identities (CKKS Scheme
+section: D(Add(c,u)) = D(c)+u, D(Add(c1,c2)) = D(c1)+D(c2), D(Mult(c,u)) =
+D(c)*u, D(Mult(c1,c2)) = D(c1)*D(c2), D(Rot(c,r)) = <D(c)>_r), against an
+independent evaluation of the exact definitions (schoolbook products and
+Fraction rounding), and against the noise-budget invariant."""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import bfv, nt, params, ring
+from oracle.encoder import BatchEncoder
+
+PRM = params.get("t1k")        # N=1024, 3 x 36-bit, P 1 x 36-bit, t=65537
+PRM2 = params.get("t2k")       # N=2048, 4 x 40-bit, P 2 x 40-bit, alpha=2
+
+
+class Ctx:
+    def __init__(self, prm, seed=11):
+        self.prm = prm
+        self.enc = BatchEncoder(prm.n, prm.t)
+        self.s = [int(x) for x in synthetic.ternary_secret(seed, prm.n)]
+        self.seed = seed
+        self.count = 0
+        self.moduli = list(prm.q) + list(prm.p)
+
+    def rand_key(self, kid):
+        d = self.prm.dnum(self.prm.L)
+        a = [synthetic.uniform_residues(self.seed, "ksk_a", (kid, j), self.moduli, self.prm.n) for j in range(d)]
+        e = [synthetic.gaussian_error(self.seed, "ksk_e", (kid, j), self.prm.n) for j in range(d)]
+        return a, e
+
+    def encrypt(self, v, level=None):
+        level = self.prm.L if level is None else level
+        self.count += 1
+        a = synthetic.uniform_residues(self.seed, "enc_a", (self.count,), self.prm.q[:level], self.prm.n)
+        e = synthetic.gaussian_error(self.seed, "enc_e", (self.count,), self.prm.n)
+        return bfv.encrypt(self.prm, self.s, self.enc.encode(v), a, e, level)
+
+    def dec(self, ct):
+        return self.enc.decode(bfv.decrypt(self.prm, self.s, ct))
+
+    def budget(self, ct, v):
+        return bfv.noise_budget(self.prm, self.s, ct, self.enc.encode(v))
+
+
+@pytest.fixture(scope="module")
+def cx():
+    c = Ctx(PRM)
+    a, e = c.rand_key(0)
+    c.rk = bfv.relin_key(PRM, c.s, a, e)
+    return c
+
+
+@pytest.fixture(scope="module")
+def cx2():
+    c = Ctx(PRM2, seed=12)
+    a, e = c.rand_key(0)
+    c.rk = bfv.relin_key(PRM2, c.s, a, e)
+    c.gk = {}
+    for r in (1, 5, 100):
+        a, e = c.rand_key(1000 + r)
+        c.gk[r] = bfv.galois_key(PRM2, c.s, r, a, e)
+    return c
+
+
+def _vec(prm, seed):
+    return np.random.default_rng(seed).integers(0, prm.t, prm.n)
+
+
+def test_encrypt_decrypt_all_levels(cx):
+    t = PRM.t
+    for level in range(1, PRM.L + 1):
+        v = _vec(PRM, level)
+        ct = cx.encrypt(v, level)
+        assert ct.level == level
+        assert (cx.dec(ct) == v).all()
+        b = cx.budget(ct, v)
+        # fresh noise: |t*e + rounding| <= t*(19 + 1/2) -> budget >= log2(Q/(2*t*19.5)) - 1 bit slack
+        assert b >= math.log2(PRM.Q(level) / (2 * t * 19.5)) - 1
+
+
+def test_encryption_matches_independent_evaluation(cx):
+    # c0 = -a*s + e + round(Q*m/t) recomputed with schoolbook product and Fractions on N=8
+    prm = params.make("tiny", 8, 30, 2, 1, 1, 17, insecure=True)
+    s = [1, 0, -1, 1, 1, 0, 0, -1]
+    a_res = synthetic.uniform_residues(5, "enc_a", (0,), prm.q, 8)
+    e = [2, -1, 0, 3, -4, 0, 1, 0]
+    m = [0, 16, 3, 8, 9, 1, 0, 5]
+    ct = bfv.encrypt(prm, s, m, a_res, e)
+    Q = prm.Q(2)
+    a = [nt.crt([int(a_res[0][i]), int(a_res[1][i])], prm.q) for i in range(8)]
+    assert ct.c1 == a
+    as_ = ring.schoolbook_mul(a, s)
+    for i in range(8):
+        want = -as_[i] + e[i] + math.floor(Fraction(Q * m[i], 17) + Fraction(1, 2))
+        assert ct.c0[i] == want % Q
+
+
+def test_add_identities(cx):
+    t = PRM.t
+    u, v, w = _vec(PRM, 1), _vec(PRM, 2), _vec(PRM, 3)
+    cu, cv = cx.encrypt(u), cx.encrypt(v)
+    assert (cx.dec(bfv.add(PRM, cu, cv)) == (u + v) % t).all()
+    assert (cx.dec(bfv.add_plain(PRM, cu, cx.enc.encode(w))) == (u + w) % t).all()
+    assert (cx.dec(bfv.mul_scalar(PRM, cu, -7)) == (-7 * u) % t).all()
+    assert (cx.dec(bfv.mac(PRM, [cu, cv], [3, -2])) == (3 * u - 2 * v) % t).all()
+
+
+def test_mul_plain_identity(cx):
+    t = PRM.t
+    u = _vec(PRM, 4)
+    w = np.random.default_rng(9).integers(-20, 21, PRM.n)
+    out = bfv.mul_plain(PRM, cx.encrypt(u), cx.enc.encode(w))
+    assert (cx.dec(out) == (u * w) % t).all()
+
+
+def test_tensor_is_the_exact_definition():
+    # independent evaluation on N=8: schoolbook products over Z and Fraction rounding
+    prm = params.make("tiny", 8, 30, 2, 1, 1, 17, insecure=True)
+    Q, t = prm.Q(2), prm.t
+    rng = np.random.default_rng(3)
+    a = bfv.Ct([int(x) for x in rng.integers(0, Q, 8)], [int(x) for x in rng.integers(0, Q, 8)], 2)
+    b = bfv.Ct([int(x) for x in rng.integers(0, Q, 8)], [int(x) for x in rng.integers(0, Q, 8)], 2)
+    d = bfv.tensor(prm, a, b)
+
+    def cl(x):
+        x %= Q
+        return x - Q if x > Q // 2 else x
+
+    A0, A1 = [cl(x) for x in a.c0], [cl(x) for x in a.c1]
+    B0, B1 = [cl(x) for x in b.c0], [cl(x) for x in b.c1]
+    e0 = ring.schoolbook_mul(A0, B0)
+    e1 = [x + y for x, y in zip(ring.schoolbook_mul(A0, B1), ring.schoolbook_mul(A1, B0))]
+    e2 = ring.schoolbook_mul(A1, B1)
+    for got, ex in zip(d, (e0, e1, e2)):
+        want = [math.floor(Fraction(t * x, Q) + Fraction(1, 2)) % Q for x in ex]
+        assert got == want
+
+
+def test_mult_relin_identity_and_budget(cx):
+    t = PRM.t
+    u, v = _vec(PRM, 5), _vec(PRM, 6)
+    cu, cv = cx.encrypt(u), cx.encrypt(v)
+    prod = bfv.multiply(PRM, cu, cv, cx.rk)
+    assert (cx.dec(prod) == u * v % t).all()
+    sq = bfv.square(PRM, cu, cx.rk)
+    assert (cx.dec(sq) == u * u % t).all()
+    # budget never increases through an operation
+    b0 = cx.budget(cu, u)
+    b1 = cx.budget(sq, u * u % t)
+    assert 0 < b1 < b0
+
+
+def test_key_switch_correctness(cx):
+    # KS with the relinearisation key maps d2 under s^2 to a pair under s:
+    # k0 + k1*s = d2*s^2 + small (mod Q)
+    prm = PRM
+    Q = prm.Q(prm.L)
+    x = bfv.from_rns(synthetic.test_poly(8, 0, prm.q, prm.n), prm.q)
+    k0, k1 = bfv.key_switch(prm, x, cx.rk, prm.L)
+    s2 = ring.negacyclic_mul(cx.s, cx.s)
+    lhs = [(a + b) % Q for a, b in zip(k0, ring.negacyclic_mul(k1, cx.s))]
+    rhs = ring.reduce(ring.negacyclic_mul(x, s2), Q)
+    err = max(abs(nt.centered(a - b, Q)) for a, b in zip(lhs, rhs))
+    # error = sum_j D_j e_j / P + rounding: far below Q
+    assert err < 2 ** 30
+
+
+def test_rotation_identity_and_hoisting(cx2):
+    prm, t = PRM2, PRM2.t
+    v = _vec(prm, 7)
+    ct = cx2.encrypt(v)
+    half = prm.n // 2
+    single = {}
+    for r in (1, 5, 100):
+        out = bfv.rotate(prm, ct, r, cx2.gk[r])
+        want = np.concatenate([np.roll(v[:half], -r), np.roll(v[half:], -r)])
+        assert (cx2.dec(out) == want).all()
+        single[r] = out
+    hoisted = bfv.rotate_hoisted(prm, ct, [1, 5, 100], [cx2.gk[r] for r in (1, 5, 100)])
+    for r, h in zip((1, 5, 100), hoisted):
+        assert h.c0 == single[r].c0 and h.c1 == single[r].c1
+
+
+def test_rotation_at_partial_digit_level(cx2):
+    # alpha = 2, level 3: the second digit has one prime left
+    prm = PRM2
+    v = _vec(prm, 8)
+    ct = cx2.encrypt(v, level=3)
+    out = bfv.rotate(prm, ct, 1, cx2.gk[1])
+    half = prm.n // 2
+    want = np.concatenate([np.roll(v[:half], -1), np.roll(v[half:], -1)])
+    assert (cx2.dec(out) == want).all()
+
+
+def test_modswitch_preserves_plaintext_and_is_exact_rounding(cx):
+    prm, t = PRM, PRM.t
+    u = _vec(prm, 9)
+    ct = cx.encrypt(u)
+    ms = bfv.modswitch(prm, ct)
+    assert ms.level == prm.L - 1
+    assert (cx.dec(ms) == u).all()
+    ql = prm.q[prm.L - 1]
+    for i in range(0, prm.n, 97):
+        x = ct.c0[i]
+        assert ms.c0[i] == math.floor(Fraction(x, ql) + Fraction(1, 2)) % prm.Q(prm.L - 1)
+
+
+def test_budget_zero_means_failure():
+    # one 30-bit prime: a fresh ciphertext decrypts, its square cannot
+    prm = params.make("onelimb", 1024, 30, 1, 1, 1, 65537, insecure=True)
+    c = Ctx(prm, seed=21)
+    a, e = c.rand_key(0)
+    rk = bfv.relin_key(prm, c.s, a, e)
+    v = _vec(prm, 10)
+    ct = c.encrypt(v)
+    assert c.budget(ct, v) > 0 and (c.dec(ct) == v).all()
+    sq = bfv.square(prm, ct, rk)
+    want = v * v % prm.t
+    assert c.budget(sq, want) <= 0
+    assert not (c.dec(sq) == want).all()
