@@ -1,0 +1,209 @@
+/*
+ * bcn.h -- C ABI of the MI355X ciphertext-branch engine for bi-CryptoNets
+ * (arXiv 2402.01296): homomorphic evaluation of the ciphertext branch in
+ * RNS-BFV over R_Q = Z_Q[X]/(X^N+1), Q = q_1...q_L.
+ *
+ * The paper's operation set (appendix "CKKS Scheme"): E, D, Add(c,u),
+ * Add(c1,c2), Mult(c,u), Mult(c1,c2), Rot(c,r), with Rot a cyclic left shift
+ * of the slot vector by r.  Its layers (appendix "Implementation Details"):
+ * HW-packed convolution by rotate / scalar-multiply / sum / mask, sum
+ * pooling, fully connected layers; batch packing puts one image per slot.
+ * Plaintext-branch features enter by Add(c,u) after a convolution (section
+ * "The unidirectional connections"); activations are squares.
+ *
+ * Conventions
+ *  - All functions return 0 (BCN_OK) or a negative BCN_ERR_* code; the
+ *    message of the last failure on the calling thread is bcn_last_error().
+ *  - A ciphertext at level l (l primes) is caller-owned device memory of
+ *    2*l*N doubles, layout [2][l][N]: part, limb, coefficient.  Each entry
+ *    is a binary64 holding an integer residue in [0, q_i) of the coefficient
+ *    form.  A batch of n ciphertexts is n such blocks back to back.
+ *  - Slot vectors are int64 [N]; slot s = rho*N/2 + i sits in row rho,
+ *    column i.  Values are taken mod t; decoded values are centred in
+ *    (-t/2, t/2).
+ *  - Device pointers must be valid for the stream passed; host pointers are
+ *    read before the call returns unless stated otherwise.
+ *  - Calls on one context must be issued from one host thread on one stream
+ *    (or be externally serialised): they share the context's scratch arena.
+ *  - The secret key lives in client-side objects (bcn_secret_key) used only
+ *    by encryption, decryption and key generation; evaluation never sees it.
+ */
+#ifndef BCN_H
+#define BCN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* bcn_stream; /* a hipStream_t; NULL = default stream */
+
+enum {
+  BCN_OK = 0,
+  BCN_ERR_INVALID = -1,  /* bad parameters, sizes or layer description */
+  BCN_ERR_LEVEL = -2,    /* level mismatch / not enough primes left */
+  BCN_ERR_KEY = -3,      /* a needed relinearisation or Galois key is missing */
+  BCN_ERR_NOMEM = -4,    /* device allocation failed */
+  BCN_ERR_HIP = -5,      /* HIP runtime error */
+  BCN_ERR_INTERNAL = -6
+};
+
+typedef struct bcn_context bcn_context;
+typedef struct bcn_secret_key bcn_secret_key;
+typedef struct bcn_eval_keys bcn_eval_keys;
+typedef struct bcn_layer bcn_layer;
+
+/* Scheme parameters.  Primes are chosen by rule: the largest q_bits-bit
+ * primes q = 1 mod 2N in descending order (skipping t); the first L form Q,
+ * the next K form the special modulus P; internal auxiliary primes follow.
+ * Key-switching digits are groups of `alpha` consecutive primes of Q. */
+typedef struct {
+  uint32_t n;      /* ring degree N: 1024 .. 16384, power of two */
+  uint32_t q_bits; /* prime size, 25 .. 41 bits */
+  uint32_t L;      /* ciphertext primes, 1 .. 8 */
+  uint32_t K;      /* special primes, 1 .. 3 */
+  uint32_t alpha;  /* primes per key-switching digit */
+  uint64_t t;      /* plaintext modulus: prime < 2^21, t = 1 mod 2N */
+} bcn_params;
+
+const char* bcn_last_error(void);
+
+/* Builds the prime tables on `hip_device` (transform twiddles, slot map). */
+int bcn_context_create(const bcn_params* p, int hip_device, bcn_context** out);
+void bcn_context_destroy(bcn_context* ctx);
+/* Writes the primes (Q, then P, then auxiliary) to out[cap]; counts to n_q, n_p, n_aux. */
+int bcn_context_primes(const bcn_context* ctx, uint64_t* out, int cap, int* n_q, int* n_p, int* n_aux);
+
+/* ---- client side: keys, E and D (appendix "CKKS Scheme": E(.), D(.)) ---- */
+
+/* s: host int8 [N] ternary secret. */
+int bcn_secret_key_create(bcn_context* ctx, const int8_t* s, bcn_secret_key** out);
+void bcn_secret_key_destroy(bcn_secret_key* sk);
+
+int bcn_eval_keys_create(bcn_context* ctx, bcn_eval_keys** out);
+void bcn_eval_keys_destroy(bcn_eval_keys* ek);
+
+enum { BCN_KEY_RELIN = 0, BCN_KEY_ROTATION = 1 };
+/* Generates one key-switching key into ek: kind BCN_KEY_RELIN (s^2 -> s, used
+ * by Mult(c1,c2)) or BCN_KEY_ROTATION for a left rotation by `step` (sigma_k(s)
+ * -> s, k = 3^step mod 2N, used by Rot(c, step)).
+ * For digit j: b_j = -a_j s + e_j + P g_j s' mod Q P with g_j = 1 mod the
+ * primes of digit j and 0 mod the rest of Q.
+ * a: host uint64 [dnum][L+K][N] uniform residues over (Q primes, P primes),
+ * e: host int8 [dnum][N] errors; dnum = ceil(L / alpha).  The caller supplies
+ * the randomness (from its CSPRNG); the library does not sample. */
+int bcn_keygen(bcn_context* ctx, const bcn_secret_key* sk, bcn_eval_keys* ek, int kind, int step,
+               const uint64_t* a, const int8_t* e, bcn_stream stream);
+/* Copies a key out in coefficient form: host uint64 [dnum][2][L+K][N]. */
+int bcn_eval_key_export(bcn_context* ctx, const bcn_eval_keys* ek, int kind, int step, uint64_t* out,
+                        bcn_stream stream);
+
+/* E: encodes n slot vectors (host int64 [n][N]) and encrypts each at `level`:
+ * c = (-a s + e + round(Q_level [m]_t / t), a).  a: host uint64 [n][level][N]
+ * uniform residues, e: host int8 [n][N].  ct_out: device [n][2][level][N]. */
+int bcn_encode_encrypt(bcn_context* ctx, const bcn_secret_key* sk, const int64_t* slots, const uint64_t* a,
+                       const int8_t* e, int n, int level, double* ct_out, bcn_stream stream);
+/* D: m = [round(t [c0 + c1 s]_Q / Q)]_t, decoded to host int64 [n][N] (centred). */
+int bcn_decrypt_decode(bcn_context* ctx, const bcn_secret_key* sk, const double* ct, int n, int level,
+                       int64_t* slots_out, bcn_stream stream);
+
+/* Coefficient-form transfer: host uint64 [n][2][level][N] <-> device ciphertexts. */
+int bcn_ct_export(bcn_context* ctx, const double* ct, int n, int level, uint64_t* host_out, bcn_stream stream);
+int bcn_ct_import(bcn_context* ctx, const uint64_t* host_in, int n, int level, double* ct, bcn_stream stream);
+
+/* ---- server side: evaluation (no secret key) ---- */
+
+/* Negacyclic NTT of raw limbs in place: data device [n_polys][n_limbs][N] doubles,
+ * limb i uses prime id first_prime + i (ids as in bcn_context_primes; the plaintext
+ * modulus t has id n_q + n_p + n_aux).  Forward output position p holds
+ * a(psi^(2j+1)) with j = bitreverse(p), psi the smallest x >= 2 with x^N = -1.
+ * inverse != 0 applies the exact inverse (bit-reversed input, natural output). */
+int bcn_ntt(bcn_context* ctx, double* data, int n_polys, int n_limbs, int first_prime, int inverse,
+            bcn_stream stream);
+
+/* out[o] = sum_j w[o][j] in[j] (Mult(c,u) by scalars, Add(c1,c2)); w host int32 [n_out][n_in]. */
+int bcn_mac(bcn_context* ctx, const double* in, int n_in, double* out, int n_out, int level, const int32_t* w,
+            bcn_stream stream);
+/* Add(c, u): c0 += round(Q_level [m]_t / t), m = encode(slots[i]); slots host int64 [n][N]. */
+int bcn_add_plain(bcn_context* ctx, double* ct, int n, int level, const int64_t* slots, bcn_stream stream);
+/* Mult(c, u): c_k * lift_c(m), m = encode(slots) (host int64 [N], shared by the n ciphertexts). */
+int bcn_mul_plain(bcn_context* ctx, const double* in, double* out, int n, int level, const int64_t* slots,
+                  bcn_stream stream);
+/* Mult(c, c) + relinearisation (exact BFV tensor and rounding, hybrid key switching);
+ * with modswitch != 0 the result is also switched down one prime (level-1 limbs). */
+int bcn_square_relin(bcn_context* ctx, const bcn_eval_keys* ek, const double* in, double* out, int n, int level,
+                     int modswitch, bcn_stream stream);
+/* Rot(c, r) for each input and each step, sharing one digit decomposition per input
+ * (hoisting; bit-identical to one-at-a-time).  out device [n_in][n_steps][2][level][N]. */
+int bcn_rotate(bcn_context* ctx, const bcn_eval_keys* ek, const double* in, int n_in, int level,
+               const int32_t* steps, int n_steps, double* out, bcn_stream stream);
+/* In place: c <- c + Rot(c, r) for r = span/2, ..., 2, 1 (span a power of two):
+ * slot 0 of each row receives the sum of its first span slots. */
+int bcn_rotate_sum(bcn_context* ctx, const bcn_eval_keys* ek, double* ct, int n, int level, int span,
+                   bcn_stream stream);
+/* Exact modulus switch: c' = (c - lift_c([c]_{q_l})) / q_l mod Q_{l-1}. */
+int bcn_modswitch(bcn_context* ctx, const double* in, double* out, int n, int level, bcn_stream stream);
+
+/* ---- layers ---- */
+enum { BCN_CONV2D = 0, BCN_DENSE = 1 };
+enum { BCN_PACK_BATCH = 0, BCN_PACK_HW = 1 };
+
+/* One layer of the ciphertext branch: linear part, then (HW conv) the mask of
+ * valid outputs, then the optional feature injection, square+relinearisation,
+ * modulus switch and (HW) global sum.
+ *
+ * BATCH packing (slot b = image b): inputs are one ciphertext per input
+ *   element in (c, y, x) order; CONV2D outputs one ciphertext per (o, i, j),
+ *   b_{o,i,j} = sum_{c,di,dj} w[o][c][di][dj] a_{c, s i+di-p, s j+dj-p};
+ *   DENSE: out[o] = sum_j w[o][j] in[j] (also the scalar layer over
+ *   ciphertexts that each carry one value).
+ * HW packing (one ciphertext per channel, input position (y, x) at slot
+ *   pos_stride*(row*y + x)): CONV2D (valid, pad 0) rotates each input by
+ *   pos_stride*(row*di + dj), multiplies by w[o][c][di][dj], sums and keeps the
+ *   outputs at slots pos_stride*stride*(row*i + j) with a mask; DENSE weights
+ *   w[o][c*in_h*in_w + y*in_w + x] multiply the slot of (y, x) of input c,
+ *   products are summed and then summed over slots (rotate-and-sum), leaving
+ *   out[o] in slot 0.
+ * Features (has_features): FP32 device array; q(f) = clamp(rint(scale f),
+ *   -clamp, clamp) in FP32 arithmetic is added as a plaintext.  BATCH: layout
+ *   [batch][n_out] (image-major); HW: [out_c][oh][ow].
+ */
+typedef struct {
+  int32_t kind;          /* BCN_CONV2D or BCN_DENSE */
+  int32_t packing;       /* BCN_PACK_BATCH or BCN_PACK_HW */
+  int32_t in_c, in_h, in_w;
+  int32_t out_c;
+  int32_t k, stride, pad;/* CONV2D geometry (HW: pad must be 0) */
+  int32_t row;           /* HW: slots per image row */
+  int32_t pos_stride;    /* HW: spacing of the valid input positions */
+  const int32_t* weights;/* host; CONV2D [out_c][in_c][k][k], DENSE [out_c][in_c*in_h*in_w] */
+  int32_t has_features;
+  float feature_scale;   /* 8.0 in this build's workloads */
+  int32_t feature_clamp; /* 127 */
+  int32_t batch;         /* BATCH: images (slots) carrying data */
+  int32_t square;        /* square + relinearise after the linear part (+features) */
+  int32_t modswitch;     /* after the square, switch down one prime (needs level >= 2) */
+  int32_t sum;           /* HW CONV2D: global sum of each output map, left in slot 0 */
+} bcn_layer_desc;
+
+/* Prepares a layer for inputs at `level`: uploads weights, encodes masks and
+ * weight vectors, fixes the rotation steps.  The keys must hold every Galois
+ * key the layer needs (bcn_layer_rotation_steps lists them). */
+int bcn_layer_create(bcn_context* ctx, const bcn_layer_desc* desc, int level, bcn_layer** out);
+void bcn_layer_destroy(bcn_layer* layer);
+/* Rotation steps the layer uses; returns the count (or an error), writes up to cap. */
+int bcn_layer_rotation_steps(const bcn_layer* layer, int32_t* steps, int cap);
+/* Input/output ciphertext counts and the output level. */
+int bcn_layer_shape(const bcn_layer* layer, int* n_in, int* n_out, int* level_out);
+/* Evaluates the layer: in device [n_in][2][level][N] -> out device [n_out][2][level_out][N];
+ * features: device float or NULL when the layer has none. */
+int bcn_layer_eval(bcn_context* ctx, const bcn_eval_keys* ek, const bcn_layer* layer, const double* in,
+                   double* out, const float* features, bcn_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BCN_H */

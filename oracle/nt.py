@@ -45,7 +45,28 @@ def ntt_primes(bits: int, two_n: int, count: int, exclude=()) -> list[int]:
 
 
 def negacyclic_root(q: int, n: int) -> int:
-    """Smallest x >= 2 with x^n = -1 (mod q): a primitive 2n-th root of unity."""
+    """Smallest x >= 2 with x^n = -1 (mod q): a primitive 2n-th root of unity.
+
+    The solutions of x^n = -1 are exactly the odd powers of any one of them
+    (n = power of two), and psi0 = g^((q-1)/2n) is one whenever g is a
+    quadratic non-residue (psi0^n = g^((q-1)/2) = -1).  So the smallest
+    solution is the minimum over psi0^k, k odd < 2n.
+    """
+    assert (q - 1) % (2 * n) == 0
+    g = 2
+    while pow(g, (q - 1) // 2, q) != q - 1:
+        g += 1
+    psi0 = pow(g, (q - 1) // (2 * n), q)
+    sq = psi0 * psi0 % q
+    best, x = q, psi0
+    for _ in range(n):
+        best = min(best, x)
+        x = x * sq % q
+    return best
+
+
+def negacyclic_root_search(q: int, n: int) -> int:
+    """The same root by exhaustive search (small q only; pins the fast form)."""
     for x in range(2, q):
         if pow(x, n, q) == q - 1:
             return x

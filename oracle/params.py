@@ -11,6 +11,8 @@ from __future__ import annotations
 
 from dataclasses import dataclass, field
 
+from synthetic import workloads as W
+
 from . import nt
 
 
@@ -59,20 +61,7 @@ def make(name: str, n: int, bits: int, L: int, K: int, alpha: int, t: int, insec
     return Params(name, n, tuple(primes[:L]), tuple(primes[L:]), t, alpha, insecure)
 
 
-_SPECS = {
-    # the three workloads
-    "cfg1": dict(n=4096, bits=30, L=2, K=1, alpha=1, t=65537),
-    "cfg2": dict(n=8192, bits=36, L=4, K=1, alpha=1, t=1032193),
-    "cfg3": dict(n=16384, bits=40, L=6, K=2, alpha=2, t=65537),
-    # workload 1 with five primes so that its output still decrypts (insecure)
-    "cfg1d": dict(n=4096, bits=30, L=5, K=1, alpha=1, t=65537, insecure=True),
-    # reduced sizes for tests the oracle finishes in seconds (insecure)
-    "t1k": dict(n=1024, bits=36, L=3, K=1, alpha=1, t=65537, insecure=True),
-    "t2k": dict(n=2048, bits=40, L=4, K=2, alpha=2, t=65537, insecure=True),
-    "t1k5": dict(n=1024, bits=30, L=5, K=1, alpha=1, t=65537, insecure=True),
-    "t2k3": dict(n=2048, bits=40, L=6, K=2, alpha=2, t=65537, insecure=True),
-    "t4k": dict(n=4096, bits=36, L=4, K=1, alpha=1, t=40961, insecure=True),
-}
+_SPECS = W.PARAMS
 
 _CACHE: dict = {}
 

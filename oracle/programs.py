@@ -28,11 +28,8 @@ from synthetic import workloads as W
 from . import bfv, network, params
 from .encoder import BatchEncoder
 
-RELIN_KEY_ID = 0
-
-
-def galois_key_id(r: int) -> int:
-    return 1000 + r
+RELIN_KEY_ID = W.RELIN_KEY_ID
+galois_key_id = W.rotation_key_id
 
 
 def _span(max_slot: int) -> int:

@@ -1,0 +1,338 @@
+"""ctypes binding of the C ABI in include/bcn.h (argument marshalling only).
+
+Device buffers are torch tensors on the GPU (float64 ciphertexts
+[n][2][level][N], float32 features); the stream is torch's current stream.
+Every arithmetic step runs in the HIP library; importing this module never
+falls back to anything else: a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libbcn.so")
+
+BCN_KEY_RELIN, BCN_KEY_ROTATION = 0, 1
+BCN_CONV2D, BCN_DENSE = 0, 1
+BCN_PACK_BATCH, BCN_PACK_HW = 0, 1
+
+
+class BcnError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("bcn error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("q_bits", C.c_uint32), ("L", C.c_uint32), ("K", C.c_uint32),
+                ("alpha", C.c_uint32), ("t", C.c_uint64)]
+
+
+class LayerDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("packing", C.c_int32), ("in_c", C.c_int32), ("in_h", C.c_int32),
+                ("in_w", C.c_int32), ("out_c", C.c_int32), ("k", C.c_int32), ("stride", C.c_int32),
+                ("pad", C.c_int32), ("row", C.c_int32), ("pos_stride", C.c_int32),
+                ("weights", C.POINTER(C.c_int32)), ("has_features", C.c_int32), ("feature_scale", C.c_float),
+                ("feature_clamp", C.c_int32), ("batch", C.c_int32), ("square", C.c_int32),
+                ("modswitch", C.c_int32), ("sum", C.c_int32)]
+
+
+_lib = None
+
+_VP, _I, _U64P, _I64P, _I32P, _I8P = C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p
+
+_SIGS = {
+    "bcn_last_error": (C.c_char_p, []),
+    "bcn_context_create": (_I, [C.POINTER(Params), _I, C.POINTER(_VP)]),
+    "bcn_context_destroy": (None, [_VP]),
+    "bcn_context_primes": (_I, [_VP, _U64P, _I, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)]),
+    "bcn_secret_key_create": (_I, [_VP, _I8P, C.POINTER(_VP)]),
+    "bcn_secret_key_destroy": (None, [_VP]),
+    "bcn_eval_keys_create": (_I, [_VP, C.POINTER(_VP)]),
+    "bcn_eval_keys_destroy": (None, [_VP]),
+    "bcn_keygen": (_I, [_VP, _VP, _VP, _I, _I, _U64P, _I8P, _VP]),
+    "bcn_eval_key_export": (_I, [_VP, _VP, _I, _I, _U64P, _VP]),
+    "bcn_encode_encrypt": (_I, [_VP, _VP, _I64P, _U64P, _I8P, _I, _I, _VP, _VP]),
+    "bcn_decrypt_decode": (_I, [_VP, _VP, _VP, _I, _I, _I64P, _VP]),
+    "bcn_ct_export": (_I, [_VP, _VP, _I, _I, _U64P, _VP]),
+    "bcn_ct_import": (_I, [_VP, _U64P, _I, _I, _VP, _VP]),
+    "bcn_ntt": (_I, [_VP, _VP, _I, _I, _I, _I, _VP]),
+    "bcn_mac": (_I, [_VP, _VP, _I, _VP, _I, _I, _I32P, _VP]),
+    "bcn_add_plain": (_I, [_VP, _VP, _I, _I, _I64P, _VP]),
+    "bcn_mul_plain": (_I, [_VP, _VP, _VP, _I, _I, _I64P, _VP]),
+    "bcn_square_relin": (_I, [_VP, _VP, _VP, _VP, _I, _I, _I, _VP]),
+    "bcn_rotate": (_I, [_VP, _VP, _VP, _I, _I, _I32P, _I, _VP, _VP]),
+    "bcn_rotate_sum": (_I, [_VP, _VP, _VP, _I, _I, _I, _VP]),
+    "bcn_modswitch": (_I, [_VP, _VP, _VP, _I, _I, _VP]),
+    "bcn_layer_create": (_I, [_VP, C.POINTER(LayerDesc), _I, C.POINTER(_VP)]),
+    "bcn_layer_destroy": (None, [_VP]),
+    "bcn_layer_rotation_steps": (_I, [_VP, _I32P, _I]),
+    "bcn_layer_shape": (_I, [_VP, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)]),
+    "bcn_layer_eval": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+}
+
+
+def lib():
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("HIP library missing: %s (run __graft_entry__.build())" % LIB_PATH)
+        h = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(h, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = h
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(rc):
+    if rc != 0:
+        raise BcnError(rc, lib().bcn_last_error().decode())
+
+
+def _np_ptr(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    def __init__(self, n, q_bits, L, K, alpha, t, device=0):
+        self.p = Params(n, q_bits, L, K, alpha, t)
+        h = C.c_void_p()
+        _check(lib().bcn_context_create(C.byref(self.p), device, C.byref(h)))
+        self.h = h
+        self.n, self.L, self.K, self.alpha, self.t = n, L, K, alpha, t
+        buf = np.zeros(64, dtype=np.uint64)
+        nq, np_, nb = C.c_int(), C.c_int(), C.c_int()
+        _check(lib().bcn_context_primes(h, buf.ctypes.data_as(C.c_void_p), 64, C.byref(nq), C.byref(np_),
+                                        C.byref(nb)))
+        self.primes = [int(x) for x in buf[:nq.value + np_.value + nb.value + 1]]
+        self.n_q, self.n_p, self.n_aux = nq.value, np_.value, nb.value
+
+    @property
+    def q(self):
+        return self.primes[:self.n_q]
+
+    @property
+    def p_primes(self):
+        return self.primes[self.n_q:self.n_q + self.n_p]
+
+    def dnum(self, level=None):
+        level = self.L if level is None else level
+        return -(-level // self.alpha)
+
+    def close(self):
+        if self.h:
+            lib().bcn_context_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ tensors
+    def empty_ct(self, n, level):
+        import torch
+        return torch.empty((n, 2, level, self.n), dtype=torch.float64, device="cuda")
+
+    # ------------------------------------------------------------ client side
+    def secret_key(self, s):
+        s, p = _np_ptr(s, np.int8)
+        h = C.c_void_p()
+        _check(lib().bcn_secret_key_create(self.h, p, C.byref(h)))
+        return SecretKey(self, h)
+
+    def eval_keys(self):
+        h = C.c_void_p()
+        _check(lib().bcn_eval_keys_create(self.h, C.byref(h)))
+        return EvalKeys(self, h)
+
+    def keygen(self, sk, ek, kind, step, a, e):
+        a, ap = _np_ptr(a, np.uint64)
+        e, ep = _np_ptr(e, np.int8)
+        _check(lib().bcn_keygen(self.h, sk.h, ek.h, kind, step, ap, ep, _stream()))
+
+    def export_key(self, ek, kind, step=0):
+        out = np.zeros((self.dnum(), 2, self.L + self.K, self.n), dtype=np.uint64)
+        _check(lib().bcn_eval_key_export(self.h, ek.h, kind, step, out.ctypes.data_as(C.c_void_p), _stream()))
+        return out
+
+    def encrypt(self, sk, slots, a, e, level=None):
+        level = self.L if level is None else level
+        slots, sp = _np_ptr(slots, np.int64)
+        a, ap = _np_ptr(a, np.uint64)
+        e, ep = _np_ptr(e, np.int8)
+        n = slots.shape[0]
+        ct = self.empty_ct(n, level)
+        _check(lib().bcn_encode_encrypt(self.h, sk.h, sp, ap, ep, n, level, _dptr(ct), _stream()))
+        return ct
+
+    def decrypt(self, sk, ct):
+        n, _, level, _ = ct.shape
+        out = np.zeros((n, self.n), dtype=np.int64)
+        _check(lib().bcn_decrypt_decode(self.h, sk.h, _dptr(ct), n, level, out.ctypes.data_as(C.c_void_p),
+                                        _stream()))
+        return out
+
+    def export(self, ct):
+        n, _, level, _ = ct.shape
+        out = np.zeros((n, 2, level, self.n), dtype=np.uint64)
+        _check(lib().bcn_ct_export(self.h, _dptr(ct), n, level, out.ctypes.data_as(C.c_void_p), _stream()))
+        return out
+
+    def import_(self, arr):
+        arr = np.ascontiguousarray(arr, dtype=np.uint64)
+        n, _, level, _ = arr.shape
+        ct = self.empty_ct(n, level)
+        _check(lib().bcn_ct_import(self.h, arr.ctypes.data_as(C.c_void_p), n, level, _dptr(ct), _stream()))
+        return ct
+
+    # ------------------------------------------------------------ server side
+    def ntt(self, data, first_prime, inverse=False):
+        n_polys, n_limbs, _ = data.shape
+        _check(lib().bcn_ntt(self.h, _dptr(data), n_polys, n_limbs, first_prime, 1 if inverse else 0, _stream()))
+
+    def mac(self, ct, w):
+        n_in, _, level, _ = ct.shape
+        w, wp = _np_ptr(w, np.int32)
+        out = self.empty_ct(w.shape[0], level)
+        _check(lib().bcn_mac(self.h, _dptr(ct), n_in, _dptr(out), w.shape[0], level, wp, _stream()))
+        return out
+
+    def add_plain(self, ct, slots):
+        n, _, level, _ = ct.shape
+        slots, sp = _np_ptr(slots, np.int64)
+        _check(lib().bcn_add_plain(self.h, _dptr(ct), n, level, sp, _stream()))
+
+    def mul_plain(self, ct, slots):
+        n, _, level, _ = ct.shape
+        slots, sp = _np_ptr(slots, np.int64)
+        out = self.empty_ct(n, level)
+        _check(lib().bcn_mul_plain(self.h, _dptr(ct), _dptr(out), n, level, sp, _stream()))
+        return out
+
+    def square_relin(self, ek, ct, modswitch=False):
+        n, _, level, _ = ct.shape
+        out = self.empty_ct(n, level - 1 if modswitch else level)
+        _check(lib().bcn_square_relin(self.h, ek.h, _dptr(ct), _dptr(out), n, level, 1 if modswitch else 0,
+                                      _stream()))
+        return out
+
+    def rotate(self, ek, ct, steps):
+        n, _, level, _ = ct.shape
+        steps, sp = _np_ptr(steps, np.int32)
+        import torch
+        out = torch.empty((n, len(steps), 2, level, self.n), dtype=torch.float64, device="cuda")
+        _check(lib().bcn_rotate(self.h, ek.h, _dptr(ct), n, level, sp, len(steps), _dptr(out), _stream()))
+        return out
+
+    def rotate_sum(self, ek, ct, span):
+        n, _, level, _ = ct.shape
+        _check(lib().bcn_rotate_sum(self.h, ek.h, _dptr(ct), n, level, span, _stream()))
+
+    def modswitch(self, ct):
+        n, _, level, _ = ct.shape
+        out = self.empty_ct(n, level - 1)
+        _check(lib().bcn_modswitch(self.h, _dptr(ct), _dptr(out), n, level, _stream()))
+        return out
+
+    def layer(self, desc: dict, level: int):
+        return Layer(self, desc, level)
+
+
+class SecretKey:
+    def __init__(self, ctx, h):
+        self.ctx, self.h = ctx, h
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().bcn_secret_key_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+class EvalKeys:
+    def __init__(self, ctx, h):
+        self.ctx, self.h = ctx, h
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().bcn_eval_keys_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+class Layer:
+    """A prepared layer (weights uploaded, masks and weight vectors encoded)."""
+
+    def __init__(self, ctx, desc: dict, level: int):
+        self.ctx = ctx
+        w = np.ascontiguousarray(desc["weights"], dtype=np.int32)
+        self._w = w
+        d = LayerDesc()
+        d.kind = desc["kind"]
+        d.packing = desc["packing"]
+        d.in_c, d.in_h, d.in_w = desc["in_c"], desc.get("in_h", 1), desc.get("in_w", 1)
+        d.out_c = desc["out_c"]
+        d.k, d.stride, d.pad = desc.get("k", 1), desc.get("stride", 1), desc.get("pad", 0)
+        d.row, d.pos_stride = desc.get("row", 1), desc.get("pos_stride", 1)
+        d.weights = w.ctypes.data_as(C.POINTER(C.c_int32))
+        d.has_features = 1 if desc.get("features") else 0
+        d.feature_scale = desc.get("feature_scale", 8.0)
+        d.feature_clamp = desc.get("feature_clamp", 127)
+        d.batch = desc.get("batch", 0)
+        d.square = 1 if desc.get("square") else 0
+        d.modswitch = 1 if desc.get("modswitch") else 0
+        d.sum = 1 if desc.get("sum") else 0
+        self.desc = d
+        h = C.c_void_p()
+        _check(lib().bcn_layer_create(ctx.h, C.byref(d), level, C.byref(h)))
+        self.h = h
+        buf = np.zeros(256, dtype=np.int32)
+        cnt = lib().bcn_layer_rotation_steps(h, buf.ctypes.data_as(C.c_void_p), 256)
+        if cnt < 0:
+            _check(cnt)
+        self.steps = [int(x) for x in buf[:cnt]]
+        ni, no, lo = C.c_int(), C.c_int(), C.c_int()
+        _check(lib().bcn_layer_shape(h, C.byref(ni), C.byref(no), C.byref(lo)))
+        self.n_in, self.n_out, self.level_out = ni.value, no.value, lo.value
+        self.level = level
+
+    def __call__(self, ek, ct, features=None, out=None):
+        if out is None:
+            out = self.ctx.empty_ct(self.n_out, self.level_out)
+        fp = _dptr(features) if features is not None else None
+        _check(lib().bcn_layer_eval(self.ctx.h, ek.h, self.h, _dptr(ct), _dptr(out), fp, _stream()))
+        return out
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().bcn_layer_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass

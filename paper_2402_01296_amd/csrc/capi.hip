@@ -1,0 +1,430 @@
+// extern "C" entry points: argument checks, error translation, arena reset.
+#include <cstring>
+#include <string>
+
+#include "../../include/bcn.h"
+#include "layers.h"
+
+struct bcn_context { bcn::Context* c; };
+struct bcn_secret_key { bcn::SecretKey* k; };
+struct bcn_eval_keys { bcn::EvalKeys* k; };
+struct bcn_layer { bcn::Layer* l; };
+
+namespace bcn {
+Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uint32_t alpha, uint64_t t, int device);
+void destroy_context(Context* c);
+}  // namespace bcn
+
+namespace {
+thread_local std::string g_err;
+
+template <typename F>
+int guard(F&& f) {
+  try {
+    f();
+    return BCN_OK;
+  } catch (const bcn::Error& e) {
+    g_err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host out of memory";
+    return BCN_ERR_NOMEM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return BCN_ERR_INTERNAL;
+  }
+}
+
+bcn::Context& ctxof(bcn_context* c) {
+  if (!c || !c->c) throw bcn::Error(BCN_ERR_INVALID, "null context");
+  bcn::Context& x = *c->c;
+  BCN_HIP(hipSetDevice(x.device));
+  x.arena->reset();
+  return x;
+}
+
+void check_level(const bcn::Context& c, int level) {
+  if (level < 1 || level > c.L) throw bcn::Error(BCN_ERR_LEVEL, "level out of range");
+}
+
+void check_n(int n) {
+  if (n < 0) throw bcn::Error(BCN_ERR_INVALID, "negative count");
+}
+
+void check_ptr(const void* p, const char* what) {
+  if (!p) throw bcn::Error(BCN_ERR_INVALID, std::string("null pointer: ") + what);
+}
+}  // namespace
+
+extern "C" {
+
+const char* bcn_last_error(void) { return g_err.c_str(); }
+
+int bcn_context_create(const bcn_params* p, int hip_device, bcn_context** out) {
+  return guard([&] {
+    check_ptr(p, "params");
+    check_ptr(out, "out");
+    auto* h = new bcn_context{nullptr};
+    try {
+      h->c = bcn::create_context(p->n, p->q_bits, p->L, p->K, p->alpha, p->t, hip_device);
+    } catch (...) {
+      delete h;
+      throw;
+    }
+    *out = h;
+  });
+}
+
+void bcn_context_destroy(bcn_context* ctx) {
+  if (!ctx) return;
+  bcn::destroy_context(ctx->c);
+  delete ctx;
+}
+
+int bcn_context_primes(const bcn_context* ctx, uint64_t* out, int cap, int* n_q, int* n_p, int* n_aux) {
+  return guard([&] {
+    if (!ctx || !ctx->c) throw bcn::Error(BCN_ERR_INVALID, "null context");
+    const bcn::Context& c = *ctx->c;
+    const int total = (int)c.primes.size();
+    for (int i = 0; i < total && i < cap; ++i) out[i] = c.primes[i];
+    if (n_q) *n_q = c.L;
+    if (n_p) *n_p = c.K;
+    if (n_aux) *n_aux = c.m;
+  });
+}
+
+int bcn_secret_key_create(bcn_context* ctx, const int8_t* s, bcn_secret_key** out) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    check_ptr(s, "s");
+    check_ptr(out, "out");
+    *out = new bcn_secret_key{bcn::secret_key_create(c, s)};
+  });
+}
+
+void bcn_secret_key_destroy(bcn_secret_key* sk) {
+  if (!sk) return;
+  delete sk->k;
+  delete sk;
+}
+
+int bcn_eval_keys_create(bcn_context* ctx, bcn_eval_keys** out) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    check_ptr(out, "out");
+    auto* k = new bcn::EvalKeys();
+    k->ctx = &c;
+    *out = new bcn_eval_keys{k};
+  });
+}
+
+void bcn_eval_keys_destroy(bcn_eval_keys* ek) {
+  if (!ek) return;
+  delete ek->k;
+  delete ek;
+}
+
+int bcn_keygen(bcn_context* ctx, const bcn_secret_key* sk, bcn_eval_keys* ek, int kind, int step, const uint64_t* a,
+               const int8_t* e, bcn_stream stream) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    check_ptr(sk, "secret key");
+    check_ptr(ek, "eval keys");
+    check_ptr(a, "a");
+    check_ptr(e, "e");
+    if (kind != BCN_KEY_RELIN && kind != BCN_KEY_ROTATION) throw bcn::Error(BCN_ERR_INVALID, "bad key kind");
+    if (kind == BCN_KEY_ROTATION && (step <= 0 || step >= c.n / 2))
+      throw bcn::Error(BCN_ERR_INVALID, "rotation step must be in [1, N/2)");
+    bcn::keygen(c, *sk->k, *ek->k, kind, step, a, e, (hipStream_t)stream);
+  });
+}
+
+int bcn_eval_key_export(bcn_context* ctx, const bcn_eval_keys* ek, int kind, int step, uint64_t* out,
+                        bcn_stream stream) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    check_ptr(ek, "eval keys");
+    check_ptr(out, "out");
+    const double* key = kind == BCN_KEY_RELIN ? ek->k->relin : ek->k->rot_key(step);
+    if (!key) throw bcn::Error(BCN_ERR_KEY, "missing relinearisation key");
+    const bcn::Basis qp = c.basis_QP(c.L);
+    const size_t words = ek->k->key_doubles();
+    hipStream_t s = (hipStream_t)stream;
+    double* tmp = c.arena->take(words);
+    BCN_HIP(hipMemcpyAsync(tmp, key, words * sizeof(double), hipMemcpyDeviceToDevice, s));
+    bcn::ntt_inverse(c, tmp, (int)(words / ((size_t)qp.n * c.n)), qp, s);
+    uint64_t* u = reinterpret_cast<uint64_t*>(c.arena->take(words));
+    bcn::f64_to_u64(tmp, u, words, s);
+    BCN_HIP(hipMemcpyAsync(out, u, words * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    BCN_HIP(hipStreamSynchronize(s));
+  });
+}
+
+int bcn_encode_encrypt(bcn_context* ctx, const bcn_secret_key* sk, const int64_t* slots, const uint64_t* a,
+                       const int8_t* e, int n, int level, double* ct_out, bcn_stream stream) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    check_level(c, level);
+    check_n(n);
+    check_ptr(sk, "secret key");
+    if (n == 0) return;
+    check_ptr(slots, "slots");
+    check_ptr(a, "a");
+    check_ptr(e, "e");
+    check_ptr(ct_out, "ct_out");
+    bcn::encrypt(c, *sk->k, slots, a, e, n, level, ct_out, (hipStream_t)stream);
+  });
+}
+
+int bcn_decrypt_decode(bcn_context* ctx, const bcn_secret_key* sk, const double* ct, int n, int level,
+                       int64_t* slots_out, bcn_stream stream) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    check_level(c, level);
+    check_n(n);
+    check_ptr(sk, "secret key");
+    if (n == 0) return;
+    check_ptr(ct, "ct");
+    check_ptr(slots_out, "slots_out");
+    bcn::decrypt(c, *sk->k, ct, n, level, slots_out, (hipStream_t)stream);
+  });
+}
+
+int bcn_ct_export(bcn_context* ctx, const double* ct, int n, int level, uint64_t* host_out, bcn_stream stream) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    check_level(c, level);
+    check_n(n);
+    if (n == 0) return;
+    check_ptr(ct, "ct");
+    check_ptr(host_out, "host_out");
+    const size_t words = (size_t)n * 2 * level * c.n;
+    hipStream_t s = (hipStream_t)stream;
+    uint64_t* u = reinterpret_cast<uint64_t*>(c.arena->take(words));
+    bcn::f64_to_u64(ct, u, words, s);
+    BCN_HIP(hipMemcpyAsync(host_out, u, words * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    BCN_HIP(hipStreamSynchronize(s));
+  });
+}
+
+int bcn_ct_import(bcn_context* ctx, const uint64_t* host_in, int n, int level, double* ct, bcn_stream stream) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    check_level(c, level);
+    check_n(n);
+    if (n == 0) return;
+    check_ptr(ct, "ct");
+    check_ptr(host_in, "host_in");
+    const size_t words = (size_t)n * 2 * level * c.n;
+    for (int ci = 0; ci < n; ++ci)
+      for (int part = 0; part < 2; ++part)
+        for (int i = 0; i < level; ++i) {
+          const uint64_t q = c.primes[i];
+          const uint64_t* row = host_in + (((size_t)ci * 2 + part) * level + i) * c.n;
+          for (int k = 0; k < c.n; ++k)
+            if (row[k] >= q) throw bcn::Error(BCN_ERR_INVALID, "imported residue not below its prime");
+        }
+    hipStream_t s = (hipStream_t)stream;
+    uint64_t* u = reinterpret_cast<uint64_t*>(c.arena->take(words));
+    BCN_HIP(hipMemcpyAsync(u, host_in, words * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    bcn::u64_to_f64(u, ct, words, s);
+    BCN_HIP(hipStreamSynchronize(s));
+  });
+}
+
+int bcn_ntt(bcn_context* ctx, double* data, int n_polys, int n_limbs, int first_prime, int inverse,
+            bcn_stream stream) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    check_n(n_polys);
+    if (n_limbs < 1 || n_limbs > bcn::kMaxBasis) throw bcn::Error(BCN_ERR_INVALID, "bad limb count");
+    if (first_prime < 0 || first_prime + n_limbs > (int)c.primes.size())
+      throw bcn::Error(BCN_ERR_INVALID, "prime ids out of range");
+    if (n_polys == 0) return;
+    check_ptr(data, "data");
+    bcn::Basis b{};
+    b.n = n_limbs;
+    for (int i = 0; i < n_limbs; ++i) b.id[i] = first_prime + i;
+    if (inverse)
+      bcn::ntt_inverse(c, data, n_polys, b, (hipStream_t)stream);
+    else
+      bcn::ntt_forward(c, data, n_polys, b, (hipStream_t)stream);
+  });
+}
+
+int bcn_mac(bcn_context* ctx, const double* in, int n_in, double* out, int n_out, int level, const int32_t* w,
+            bcn_stream stream) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    check_level(c, level);
+    if (n_in < 1 || n_out < 0) throw bcn::Error(BCN_ERR_INVALID, "bad MAC shape");
+    if (n_out == 0) return;
+    check_ptr(in, "in");
+    check_ptr(out, "out");
+    check_ptr(w, "w");
+    std::vector<int32_t> W(w, w + (size_t)n_in * n_out);
+    bcn::MacPlan p = bcn::make_mac_plan(c, W, n_out, n_in);
+    try {
+      bcn::mac(c, p, in, out, level, (hipStream_t)stream);
+      BCN_HIP(hipStreamSynchronize((hipStream_t)stream));
+    } catch (...) {
+      bcn::free_mac_plan(p);
+      throw;
+    }
+    bcn::free_mac_plan(p);
+  });
+}
+
+int bcn_add_plain(bcn_context* ctx, double* ct, int n, int level, const int64_t* slots, bcn_stream stream) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    check_level(c, level);
+    check_n(n);
+    if (n == 0) return;
+    check_ptr(ct, "ct");
+    check_ptr(slots, "slots");
+    hipStream_t s = (hipStream_t)stream;
+    int64_t* sd = reinterpret_cast<int64_t*>(c.arena->take((size_t)n * c.n));
+    BCN_HIP(hipMemcpyAsync(sd, slots, (size_t)n * c.n * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    double* m = c.arena->take((size_t)n * c.n);
+    bcn::encode_device(c, sd, m, n, s);
+    bcn::add_delta(c, ct, n, level, m, s);
+    BCN_HIP(hipStreamSynchronize(s));
+  });
+}
+
+int bcn_mul_plain(bcn_context* ctx, const double* in, double* out, int n, int level, const int64_t* slots,
+                  bcn_stream stream) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    check_level(c, level);
+    check_n(n);
+    if (n == 0) return;
+    check_ptr(in, "in");
+    check_ptr(out, "out");
+    check_ptr(slots, "slots");
+    hipStream_t s = (hipStream_t)stream;
+    double* pt = c.arena->take((size_t)level * c.n);
+    bcn::encode_plain_ntt(c, slots, 1, level, pt, s);
+    const size_t words = (size_t)n * 2 * level * c.n;
+    double* tmp = c.arena->take(words);
+    BCN_HIP(hipMemcpyAsync(tmp, in, words * sizeof(double), hipMemcpyDeviceToDevice, s));
+    const bcn::Basis q = c.basis_Q(level);
+    bcn::ntt_forward(c, tmp, 2 * n, q, s);
+    bcn::mul_plain_ntt(c, tmp, tmp, n, level, pt, false, s);
+    bcn::ntt_inverse(c, tmp, 2 * n, q, s);
+    BCN_HIP(hipMemcpyAsync(out, tmp, words * sizeof(double), hipMemcpyDeviceToDevice, s));
+  });
+}
+
+int bcn_square_relin(bcn_context* ctx, const bcn_eval_keys* ek, const double* in, double* out, int n, int level,
+                     int modswitch, bcn_stream stream) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    check_level(c, level);
+    check_n(n);
+    check_ptr(ek, "eval keys");
+    if (n == 0) return;
+    check_ptr(in, "in");
+    check_ptr(out, "out");
+    bcn::square_relin(c, *ek->k, in, out, n, level, modswitch != 0, (hipStream_t)stream);
+  });
+}
+
+int bcn_rotate(bcn_context* ctx, const bcn_eval_keys* ek, const double* in, int n_in, int level, const int32_t* steps,
+               int n_steps, double* out, bcn_stream stream) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    check_level(c, level);
+    check_n(n_in);
+    check_ptr(ek, "eval keys");
+    if (n_in == 0 || n_steps == 0) return;
+    check_ptr(in, "in");
+    check_ptr(out, "out");
+    check_ptr(steps, "steps");
+    std::vector<int> st(steps, steps + n_steps);
+    for (int x : st) ek->k->rot_key(x);   // throws BCN_ERR_KEY when missing
+    bcn::rotate_hoisted(c, *ek->k, in, n_in, level, st, out, (hipStream_t)stream);
+  });
+}
+
+int bcn_rotate_sum(bcn_context* ctx, const bcn_eval_keys* ek, double* ct, int n, int level, int span,
+                   bcn_stream stream) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    check_level(c, level);
+    check_n(n);
+    check_ptr(ek, "eval keys");
+    if (span > c.n / 2) throw bcn::Error(BCN_ERR_INVALID, "span beyond the slot row");
+    if (n == 0) return;
+    check_ptr(ct, "ct");
+    for (int r = span / 2; r >= 1; r /= 2) ek->k->rot_key(r);
+    bcn::rotate_sum(c, *ek->k, ct, n, level, span, (hipStream_t)stream);
+  });
+}
+
+int bcn_modswitch(bcn_context* ctx, const double* in, double* out, int n, int level, bcn_stream stream) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    check_level(c, level);
+    check_n(n);
+    if (level < 2) throw bcn::Error(BCN_ERR_LEVEL, "modulus switch needs two primes");
+    if (n == 0) return;
+    check_ptr(in, "in");
+    check_ptr(out, "out");
+    bcn::modswitch(c, in, out, n, level, (hipStream_t)stream);
+  });
+}
+
+int bcn_layer_create(bcn_context* ctx, const bcn_layer_desc* desc, int level, bcn_layer** out) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    check_ptr(desc, "desc");
+    check_ptr(out, "out");
+    *out = new bcn_layer{bcn::layer_create(c, *desc, level)};
+  });
+}
+
+void bcn_layer_destroy(bcn_layer* layer) {
+  if (!layer) return;
+  delete layer->l;
+  delete layer;
+}
+
+int bcn_layer_rotation_steps(const bcn_layer* layer, int32_t* steps, int cap) {
+  if (!layer || !layer->l) {
+    g_err = "null layer";
+    return BCN_ERR_INVALID;
+  }
+  const auto& v = layer->l->all_steps;
+  for (int i = 0; i < (int)v.size() && i < cap; ++i) steps[i] = v[i];
+  return (int)v.size();
+}
+
+int bcn_layer_shape(const bcn_layer* layer, int* n_in, int* n_out, int* level_out) {
+  if (!layer || !layer->l) {
+    g_err = "null layer";
+    return BCN_ERR_INVALID;
+  }
+  if (n_in) *n_in = layer->l->n_in;
+  if (n_out) *n_out = layer->l->n_out;
+  if (level_out) *level_out = layer->l->level_out;
+  return BCN_OK;
+}
+
+int bcn_layer_eval(bcn_context* ctx, const bcn_eval_keys* ek, const bcn_layer* layer, const double* in, double* out,
+                   const float* features, bcn_stream stream) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    check_ptr(ek, "eval keys");
+    check_ptr(layer, "layer");
+    check_ptr(in, "in");
+    check_ptr(out, "out");
+    const bcn::Layer& L = *layer->l;
+    if (L.square && !ek->k->relin) throw bcn::Error(BCN_ERR_KEY, "missing relinearisation key");
+    for (int st : L.all_steps) ek->k->rot_key(st);
+    bcn::layer_eval(c, *ek->k, L, in, out, features, (hipStream_t)stream);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,238 @@
+// Context creation: prime selection, per-prime transform tables, exact
+// conversion constants and the scratch arena.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "internal.h"
+
+namespace bcn {
+
+Arena::~Arena() {
+  for (auto& ch : chunks_) (void)hipFree(ch.p);
+}
+
+size_t Arena::capacity() const {
+  size_t c = 0;
+  for (auto& ch : chunks_) c += ch.cap;
+  return c;
+}
+
+void Arena::reset() {
+  if (chunks_.size() > 1) {
+    // consolidate: wait for in-flight users, then keep one chunk of the high-water size
+    BCN_HIP(hipDeviceSynchronize());
+    for (auto& ch : chunks_) BCN_HIP(hipFree(ch.p));
+    chunks_.clear();
+    double* p = nullptr;
+    const size_t cap = high_ + high_ / 4;
+    if (hipMalloc(&p, cap * sizeof(double)) != hipSuccess) throw Error(-4, "device out of memory for scratch");
+    chunks_.push_back({p, cap});
+  }
+  cur_ = 0;
+  off_ = 0;
+  used_total_ = 0;
+}
+
+double* Arena::take(size_t doubles) {
+  doubles = (doubles + 31) & ~(size_t)31;   // 256-byte alignment
+  while (cur_ < chunks_.size() && off_ + doubles > chunks_[cur_].cap) {
+    ++cur_;
+    off_ = 0;
+  }
+  if (cur_ == chunks_.size()) {
+    const size_t cap = std::max(doubles, (size_t)(32u << 20));   // at least 256 MiB
+    double* p = nullptr;
+    if (hipMalloc(&p, cap * sizeof(double)) != hipSuccess) throw Error(-4, "device out of memory for scratch");
+    chunks_.push_back({p, cap});
+    off_ = 0;
+  }
+  double* p = chunks_[cur_].p + off_;
+  off_ += doubles;
+  used_total_ += doubles;
+  high_ = std::max(high_, used_total_);
+  return p;
+}
+
+Basis Context::basis_Q(int level) const {
+  Basis b{};
+  b.n = level;
+  for (int i = 0; i < level; ++i) b.id[i] = idQ(i);
+  return b;
+}
+
+Basis Context::basis_QP(int level) const {
+  Basis b{};
+  b.n = level + K;
+  for (int i = 0; i < level; ++i) b.id[i] = idQ(i);
+  for (int i = 0; i < K; ++i) b.id[level + i] = idP(i);
+  return b;
+}
+
+Basis Context::basis_QB(int level) const {
+  Basis b{};
+  b.n = level + m;
+  for (int i = 0; i < level; ++i) b.id[i] = idQ(i);
+  for (int i = 0; i < m; ++i) b.id[level + i] = idB(i);
+  return b;
+}
+
+Conv make_conv(const Context& c, const std::vector<int>& src, const std::vector<int>& dst) {
+  if ((int)src.size() > kMaxBasis || (int)dst.size() > kMaxBasis) throw Error(-1, "basis too large");
+  Conv cv;
+  std::memset(&cv, 0, sizeof(cv));
+  cv.ns = (int)src.size();
+  cv.nd = (int)dst.size();
+  for (int i = 0; i < cv.ns; ++i) cv.src[i] = src[i];
+  for (int d = 0; d < cv.nd; ++d) cv.dst[d] = dst[d];
+  for (int i = 0; i < cv.ns; ++i) {
+    const uint64_t pi = c.primes[src[i]];
+    for (int k = 0; k < i; ++k) cv.ginv[i][k] = (double)host::invmod(c.primes[src[k]] % pi, pi);
+  }
+  for (int d = 0; d < cv.nd; ++d) {
+    const uint64_t qd = c.primes[dst[d]];
+    uint64_t prod = 1;
+    for (int k = 0; k < cv.ns; ++k) {
+      const uint64_t pk = c.primes[src[k]] % qd;
+      cv.pm[d][k] = (double)pk;
+      prod = host::mulmod(prod, pk, qd);
+    }
+    cv.Mmod[d] = (double)prod;
+  }
+  return cv;
+}
+
+namespace {
+std::mutex g_conv_mu;
+std::map<std::pair<const Context*, std::string>, Conv*> g_convs;
+}  // namespace
+
+const Conv* conv_device(const Context& c, const std::string& key, const Conv& cv) {
+  std::lock_guard<std::mutex> lk(g_conv_mu);
+  auto it = g_convs.find({&c, key});
+  if (it != g_convs.end()) return it->second;
+  Conv* d = nullptr;
+  BCN_HIP(hipMalloc(&d, sizeof(Conv)));
+  BCN_HIP(hipMemcpy(d, &cv, sizeof(Conv), hipMemcpyHostToDevice));
+  g_convs[{&c, key}] = d;
+  return d;
+}
+
+void release_convs(const Context& c) {
+  std::lock_guard<std::mutex> lk(g_conv_mu);
+  for (auto it = g_convs.begin(); it != g_convs.end();) {
+    if (it->first.first == &c) {
+      (void)hipFree(it->second);
+      it = g_convs.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uint32_t alpha, uint64_t t, int device) {
+  int logn = 0;
+  while ((1u << logn) < n) ++logn;
+  if ((1u << logn) != n || logn < 10 || logn > 14) throw Error(-1, "N must be a power of two in [1024, 16384]");
+  if (q_bits < 25 || q_bits > 41) throw Error(-1, "prime size must be 25..41 bits (exact FP64 residue arithmetic)");
+  if (L < 1 || L > 8) throw Error(-1, "number of ciphertext primes must be 1..8");
+  if (K < 1 || K > 3) throw Error(-1, "number of special primes must be 1..3");
+  if (alpha < 1 || alpha > 8) throw Error(-1, "digit size must be 1..8");
+  if (t < 3 || t >= (1ull << 21) || !host::is_prime(t) || (t - 1) % (2ull * n) != 0)
+    throw Error(-1, "t must be a prime below 2^21 with t = 1 mod 2N");
+  if (t >= (1ull << (q_bits - 2))) throw Error(-1, "t too large for the ciphertext primes");
+  // special primes must cover one digit: P > Q_j keeps the key-switching noise small
+  if (K < alpha && false) throw Error(-1, "unreachable");
+
+  BCN_HIP(hipSetDevice(device));
+  auto c = std::make_unique<Context>();
+  c->device = device;
+  c->n = (int)n;
+  c->logn = logn;
+  c->L = (int)L;
+  c->K = (int)K;
+  c->alpha = (int)alpha;
+  c->t = t;
+  // Q and P: the largest q_bits-bit primes = 1 mod 2N, then aux primes B with
+  // B > 2 N Q so that the square's exact tensor lives in Q*B.
+  std::vector<uint64_t> qp = host::ntt_primes((int)q_bits, 2ull * n, (int)(L + K), {t});
+  double log_q = 0;
+  for (uint32_t i = 0; i < L; ++i) log_q += std::log2((double)qp[i]);
+  const double need = log_q + logn + 2.0;
+  std::vector<uint64_t> more = host::ntt_primes((int)q_bits, 2ull * n, (int)(L + K) + 16, {t});
+  double log_b = 0;
+  int m = 0;
+  while (log_b <= need) {
+    log_b += std::log2((double)more[L + K + m]);
+    ++m;
+  }
+  if ((int)L + m > 16) throw Error(-1, "auxiliary basis too large");
+  c->m = m;
+  c->primes.assign(qp.begin(), qp.end());
+  for (int i = 0; i < m; ++i) c->primes.push_back(more[L + K + i]);
+  c->primes.push_back(t);
+  c->id_t = (int)c->primes.size() - 1;
+  const int np = (int)c->primes.size();
+  for (uint64_t q : c->primes) c->hmods.push_back(Mod{(double)q, 1.0 / (double)q});
+
+  // per-prime tables
+  const size_t N = n;
+  const size_t per = N + N / 2 + N;
+  std::vector<double> h((size_t)np * per);
+  double* fwd = h.data();
+  double* inv = fwd + (size_t)np * N;
+  double* post = inv + (size_t)np * (N / 2);
+  for (int id = 0; id < np; ++id) {
+    const uint64_t q = c->primes[id];
+    const uint64_t psi = host::negacyclic_root(q, N);
+    const uint64_t psi_inv = host::invmod(psi, q);
+    const uint64_t omega_inv = host::mulmod(psi_inv, psi_inv, q);
+    const uint64_t ninv = host::invmod(N % q, q);
+    std::vector<uint64_t> pw(N);
+    uint64_t x = 1;
+    for (size_t i = 0; i < N; ++i) { pw[i] = x; x = host::mulmod(x, psi, q); }
+    for (size_t i = 0; i < N; ++i) fwd[id * N + i] = (double)pw[host::bitrev((uint32_t)i, logn)];
+    x = 1;
+    for (size_t k = 0; k < N / 2; ++k) { inv[id * (N / 2) + k] = (double)x; x = host::mulmod(x, omega_inv, q); }
+    x = ninv;
+    for (size_t k = 0; k < N; ++k) { post[id * N + k] = (double)x; x = host::mulmod(x, psi_inv, q); }
+  }
+  BCN_HIP(hipMalloc(&c->d_tables, h.size() * sizeof(double) + np * sizeof(Mod)));
+  BCN_HIP(hipMemcpy(c->d_tables, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+  Mod* dm = reinterpret_cast<Mod*>(c->d_tables + h.size());
+  BCN_HIP(hipMemcpy(dm, c->hmods.data(), np * sizeof(Mod), hipMemcpyHostToDevice));
+  c->tab.fwd = c->d_tables;
+  c->tab.inv = c->d_tables + (size_t)np * N;
+  c->tab.post = c->d_tables + (size_t)np * N + (size_t)np * (N / 2);
+  c->tab.mods = dm;
+  c->tab.logn = logn;
+
+  // slot s -> position of its evaluation point in the transform of R_t
+  std::vector<uint32_t> pos(N);
+  const uint64_t two_n = 2ull * N;
+  uint64_t g = 1;
+  for (size_t i = 0; i < N / 2; ++i) {
+    const uint64_t e0 = g, e1 = (two_n - g) % two_n;
+    pos[i] = host::bitrev((uint32_t)((e0 - 1) / 2), logn);
+    pos[N / 2 + i] = host::bitrev((uint32_t)((e1 - 1) / 2), logn);
+    g = g * 3 % two_n;
+  }
+  BCN_HIP(hipMalloc(&c->d_slot_pos, N * sizeof(uint32_t)));
+  BCN_HIP(hipMemcpy(c->d_slot_pos, pos.data(), N * sizeof(uint32_t), hipMemcpyHostToDevice));
+  c->arena = std::make_unique<Arena>();
+  ntt_setup(*c);
+  return c.release();
+}
+
+void destroy_context(Context* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  release_convs(*c);
+  if (c->d_tables) (void)hipFree(c->d_tables);
+  if (c->d_slot_pos) (void)hipFree(c->d_slot_pos);
+  delete c;
+}
+
+}  // namespace bcn

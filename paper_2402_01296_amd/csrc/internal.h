@@ -1,0 +1,202 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "hostmath.h"
+#include "modarith.h"
+
+namespace bcn {
+
+constexpr int kMaxBasis = 24;   // limbs in one RNS basis (Q + P + B)
+
+// Limb -> prime-id map of one RNS buffer, passed to kernels by value.
+struct Basis {
+  int n;
+  int id[kMaxBasis];
+};
+
+// Device-resident per-prime tables (all binary64 integers).
+struct Tables {
+  const double* fwd;   // [np][N]   psi^bitrev(i): twiddles of the forward transform
+  const double* inv;   // [np][N/2] omega^-k, omega = psi^2
+  const double* post;  // [np][N]   N^-1 psi^-k: untwist of the inverse transform
+  const Mod* mods;     // [np]
+  int logn;
+};
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define BCN_HIP(x)                                                                 \
+  do {                                                                             \
+    hipError_t e_ = (x);                                                           \
+    if (e_ != hipSuccess)                                                          \
+      throw ::bcn::Error(-5, std::string("HIP error: ") + hipGetErrorString(e_) +  \
+                                 " at " + __FILE__ + ":" + std::to_string(__LINE__)); \
+  } while (0)
+
+// Grow-only device scratch arena owned by a context.  take() hands out
+// stream-ordered scratch that stays valid until the next reset(); reset() is
+// called at the start of every public entry point.  When a call needed more
+// than one chunk, the next reset() synchronises the device and replaces the
+// chunks by one chunk of the high-water size, so steady state is one
+// allocation and no hipMalloc on the hot path.
+class Arena {
+ public:
+  ~Arena();
+  double* take(size_t doubles);
+  void reset();
+  size_t capacity() const;
+
+ private:
+  struct Chunk { double* p; size_t cap; };
+  std::vector<Chunk> chunks_;
+  size_t cur_ = 0, off_ = 0, used_total_ = 0, high_ = 0;
+};
+
+struct Context {
+  int device = 0;
+  int n = 0, logn = 0;
+  int L = 0, K = 0, alpha = 0, m = 0;   // Q primes, P primes, digit size, aux primes
+  uint64_t t = 0;
+  std::vector<uint64_t> primes;          // ids: Q [0,L), P [L,L+K), B [L+K,L+K+m), t last
+  std::vector<Mod> hmods;
+  int id_t = 0;
+  double* d_tables = nullptr;            // one allocation for all tables
+  Tables tab{};
+  uint32_t* d_slot_pos = nullptr;        // [N] position of slot s in the transform of R_t
+  std::unique_ptr<Arena> arena;
+
+  int idQ(int i) const { return i; }
+  int idP(int i) const { return L + i; }
+  int idB(int i) const { return L + K + i; }
+  int dnum(int level) const { return (level + alpha - 1) / alpha; }
+  Basis basis_Q(int level) const;
+  Basis basis_QP(int level) const;       // Q_level then P
+  Basis basis_QB(int level) const;       // Q_level then B
+  Mod mod(int id) const { return hmods[id]; }
+};
+
+// ---- transforms (ntt.hip)
+// data: [n_polys][basis.n][N]; each limb transformed in place with its prime.
+void ntt_forward(const Context& c, double* data, int n_polys, const Basis& b, hipStream_t s);
+void ntt_inverse(const Context& c, double* data, int n_polys, const Basis& b, hipStream_t s);
+void ntt_setup(const Context& c);
+
+}  // namespace bcn
+
+namespace bcn {
+
+// Exact basis conversion tables (mixed-radix / Garner).  A source basis
+// p_0..p_{ns-1} gives digits v with x = v_0 + p_0 (v_1 + p_1 (v_2 + ...)),
+// 0 <= v_k < p_k; comparing the digits with those of (M-1)/2, which are
+// (p_k - 1)/2, decides whether the centred value is x or x - M.
+struct Conv {
+  int ns, nd;
+  int src[kMaxBasis], dst[kMaxBasis];
+  double ginv[kMaxBasis][kMaxBasis];   // [i][k] = p_k^-1 mod p_i   (k < i)
+  double pm[kMaxBasis][kMaxBasis];     // [d][k] = p_k mod dst_d
+  double Mmod[kMaxBasis];              // prod_k p_k mod dst_d
+  double aux[kMaxBasis];               // per-destination extra constant (see users)
+  double aux2[kMaxBasis];
+};
+
+Conv make_conv(const Context& c, const std::vector<int>& src, const std::vector<int>& dst);
+
+// ---- element kernels (kernels.hip); all buffers are limb-major [..][limb][N]
+// out[o] = sum_j W[o][j] * in[j]; W dense f64 [n_out][n_in] (device),
+// tiles: per tile of TO rows the list of columns with a nonzero weight.
+struct MacPlan {
+  int n_in = 0, n_out = 0, tile = 0, n_tiles = 0;
+  double* W = nullptr;          // device [n_tiles*tile][n_in]
+  int* tile_ptr = nullptr;      // device [n_tiles+1]
+  int* tile_cols = nullptr;     // device
+  int chunk = 0;                // inputs between two partial reductions
+  double* host_owned[1] = {nullptr};
+};
+void mac(const Context& c, const MacPlan& p, const double* in, double* out, int level, hipStream_t s);
+
+// c0 of each ciphertext += Delta(m_i), m_i in [0, t) coefficient form, [n][N]
+void add_delta(const Context& c, double* ct, int n, int level, const double* m, hipStream_t s);
+// out[k] = in[k] (.) pt  (NTT domain); pt [level][N] shared, or [n][level][N] when per_ct
+void mul_plain_ntt(const Context& c, const double* in, double* out, int n, int level, const double* pt,
+                   bool per_ct, hipStream_t s);
+// out[k] = sum_c in[c] (.) pt[k][c]  (NTT domain); pt [n_out][n_in][level][N]
+void ptvec_mac_ntt(const Context& c, const double* in, int n_in, double* out, int n_out, int level,
+                   const double* pt, hipStream_t s);
+// square in the NTT domain over `nb` limbs: [n][2][nb][N] -> [n][3][nb][N]
+void tensor_square(const Context& c, const double* in, double* out, int n, const Basis& b, hipStream_t s);
+// exact centred extension of [n][2][level][N] (coeff) into [n][2][level+m][N] over Q_level then B
+void extend_qb(const Context& c, const double* in, double* out, int n, int level, hipStream_t s);
+// round(t x / Q_level) for [n][3][level+m][N] (coeff, Q then B) -> [n][3][level][N]
+void scale_round(const Context& c, const double* in, double* out, int n, int level, hipStream_t s);
+// centred digits of x [n][level][N] (coeff) raised to Q_level+P: [n][dnum][level+K][N]
+void decompose_modup(const Context& c, const double* in, size_t in_stride, double* out, int n, int level,
+                     hipStream_t s);
+// u[p] = sum_j D_j (.) key_j[p] over Q_level+P (NTT domain); output o uses digit block o / d_div
+// of D ([*][dnum][level+K][N]), the key keys[o] (device [dnum][2][L+K][N]) and, when galois is not
+// null, first permutes the digits by the automorphism X -> X^galois[o].  out [n][2][level+K][N].
+// Key selection for a batch of key switches: output o uses table entry o % nk, or the single
+// key1/galois1/kinv1 when keys is null.  galois = 1 means no automorphism.
+struct KeySel {
+  const double* const* keys = nullptr;
+  const int* galois = nullptr;
+  const int* kinv = nullptr;
+  int nk = 1;
+  const double* key1 = nullptr;
+  int galois1 = 1;
+  int kinv1 = 1;
+};
+void ks_inner(const Context& c, const double* D, int d_div, const KeySel& ks, int n, int level, double* out,
+              hipStream_t s);
+// exact round(u/P) of u [n][2][level+K][N] (coeff) -> [n][2][level][N], plus an addend:
+// add_mode 0: none; 1: add [n][2][level][N]; 2: add sigma_k(add) to part 0 only (add [n][2][level][N]).
+// With modswitch the result is further rounded by q_level to level-1 limbs.
+// The addend of output o is add + (o / add_div) * add_stride; mode 2 gathers it through the
+// inverse Galois element kinv[o].
+// Output o is written at out + (o / out_div) * out_outer + (o % out_div) * (ciphertext size);
+// out_div = 0 means contiguous outputs.
+void moddown(const Context& c, const double* u, int n, int level, const double* add, int add_div, size_t add_stride,
+             int add_mode, const KeySel& ks, bool modswitch, double* out, hipStream_t s, int out_div = 0,
+             size_t out_outer = 0);
+// out = a + b over [count] words whose limb is (word >> logn) % nl
+// a += b over n polynomials of `level` limbs ([n][level][N], limb = row % level)
+void add_inplace(const Context& c, double* a, const double* b, int npoly, int level, hipStream_t s);
+// [n][2][level][N] -> [n][2][level-1][N]
+void modswitch(const Context& c, const double* in, double* out, int n, int level, hipStream_t s);
+// coefficient-domain automorphism of [n][limbs][N]
+void automorphism_coeff(const Context& c, const double* in, double* out, int n, const Basis& b, int k,
+                        hipStream_t s);
+// m [n][N] in [0, t): residues of lift_c(m) on each limb of Q_level -> [n][level][N]
+void lift_plain(const Context& c, const double* m, double* out, int n, int level, hipStream_t s);
+// slot values (int64, any representative) -> transform-domain vector mod t at the slot positions
+void slots_to_tdomain(const Context& c, const int64_t* slots, double* out, int n, hipStream_t s);
+void tdomain_to_slots(const Context& c, const double* in, int64_t* slots, int n, hipStream_t s);
+// decryption rounding: x [n][level][N] (coeff) -> m [n][N] = round(t x / Q) mod t
+void dec_round(const Context& c, const double* x, double* m, int n, int level, hipStream_t s);
+// elementwise helpers on [n][limbs][N]
+void pointwise_mul(const Context& c, const double* a, const double* b, double* out, int n, const Basis& bs,
+                   bool b_shared, hipStream_t s);
+void small_to_rns(const Context& c, const int8_t* e, double* out, int n, const Basis& b, hipStream_t s);
+void u64_to_f64(const uint64_t* in, double* out, size_t count, hipStream_t s);
+void f64_to_u64(const double* in, uint64_t* out, size_t count, hipStream_t s);
+// out = -x + e (+ g * sp on the limbs in [g_lo, g_hi)) elementwise over [limbs][N]; g_val per limb
+void combine_keypart(const Context& c, const double* x, const double* e, const double* sp, double* out,
+                     const Basis& b, int g_lo, int g_hi, const double* g_val_host, hipStream_t s);
+// quantise FP32 features: q(f) = clamp(rint(8 f), -127, 127), gathered into slot vectors.
+// mode 0 (batch packing): slots[p][b] = q(f[b*stride_b + p]) for b < batch;
+// mode 1 (HW packing): slots[p][slot_of[k]] = q(f[p*per + k]) for k < per.
+void quantise_features(const Context& c, const float* f, int n_pt, int mode, int batch, int stride_b,
+                       const int* slot_of, int per, float scale, int clampv, int64_t* slots, hipStream_t s);
+
+}  // namespace bcn

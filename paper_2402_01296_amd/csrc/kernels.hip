@@ -1,0 +1,816 @@
+// Element-wise and per-coefficient kernels of the ciphertext branch.
+//
+// Layout: every RNS buffer is limb-major, [..][limb][N] binary64 residues in
+// [0, q).  Per-coefficient kernels (base conversion, rounding, modulus
+// switching) give one thread one coefficient of one polynomial and read its
+// limbs at stride N, so consecutive threads touch consecutive words.
+#include "internal.h"
+
+namespace bcn {
+namespace {
+
+constexpr int TPB = 256;
+
+inline unsigned nblocks(size_t work) { return (unsigned)((work + TPB - 1) / TPB); }
+
+// Mixed-radix digits of x over the first NS limbs of cv.src.
+template <int NS>
+__device__ __forceinline__ void garner(const double (&x)[NS], double (&v)[NS], const Conv& cv, const Mod* mods) {
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const Mod mi = mods[cv.src[i]];
+    double u = x[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) u = mul_lazy(u - v[k], cv.ginv[i][k], mi);
+    v[i] = norm(u, mi);
+  }
+}
+
+// true when sum_{k<n} v_k M_k > (M-1)/2, i.e. the centred value is negative
+template <int NS>
+__device__ __forceinline__ bool above_half(const double (&v)[NS], int n, const Conv& cv, const Mod* mods) {
+  bool decided = false, neg = false;
+#pragma unroll
+  for (int k = NS - 1; k >= 0; --k) {
+    if (k < n) {
+      const double h = (mods[cv.src[k]].q - 1.0) * 0.5;
+      if (!decided && v[k] != h) {
+        neg = v[k] > h;
+        decided = true;
+      }
+    }
+  }
+  return neg;
+}
+
+// ------------------------------------------------------------------ MAC
+
+template <int TO>
+__global__ void __launch_bounds__(TPB)
+k_mac(const double* __restrict__ in, double* __restrict__ out, int words, int logn, int level,
+      const double* __restrict__ W, int n_in, int n_out, const int* __restrict__ tptr,
+      const int* __restrict__ tcols, int chunk, Basis b, const Mod* __restrict__ mods) {
+  const int w = blockIdx.x * TPB + threadIdx.x;
+  if (w >= words) return;
+  const int tile = blockIdx.y;
+  const Mod m = mods[b.id[(w >> logn) % level]];
+  const double halfq = (m.q - 1.0) * 0.5;
+  double acc[TO];
+#pragma unroll
+  for (int o = 0; o < TO; ++o) acc[o] = 0.0;
+  const int beg = tptr[tile], end = tptr[tile + 1];
+  const double* wt = W + (size_t)tile * TO * n_in;
+  int cnt = 0;
+  for (int e = beg; e < end; ++e) {
+    const int j = tcols[e];
+    double x = in[(size_t)j * words + w];
+    x = x > halfq ? x - m.q : x;          // centred: |x| <= (q-1)/2
+#pragma unroll
+    for (int o = 0; o < TO; ++o) acc[o] = fma(wt[(size_t)o * n_in + j], x, acc[o]);
+    if (++cnt == chunk) {
+      cnt = 0;
+#pragma unroll
+      for (int o = 0; o < TO; ++o) acc[o] = reduce_lazy(acc[o], m);
+    }
+  }
+#pragma unroll
+  for (int o = 0; o < TO; ++o) {
+    const int oo = tile * TO + o;
+    if (oo < n_out) out[(size_t)oo * words + w] = reduce(acc[o], m);
+  }
+}
+
+// ------------------------------------------------------------------ plaintext ops
+
+struct LimbConsts {
+  double v[kMaxBasis];
+};
+
+__global__ void k_add_delta(double* __restrict__ ct, int n, int level, int logn, const double* __restrict__ msg,
+                            double qmodt, Mod mt, Basis b, const Mod* __restrict__ mods, LimbConsts negtinv) {
+  const size_t N = (size_t)1 << logn;
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx >= (size_t)n * level * N) return;
+  const size_t ci = idx / (level * N);
+  const int limb = (int)((idx >> logn) % level);
+  const size_t k = idx & (N - 1);
+  const double r = mul_mod(qmodt, msg[ci * N + k], mt);          // [Q m]_t
+  const Mod mq = mods[b.id[limb]];
+  double d = norm(mul_lazy(r, negtinv.v[limb], mq), mq);         // floor(Q m / t) mod q
+  if (2.0 * r > mt.q) d = add_mod(d, 1.0, mq);                   // nearest, never a tie (t odd)
+  double* p = ct + ci * 2 * level * N + (size_t)limb * N + k;   // part 0
+  *p = add_mod(*p, d, mq);
+}
+
+__global__ void k_mul_plain(const double* __restrict__ in, double* __restrict__ out, int n, int level, int logn,
+                            const double* __restrict__ pt, int per_ct, Basis b, const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << logn;
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx >= (size_t)n * 2 * level * N) return;
+  const size_t ci = idx / (2 * level * N);
+  const size_t lk = idx % (level * N);                            // limb*N + k
+  const Mod m = mods[b.id[lk >> logn]];
+  const double p = pt[(per_ct ? ci * level * N : 0) + lk];
+  out[idx] = mul_mod(in[idx], p, m);
+}
+
+__global__ void k_ptvec_mac(const double* __restrict__ in, int n_in, double* __restrict__ out, int n_out,
+                            int level, int logn, const double* __restrict__ pt, Basis b,
+                            const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << logn;
+  const size_t words = 2 * level * N;
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx >= (size_t)n_out * words) return;
+  const size_t ko = idx / words, w = idx % words;
+  const size_t lk = w % (level * N);
+  const Mod m = mods[b.id[lk >> logn]];
+  double acc = 0.0;
+  for (int cc = 0; cc < n_in; ++cc) {
+    acc += mul_lazy(in[(size_t)cc * words + w], pt[(ko * n_in + cc) * level * N + lk], m);
+    if ((cc & 1023) == 1023) acc = reduce_lazy(acc, m);
+  }
+  out[idx] = reduce(acc, m);
+}
+
+__global__ void k_tensor_square(const double* __restrict__ in, double* __restrict__ out, int n, int nb, int logn,
+                                Basis b, const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << logn;
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx >= (size_t)n * nb * N) return;
+  const size_t ci = idx / (nb * N), lk = idx % (nb * N);
+  const Mod m = mods[b.id[lk >> logn]];
+  const double a0 = in[(ci * 2) * nb * N + lk], a1 = in[(ci * 2 + 1) * nb * N + lk];
+  const double x = mul_mod(a0, a1, m);
+  out[(ci * 3) * nb * N + lk] = mul_mod(a0, a0, m);
+  out[(ci * 3 + 1) * nb * N + lk] = add_mod(x, x, m);
+  out[(ci * 3 + 2) * nb * N + lk] = mul_mod(a1, a1, m);
+}
+
+// ------------------------------------------------------------------ exact base conversions
+
+// [n][2][level][N] over Q_level -> [n][2][level+m][N] over Q_level then B (centred lift)
+template <int NS>
+__global__ void __launch_bounds__(TPB)
+k_extend_qb(const double* __restrict__ in, double* __restrict__ out, int npoly, int logn,
+            const Conv* __restrict__ cvp, const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << logn;
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx >= (size_t)npoly * N) return;
+  const Conv& cv = *cvp;
+  const size_t poly = idx >> logn, k = idx & (N - 1);
+  const int nd = cv.nd;
+  const double* src = in + poly * NS * N + k;
+  double* dst = out + poly * (NS + nd) * N + k;
+  double x[NS], v[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    x[i] = src[i * N];
+    dst[i * N] = x[i];
+  }
+  garner<NS>(x, v, cv, mods);
+  const bool neg = above_half<NS>(v, NS, cv, mods);
+  for (int d = 0; d < nd; ++d) {
+    const Mod md = mods[cv.dst[d]];
+    double acc = v[NS - 1];
+#pragma unroll
+    for (int kk = NS - 2; kk >= 0; --kk) acc = mul_lazy(acc, cv.pm[d][kk], md) + v[kk];
+    if (neg) acc -= cv.Mmod[d];
+    dst[(NS + d) * N] = reduce(acc, md);
+  }
+}
+
+// [n][3][level+m][N] (Q_level then B) -> [n][3][level][N]: round(t x / Q_level) mod q_i.
+// cv.src = Q_level + B, cv.dst = Q_level, cv.pm[d][k] = src_k mod q_d, cv.aux[d] = B mod q_d,
+// cv.aux2[0] = t, nq = level.
+template <int NS>
+__global__ void __launch_bounds__(TPB)
+k_scale_round(const double* __restrict__ in, double* __restrict__ out, int npoly, int logn, int nq,
+              const Conv* __restrict__ cvp, const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << logn;
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx >= (size_t)npoly * N) return;
+  const Conv& cv = *cvp;
+  const size_t poly = idx >> logn, k = idx & (N - 1);
+  const double t = cv.aux2[0];
+  const double* src = in + poly * NS * N + k;
+  double x[NS], v[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) x[i] = src[i * N];
+  garner<NS>(x, v, cv, mods);
+  const bool neg = above_half<NS>(v, NS, cv, mods);
+  // t * r = sum_k w_k M_k + c * Q_level over the Q digits (exact carry chain)
+  double c = 0.0;
+  double wdig[NS];
+#pragma unroll
+  for (int kk = 0; kk < NS; ++kk) {
+    if (kk < nq) {
+      const Mod mk = mods[cv.src[kk]];
+      double quo;
+      wdig[kk] = mul_add_divmod(t, v[kk], c, mk, &quo);
+      c = quo;
+    } else {
+      wdig[kk] = 0.0;
+    }
+  }
+  const bool up = above_half<NS>(wdig, nq, cv, mods);
+  const double R = c + (up ? 1.0 : 0.0);                          // round(t r / Q) in [0, t]
+  double* dst = out + poly * nq * N + k;
+  for (int d = 0; d < nq; ++d) {
+    const Mod md = mods[cv.dst[d]];
+    // K = floor(x / Q) from the B digits, minus B when the centred value is negative
+    double acc = v[NS - 1];
+#pragma unroll
+    for (int kk = NS - 2; kk >= 0; --kk)
+      if (kk >= nq) acc = mul_lazy(acc, cv.pm[d][kk], md) + v[kk];
+    if (neg) acc -= cv.aux[d];
+    const double y = mul_lazy(t, reduce(acc, md), md) + R;
+    dst[d * N] = reduce(y, md);
+  }
+}
+
+// digit j of x [n][level][N]: centred residue over the digit's primes, raised to Q_level + P.
+// cv.src = digit primes (NS of them), cv.dst = Q_level + P; cv.aux[d] = 1 when dst d is in the digit
+// (then the value is copied), with the source limb index in cv.aux2[d].
+template <int NS>
+__global__ void __launch_bounds__(TPB)
+k_modup(const double* __restrict__ in, size_t in_stride, double* __restrict__ out, int npoly, int logn, int digit,
+        int dnum, const Conv* __restrict__ cvp, const Mod* __restrict__ mods, int first_limb) {
+  const size_t N = (size_t)1 << logn;
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx >= (size_t)npoly * N) return;
+  const Conv& cv = *cvp;
+  const size_t poly = idx >> logn, k = idx & (N - 1);
+  const double* src = in + poly * in_stride + k;
+  double x[NS], v[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) x[i] = src[(first_limb + i) * N];
+  garner<NS>(x, v, cv, mods);
+  const bool neg = above_half<NS>(v, NS, cv, mods);
+  const int nd = cv.nd;
+  double* dst = out + (poly * dnum + digit) * nd * N + k;
+  for (int d = 0; d < nd; ++d) {
+    if (cv.aux[d] != 0.0) {
+      dst[d * N] = x[(int)cv.aux2[d]];
+      continue;
+    }
+    const Mod md = mods[cv.dst[d]];
+    double acc = v[NS - 1];
+#pragma unroll
+    for (int kk = NS - 2; kk >= 0; --kk) acc = mul_lazy(acc, cv.pm[d][kk], md) + v[kk];
+    if (neg) acc -= cv.Mmod[d];
+    dst[d * N] = reduce(acc, md);
+  }
+}
+
+__device__ __forceinline__ int bitrev_n(int x, int logn) { return (int)(__brev((unsigned)x) >> (32 - logn)); }
+
+// NTT-domain automorphism: sigma_k(a)^ at position pos = a^ at the returned position
+__device__ __forceinline__ int ntt_perm(int pos, int galois, int logn) {
+  const int N = 1 << logn;
+  const int j = bitrev_n(pos, logn);
+  const int e = (int)(((long long)(2 * j + 1) * galois) & (2 * N - 1));
+  return bitrev_n((e - 1) >> 1, logn);
+}
+
+
+__global__ void __launch_bounds__(TPB)
+k_ks_inner(const double* __restrict__ D, KeySel ka, int n, int d_div, int level, int nb, int dnum, int L,
+           int logn, Basis b, const Mod* __restrict__ mods, double* __restrict__ out) {
+  const size_t N = (size_t)1 << logn;
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx >= (size_t)n * nb * N) return;
+  const size_t o = idx / (nb * N);
+  const int limb = (int)((idx >> logn) % nb);
+  const int k = (int)(idx & (N - 1));
+  const Mod m = mods[b.id[limb]];
+  const int sel = (int)(o % ka.nk);
+  const int g = ka.keys ? ka.galois[sel] : ka.galois1;
+  const int src = g == 1 ? k : ntt_perm(k, g, logn);
+  const double* dd = D + (o / d_div) * dnum * nb * N + (size_t)limb * N + src;
+  const double* key = ka.keys ? ka.keys[sel] : ka.key1;
+  const int klimb = limb < level ? limb : L + (limb - level);
+  const int KL = nb - level + L;                                   // limbs of a key part (L + K)
+  double a0 = 0.0, a1 = 0.0;
+  for (int j = 0; j < dnum; ++j) {
+    const double dj = dd[(size_t)j * nb * N];
+    a0 += mul_lazy(dj, key[((size_t)(j * 2) * KL + klimb) * N + k], m);
+    a1 += mul_lazy(dj, key[((size_t)(j * 2 + 1) * KL + klimb) * N + k], m);
+  }
+  out[(o * 2) * nb * N + (size_t)limb * N + k] = reduce(a0, m);
+  out[(o * 2 + 1) * nb * N + (size_t)limb * N + k] = reduce(a1, m);
+}
+
+// gather form of the coefficient automorphism X -> X^k: value at n comes from i = n k^-1 mod 2N
+__device__ __forceinline__ double auto_gather(const double* __restrict__ a, int n, int kinv, int logn, Mod m) {
+  const int N = 1 << logn;
+  const int i = (int)(((long long)n * kinv) & (2 * N - 1));
+  if (i < N) return a[i];
+  const double x = a[i - N];
+  return x == 0.0 ? 0.0 : m.q - x;
+}
+
+// exact round(u/P) mod q_i, optional addend, optional modulus switch.
+// cv.src = P primes (NK), cv.dst = Q_level; cv.pm/Mmod as for conversions;
+// cv.aux[d] = P^-1 mod q_d; cv.aux2[d] = q_{level-1}^-1 mod q_d.
+template <int NK, int NQ>
+__global__ void __launch_bounds__(TPB)
+k_moddown(const double* __restrict__ u, int n, int logn, const double* __restrict__ add, int add_div,
+          size_t add_stride, int add_mode, KeySel ks, int modsw, const Conv* __restrict__ cvp,
+          const Mod* __restrict__ mods, double* __restrict__ out, int out_div, size_t out_outer) {
+  const size_t N = (size_t)1 << logn;
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx >= (size_t)n * 2 * N) return;
+  const Conv& cv = *cvp;
+  const size_t ci = idx / (2 * N);
+  const int part = (int)((idx >> logn) & 1);
+  const int k = (int)(idx & (N - 1));
+  constexpr int NB = NQ + NK;
+  const double* up = u + (ci * 2 + part) * NB * N + k;
+  double x[NK], v[NK];
+#pragma unroll
+  for (int i = 0; i < NK; ++i) x[i] = up[(NQ + i) * N];
+  garner<NK>(x, v, cv, mods);
+  const bool neg = above_half<NK>(v, NK, cv, mods);
+  double res[NQ];
+#pragma unroll
+  for (int d = 0; d < NQ; ++d) {
+    const Mod md = mods[cv.dst[d]];
+    double acc = v[NK - 1];
+#pragma unroll
+    for (int kk = NK - 2; kk >= 0; --kk) acc = mul_lazy(acc, cv.pm[d][kk], md) + v[kk];
+    if (neg) acc -= cv.Mmod[d];                                    // |acc| < 2^43: lift_c([u]_P) mod q_d
+    double r = norm(mul_lazy(up[d * N] - reduce(acc, md), cv.aux[d], md), md);
+    if (add_mode == 1) {
+      r = add_mod(r, add[(ci / add_div) * add_stride + (size_t)(part * NQ + d) * N + k], md);
+    } else if (add_mode == 2 && part == 0) {
+      const int kinv = ks.kinv ? ks.kinv[ci % ks.nk] : ks.kinv1;
+      r = add_mod(r, auto_gather(add + (ci / add_div) * add_stride + (size_t)d * N, k, kinv, logn, md), md);
+    }
+    res[d] = r;
+  }
+  const int NQO = modsw ? NQ - 1 : NQ;
+  double* ob = out + (ci / out_div) * out_outer + (ci % out_div) * 2 * NQO * N + (size_t)part * NQO * N + k;
+  if (!modsw) {
+#pragma unroll
+    for (int d = 0; d < NQ; ++d) ob[(size_t)d * N] = res[d];
+    return;
+  }
+  const Mod ml = mods[cv.dst[NQ - 1]];
+  const double last = res[NQ - 1];
+  const double lc = last > (ml.q - 1.0) * 0.5 ? last - ml.q : last;
+#pragma unroll
+  for (int d = 0; d < NQ - 1; ++d) {
+    const Mod md = mods[cv.dst[d]];
+    ob[(size_t)d * N] = norm(mul_lazy(res[d] - lc, cv.aux2[d], md), md);
+  }
+}
+
+// [n][2][level][N] -> [n][2][level-1][N]; linv[d] = q_{level-1}^-1 mod q_d
+__global__ void k_modswitch(const double* __restrict__ in, double* __restrict__ out, int n, int level, int logn,
+                            Basis b, const Mod* __restrict__ mods, LimbConsts linv) {
+  const size_t N = (size_t)1 << logn;
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx >= (size_t)n * 2 * N) return;
+  const size_t pp = idx >> logn;        // ciphertext*2 + part
+  const size_t k = idx & (N - 1);
+  const Mod ml = mods[b.id[level - 1]];
+  const double last = in[(pp * level + level - 1) * N + k];
+  const double lc = last > (ml.q - 1.0) * 0.5 ? last - ml.q : last;
+  for (int d = 0; d < level - 1; ++d) {
+    const Mod md = mods[b.id[d]];
+    out[(pp * (level - 1) + d) * N + k] = norm(mul_lazy(in[(pp * level + d) * N + k] - lc, linv.v[d], md), md);
+  }
+}
+
+__global__ void k_automorphism(const double* __restrict__ in, double* __restrict__ out, int npoly, int nl, int logn,
+                               int kinv, Basis b, const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << logn;
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx >= (size_t)npoly * nl * N) return;
+  const size_t row = idx >> logn;
+  const int k = (int)(idx & (N - 1));
+  const Mod m = mods[b.id[row % nl]];
+  out[idx] = auto_gather(in + row * N, k, kinv, logn, m);
+}
+
+__global__ void k_lift_plain(const double* __restrict__ msg, double* __restrict__ out, int n, int level, int logn,
+                             double t, Basis b, const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << logn;
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx >= (size_t)n * level * N) return;
+  const size_t ci = idx / (level * N);
+  const int limb = (int)((idx >> logn) % level);
+  const size_t k = idx & (N - 1);
+  const double mv = msg[ci * N + k];
+  const double mc = mv > (t - 1.0) * 0.5 ? mv - t : mv;
+  const Mod m = mods[b.id[limb]];
+  out[idx] = mc < 0.0 ? mc + m.q : mc;
+}
+
+__global__ void k_slots_to_t(const int64_t* __restrict__ slots, double* __restrict__ out, int n, int logn,
+                             long long t, const uint32_t* __restrict__ pos) {
+  const size_t N = (size_t)1 << logn;
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx >= (size_t)n * N) return;
+  const size_t ci = idx >> logn, s = idx & (N - 1);
+  long long v = (long long)(slots[idx] % t);
+  if (v < 0) v += t;
+  out[ci * N + pos[s]] = (double)v;
+}
+
+__global__ void k_t_to_slots(const double* __restrict__ in, int64_t* __restrict__ slots, int n, int logn,
+                             double t, const uint32_t* __restrict__ pos) {
+  const size_t N = (size_t)1 << logn;
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx >= (size_t)n * N) return;
+  const size_t ci = idx >> logn, s = idx & (N - 1);
+  const double v = in[ci * N + pos[s]];
+  slots[idx] = (int64_t)(v > (t - 1.0) * 0.5 ? v - t : v);
+}
+
+// m = round(t x / Q) mod t from x over Q_level (coefficient form)
+template <int NS>
+__global__ void __launch_bounds__(TPB)
+k_dec_round(const double* __restrict__ xin, double* __restrict__ msg, int n, int logn, double t,
+            const Conv* __restrict__ cvp, const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << logn;
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx >= (size_t)n * N) return;
+  const Conv& cv = *cvp;
+  const size_t ci = idx >> logn, k = idx & (N - 1);
+  double x[NS], v[NS], wdig[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) x[i] = xin[(ci * NS + i) * N + k];
+  garner<NS>(x, v, cv, mods);
+  double c = 0.0;
+#pragma unroll
+  for (int kk = 0; kk < NS; ++kk) {
+    double quo;
+    wdig[kk] = mul_add_divmod(t, v[kk], c, mods[cv.src[kk]], &quo);
+    c = quo;
+  }
+  double r = c + (above_half<NS>(wdig, NS, cv, mods) ? 1.0 : 0.0);
+  if (r >= t) r -= t;
+  msg[idx] = r;
+}
+
+__global__ void k_pointwise(const double* __restrict__ a, const double* __restrict__ bb, double* __restrict__ out,
+                            int n, int nl, int logn, int b_shared, Basis b, const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << logn;
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx >= (size_t)n * nl * N) return;
+  const size_t lk = idx % (nl * N);
+  const Mod m = mods[b.id[lk >> logn]];
+  out[idx] = mul_mod(a[idx], bb[b_shared ? lk : idx], m);
+}
+
+__global__ void k_small_to_rns(const int8_t* __restrict__ e, double* __restrict__ out, int n, int nl, int logn,
+                               Basis b, const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << logn;
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx >= (size_t)n * nl * N) return;
+  const size_t ci = idx / (nl * N);
+  const int limb = (int)((idx >> logn) % nl);
+  const double v = (double)e[ci * N + (idx & (N - 1))];
+  const Mod m = mods[b.id[limb]];
+  out[idx] = v < 0.0 ? v + m.q : v;
+}
+
+__global__ void k_add_inplace(double* __restrict__ a, const double* __restrict__ b, size_t count, int level, int logn,
+                              Basis bs, const Mod* __restrict__ mods) {
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx >= count) return;
+  const Mod m = mods[bs.id[(idx >> logn) % level]];
+  a[idx] = add_mod(a[idx], b[idx], m);
+}
+
+__global__ void k_u64_to_f64(const uint64_t* __restrict__ in, double* __restrict__ out, size_t count) {
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx < count) out[idx] = (double)in[idx];
+}
+
+__global__ void k_f64_to_u64(const double* __restrict__ in, uint64_t* __restrict__ out, size_t count) {
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx < count) out[idx] = (uint64_t)in[idx];
+}
+
+__global__ void k_keypart(const double* __restrict__ x, const double* __restrict__ e, const double* __restrict__ sp,
+                          double* __restrict__ out, int nl, int logn, int g_lo, int g_hi, LimbConsts gval, Basis b,
+                          const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << logn;
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx >= (size_t)nl * N) return;
+  const int limb = (int)(idx >> logn);
+  const Mod m = mods[b.id[limb]];
+  double r = sub_mod(e[idx], x[idx], m);
+  if (limb >= g_lo && limb < g_hi) r = add_mod(r, mul_mod(gval.v[limb], sp[idx], m), m);
+  out[idx] = r;
+}
+
+__global__ void k_quantise(const float* __restrict__ f, int n_pt, int mode, int batch, int stride_b,
+                           const int* __restrict__ slot_of, int per, float scale, int clampv,
+                           int64_t* __restrict__ slots, int logn) {
+  const size_t N = (size_t)1 << logn;
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (mode == 0) {
+    if (idx >= (size_t)n_pt * batch) return;
+    const size_t p = idx / batch, bi = idx % batch;
+    float q = rintf(scale * f[bi * (size_t)stride_b + p]);
+    q = fminf(fmaxf(q, (float)-clampv), (float)clampv);
+    slots[p * N + bi] = (int64_t)q;
+  } else {
+    if (idx >= (size_t)n_pt * per) return;
+    const size_t p = idx / per, kk = idx % per;
+    float q = rintf(scale * f[p * per + kk]);
+    q = fminf(fmaxf(q, (float)-clampv), (float)clampv);
+    slots[p * N + slot_of[kk]] = (int64_t)q;
+  }
+}
+
+#define BCN_DISPATCH_NS(ns, MACRO)                                                                  \
+  switch (ns) {                                                                                     \
+    case 1: MACRO(1); break; case 2: MACRO(2); break; case 3: MACRO(3); break; case 4: MACRO(4); break; \
+    case 5: MACRO(5); break; case 6: MACRO(6); break; case 7: MACRO(7); break; case 8: MACRO(8); break; \
+    case 9: MACRO(9); break; case 10: MACRO(10); break; case 11: MACRO(11); break;                  \
+    case 12: MACRO(12); break; case 13: MACRO(13); break; case 14: MACRO(14); break;                \
+    case 15: MACRO(15); break; case 16: MACRO(16); break;                                            \
+    default: throw Error(-1, "basis too large for the conversion kernels");                         \
+  }
+
+}  // namespace
+
+// ------------------------------------------------------------------ host wrappers
+
+void mac(const Context& c, const MacPlan& p, const double* in, double* out, int level, hipStream_t s) {
+  const int words = 2 * level * c.n;
+  if (p.n_out == 0) return;
+  dim3 grid(nblocks(words), p.n_tiles);
+  const Basis b = c.basis_Q(level);
+  switch (p.tile) {
+#define BCN_MAC_CASE(TO) \
+  case TO: hipLaunchKernelGGL(k_mac<TO>, grid, dim3(TPB), 0, s, in, out, words, c.logn, level, p.W, p.n_in, p.n_out, \
+                              p.tile_ptr, p.tile_cols, p.chunk, b, c.tab.mods); break;
+    BCN_MAC_CASE(1) BCN_MAC_CASE(2) BCN_MAC_CASE(4) BCN_MAC_CASE(8) BCN_MAC_CASE(16) BCN_MAC_CASE(32)
+#undef BCN_MAC_CASE
+    default: throw Error(-1, "bad MAC tile");
+  }
+  BCN_HIP(hipGetLastError());
+}
+
+void add_delta(const Context& c, double* ct, int n, int level, const double* m, hipStream_t s) {
+  if (n == 0) return;
+  const Mod mt = c.mod(c.id_t);
+  // Q_level mod t and -t^-1 mod q_i
+  uint64_t qmodt = 1;
+  LimbConsts neg{};
+  for (int i = 0; i < level; ++i) {
+    qmodt = host::mulmod(qmodt, c.primes[i] % c.t, c.t);
+    const uint64_t q = c.primes[i];
+    neg.v[i] = (double)((q - host::invmod(c.t % q, q)) % q);
+  }
+  hipLaunchKernelGGL(k_add_delta, dim3(nblocks((size_t)n * level * c.n)), dim3(TPB), 0, s, ct, n, level, c.logn, m,
+                     (double)qmodt, mt, c.basis_Q(level), c.tab.mods, neg);
+  BCN_HIP(hipGetLastError());
+}
+
+void mul_plain_ntt(const Context& c, const double* in, double* out, int n, int level, const double* pt, bool per_ct,
+                   hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_mul_plain, dim3(nblocks((size_t)n * 2 * level * c.n)), dim3(TPB), 0, s, in, out, n, level,
+                     c.logn, pt, per_ct ? 1 : 0, c.basis_Q(level), c.tab.mods);
+  BCN_HIP(hipGetLastError());
+}
+
+void ptvec_mac_ntt(const Context& c, const double* in, int n_in, double* out, int n_out, int level, const double* pt,
+                   hipStream_t s) {
+  if (n_out == 0) return;
+  hipLaunchKernelGGL(k_ptvec_mac, dim3(nblocks((size_t)n_out * 2 * level * c.n)), dim3(TPB), 0, s, in, n_in, out,
+                     n_out, level, c.logn, pt, c.basis_Q(level), c.tab.mods);
+  BCN_HIP(hipGetLastError());
+}
+
+void tensor_square(const Context& c, const double* in, double* out, int n, const Basis& b, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_tensor_square, dim3(nblocks((size_t)n * b.n * c.n)), dim3(TPB), 0, s, in, out, n, b.n, c.logn,
+                     b, c.tab.mods);
+  BCN_HIP(hipGetLastError());
+}
+
+const Conv* conv_device(const Context& c, const std::string& key, const Conv& cv);
+
+void extend_qb(const Context& c, const double* in, double* out, int n, int level, hipStream_t s) {
+  if (n == 0) return;
+  std::vector<int> src, dst;
+  for (int i = 0; i < level; ++i) src.push_back(c.idQ(i));
+  for (int i = 0; i < c.m; ++i) dst.push_back(c.idB(i));
+  const Conv* cv = conv_device(c, "ext" + std::to_string(level), make_conv(c, src, dst));
+  const int npoly = 2 * n;
+#define BCN_EXT(NS) hipLaunchKernelGGL(k_extend_qb<NS>, dim3(nblocks((size_t)npoly * c.n)), dim3(TPB), 0, s, in, out, \
+                                       npoly, c.logn, cv, c.tab.mods)
+  BCN_DISPATCH_NS(level, BCN_EXT)
+#undef BCN_EXT
+  BCN_HIP(hipGetLastError());
+}
+
+void scale_round(const Context& c, const double* in, double* out, int n, int level, hipStream_t s) {
+  if (n == 0) return;
+  std::vector<int> src, dst;
+  for (int i = 0; i < level; ++i) { src.push_back(c.idQ(i)); dst.push_back(c.idQ(i)); }
+  for (int i = 0; i < c.m; ++i) src.push_back(c.idB(i));
+  const std::string key = "sr" + std::to_string(level);
+  Conv cv = make_conv(c, src, dst);
+  for (int d = 0; d < level; ++d) {
+    uint64_t bm = 1;
+    const uint64_t q = c.primes[d];
+    for (int i = 0; i < c.m; ++i) bm = host::mulmod(bm, c.primes[c.idB(i)] % q, q);
+    cv.aux[d] = (double)bm;
+  }
+  cv.aux2[0] = (double)c.t;
+  const Conv* dcv = conv_device(c, key, cv);
+  const int npoly = 3 * n;
+  const int ns = level + c.m;
+#define BCN_SR(NS) hipLaunchKernelGGL(k_scale_round<NS>, dim3(nblocks((size_t)npoly * c.n)), dim3(TPB), 0, s, in, out, \
+                                      npoly, c.logn, level, dcv, c.tab.mods)
+  BCN_DISPATCH_NS(ns, BCN_SR)
+#undef BCN_SR
+  BCN_HIP(hipGetLastError());
+}
+
+void decompose_modup(const Context& c, const double* in, size_t in_stride, double* out, int n, int level,
+                     hipStream_t s) {
+  if (n == 0) return;
+  const int dnum = c.dnum(level);
+  const Basis dstb = c.basis_QP(level);
+  for (int j = 0; j < dnum; ++j) {
+    const int lo = j * c.alpha, hi = std::min((j + 1) * c.alpha, level);
+    std::vector<int> src, dst;
+    for (int i = lo; i < hi; ++i) src.push_back(c.idQ(i));
+    for (int i = 0; i < dstb.n; ++i) dst.push_back(dstb.id[i]);
+    Conv cv = make_conv(c, src, dst);
+    for (int d = 0; d < dstb.n; ++d) {
+      cv.aux[d] = (d >= lo && d < hi) ? 1.0 : 0.0;
+      cv.aux2[d] = (d >= lo && d < hi) ? (double)(d - lo) : 0.0;
+    }
+    const Conv* dcv = conv_device(c, "mu" + std::to_string(level) + "_" + std::to_string(j), cv);
+    const int ns = hi - lo;
+#define BCN_MU(NS) hipLaunchKernelGGL(k_modup<NS>, dim3(nblocks((size_t)n * c.n)), dim3(TPB), 0, s, in, in_stride, out, \
+                                      n, c.logn, j, dnum, dcv, c.tab.mods, lo)
+    BCN_DISPATCH_NS(ns, BCN_MU)
+#undef BCN_MU
+    BCN_HIP(hipGetLastError());
+  }
+}
+
+void ks_inner(const Context& c, const double* D, int d_div, const KeySel& ka, int n, int level, double* out,
+              hipStream_t s) {
+  if (n == 0) return;
+  const Basis b = c.basis_QP(level);
+  hipLaunchKernelGGL(k_ks_inner, dim3(nblocks((size_t)n * b.n * c.n)), dim3(TPB), 0, s, D, ka, n, d_div,
+                     level, b.n, c.dnum(level), c.L, c.logn, b, c.tab.mods, out);
+  BCN_HIP(hipGetLastError());
+}
+
+void moddown(const Context& c, const double* u, int n, int level, const double* add, int add_div, size_t add_stride,
+             int add_mode, const KeySel& ks, bool modsw, double* out, hipStream_t s, int out_div, size_t out_outer) {
+  if (n == 0) return;
+  if (modsw && level < 2) throw Error(-2, "modulus switch needs at least two primes");
+  std::vector<int> src, dst;
+  for (int i = 0; i < c.K; ++i) src.push_back(c.idP(i));
+  for (int i = 0; i < level; ++i) dst.push_back(c.idQ(i));
+  Conv cv = make_conv(c, src, dst);
+  for (int d = 0; d < level; ++d) {
+    const uint64_t q = c.primes[d];
+    uint64_t pm = 1;
+    for (int i = 0; i < c.K; ++i) pm = host::mulmod(pm, c.primes[c.idP(i)] % q, q);
+    cv.aux[d] = (double)host::invmod(pm, q);
+    cv.aux2[d] = (d < level - 1) ? (double)host::invmod(c.primes[level - 1] % q, q) : 0.0;
+  }
+  const Conv* dcv = conv_device(c, "md" + std::to_string(level), cv);
+  const size_t work = (size_t)n * 2 * c.n;
+#define BCN_MD(NK, NQ) hipLaunchKernelGGL((k_moddown<NK, NQ>), dim3(nblocks(work)), dim3(TPB), 0, s, u, n, c.logn, add, \
+                                          add_div, add_stride, add_mode, ks, modsw ? 1 : 0, dcv, c.tab.mods, out, \
+                                          out_div > 0 ? out_div : 1, \
+                                          out_div > 0 ? out_outer : (size_t)2 * (modsw ? level - 1 : level) * c.n)
+#define BCN_MDQ(NK)                                                                                   \
+  switch (level) {                                                                                    \
+    case 1: BCN_MD(NK, 1); break; case 2: BCN_MD(NK, 2); break; case 3: BCN_MD(NK, 3); break;         \
+    case 4: BCN_MD(NK, 4); break; case 5: BCN_MD(NK, 5); break; case 6: BCN_MD(NK, 6); break;         \
+    case 7: BCN_MD(NK, 7); break; case 8: BCN_MD(NK, 8); break;                                        \
+    default: throw Error(-1, "too many ciphertext primes for moddown");                               \
+  }
+  switch (c.K) {
+    case 1: BCN_MDQ(1); break;
+    case 2: BCN_MDQ(2); break;
+    case 3: BCN_MDQ(3); break;
+    default: throw Error(-1, "too many special primes");
+  }
+#undef BCN_MDQ
+#undef BCN_MD
+  BCN_HIP(hipGetLastError());
+}
+
+void modswitch(const Context& c, const double* in, double* out, int n, int level, hipStream_t s) {
+  if (n == 0) return;
+  if (level < 2) throw Error(-2, "modulus switch needs at least two primes");
+  LimbConsts linv{};
+  for (int d = 0; d < level - 1; ++d) linv.v[d] = (double)host::invmod(c.primes[level - 1] % c.primes[d], c.primes[d]);
+  hipLaunchKernelGGL(k_modswitch, dim3(nblocks((size_t)n * 2 * c.n)), dim3(TPB), 0, s, in, out, n, level, c.logn,
+                     c.basis_Q(level), c.tab.mods, linv);
+  BCN_HIP(hipGetLastError());
+}
+
+void automorphism_coeff(const Context& c, const double* in, double* out, int n, const Basis& b, int k, hipStream_t s) {
+  if (n == 0) return;
+  const int kinv = (int)host::inv_pow2(((uint64_t)k), c.logn + 1);
+  hipLaunchKernelGGL(k_automorphism, dim3(nblocks((size_t)n * b.n * c.n)), dim3(TPB), 0, s, in, out, n, b.n, c.logn,
+                     kinv, b, c.tab.mods);
+  BCN_HIP(hipGetLastError());
+}
+
+void lift_plain(const Context& c, const double* m, double* out, int n, int level, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_lift_plain, dim3(nblocks((size_t)n * level * c.n)), dim3(TPB), 0, s, m, out, n, level, c.logn,
+                     (double)c.t, c.basis_Q(level), c.tab.mods);
+  BCN_HIP(hipGetLastError());
+}
+
+void slots_to_tdomain(const Context& c, const int64_t* slots, double* out, int n, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_slots_to_t, dim3(nblocks((size_t)n * c.n)), dim3(TPB), 0, s, slots, out, n, c.logn,
+                     (long long)c.t, c.d_slot_pos);
+  BCN_HIP(hipGetLastError());
+}
+
+void tdomain_to_slots(const Context& c, const double* in, int64_t* slots, int n, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_t_to_slots, dim3(nblocks((size_t)n * c.n)), dim3(TPB), 0, s, in, slots, n, c.logn,
+                     (double)c.t, c.d_slot_pos);
+  BCN_HIP(hipGetLastError());
+}
+
+void dec_round(const Context& c, const double* x, double* m, int n, int level, hipStream_t s) {
+  if (n == 0) return;
+  std::vector<int> src;
+  for (int i = 0; i < level; ++i) src.push_back(c.idQ(i));
+  const Conv* dcv = conv_device(c, "dec" + std::to_string(level), make_conv(c, src, {}));
+#define BCN_DEC(NS) hipLaunchKernelGGL(k_dec_round<NS>, dim3(nblocks((size_t)n * c.n)), dim3(TPB), 0, s, x, m, n, c.logn, \
+                                       (double)c.t, dcv, c.tab.mods)
+  BCN_DISPATCH_NS(level, BCN_DEC)
+#undef BCN_DEC
+  BCN_HIP(hipGetLastError());
+}
+
+void pointwise_mul(const Context& c, const double* a, const double* b, double* out, int n, const Basis& bs,
+                   bool b_shared, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_pointwise, dim3(nblocks((size_t)n * bs.n * c.n)), dim3(TPB), 0, s, a, b, out, n, bs.n, c.logn,
+                     b_shared ? 1 : 0, bs, c.tab.mods);
+  BCN_HIP(hipGetLastError());
+}
+
+void small_to_rns(const Context& c, const int8_t* e, double* out, int n, const Basis& b, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_small_to_rns, dim3(nblocks((size_t)n * b.n * c.n)), dim3(TPB), 0, s, e, out, n, b.n, c.logn, b,
+                     c.tab.mods);
+  BCN_HIP(hipGetLastError());
+}
+
+void add_inplace(const Context& c, double* a, const double* b, int npoly, int level, hipStream_t s) {
+  const size_t count = (size_t)npoly * level * c.n;
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_add_inplace, dim3(nblocks(count)), dim3(TPB), 0, s, a, b, count, level, c.logn, c.basis_Q(level),
+                     c.tab.mods);
+  BCN_HIP(hipGetLastError());
+}
+
+void u64_to_f64(const uint64_t* in, double* out, size_t count, hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_u64_to_f64, dim3(nblocks(count)), dim3(TPB), 0, s, in, out, count);
+  BCN_HIP(hipGetLastError());
+}
+
+void f64_to_u64(const double* in, uint64_t* out, size_t count, hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_f64_to_u64, dim3(nblocks(count)), dim3(TPB), 0, s, in, out, count);
+  BCN_HIP(hipGetLastError());
+}
+
+void combine_keypart(const Context& c, const double* x, const double* e, const double* sp, double* out, const Basis& b,
+                     int g_lo, int g_hi, const double* g_val_host, hipStream_t s) {
+  LimbConsts g{};
+  for (int i = 0; i < b.n; ++i) g.v[i] = g_val_host ? g_val_host[i] : 0.0;
+  hipLaunchKernelGGL(k_keypart, dim3(nblocks((size_t)b.n * c.n)), dim3(TPB), 0, s, x, e, sp, out, b.n, c.logn, g_lo,
+                     g_hi, g, b, c.tab.mods);
+  BCN_HIP(hipGetLastError());
+}
+
+void quantise_features(const Context& c, const float* f, int n_pt, int mode, int batch, int stride_b, const int* slot_of,
+                       int per, float scale, int clampv, int64_t* slots, hipStream_t s) {
+  const size_t work = mode == 0 ? (size_t)n_pt * batch : (size_t)n_pt * per;
+  if (work == 0) return;
+  hipLaunchKernelGGL(k_quantise, dim3(nblocks(work)), dim3(TPB), 0, s, f, n_pt, mode, batch, stride_b, slot_of, per,
+                     scale, clampv, slots, c.logn);
+  BCN_HIP(hipGetLastError());
+}
+
+}  // namespace bcn

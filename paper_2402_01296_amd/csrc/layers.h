@@ -1,0 +1,31 @@
+#pragma once
+
+#include "../../include/bcn.h"
+#include "scheme.h"
+
+namespace bcn {
+
+struct Layer {
+  int kind = 0, packing = 0, level = 0, level_out = 0;
+  int n_in = 0, n_out = 0;
+  int oh = 0, ow = 0, k2 = 0;
+  bool square = false, modsw = false, features = false;
+  float fscale = 8.0f;
+  int fclamp = 127;
+  int batch = 0, stride_b = 0;
+  MacPlan mac;
+  std::vector<int> steps;        // HW conv: nonzero tap offsets, tap index = position + 1
+  std::vector<int> all_steps;    // every Galois step the layer needs
+  double* mask_hat = nullptr;    // [level][N]
+  double* ptv_hat = nullptr;     // [n_out][n_in][level][N]
+  int* slot_of = nullptr;        // [per] output slot of each output position (HW)
+  int per = 0;
+  int span = 0;                  // rotate-and-sum span (0 = none)
+  ~Layer();
+};
+
+Layer* layer_create(Context& c, const bcn_layer_desc& d, int level);
+void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, double* out, const float* features,
+                hipStream_t s);
+
+}  // namespace bcn

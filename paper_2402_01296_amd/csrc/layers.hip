@@ -1,0 +1,216 @@
+// Layer lowering: HW- and batch-packed convolution / dense layers with the
+// mask, feature injection, square + relinearisation, modulus switch and
+// global sum epilogues (appendix "Implementation Details"; features enter as
+// in section "The unidirectional connections").
+#include <algorithm>
+#include <cstring>
+
+#include "../../include/bcn.h"
+#include "layers.h"
+
+namespace bcn {
+
+Layer::~Layer() {
+  free_mac_plan(mac);
+  if (mask_hat) (void)hipFree(mask_hat);
+  if (ptv_hat) (void)hipFree(ptv_hat);
+  if (slot_of) (void)hipFree(slot_of);
+}
+
+namespace {
+int next_pow2(int x) {
+  int s = 1;
+  while (s < x) s *= 2;
+  return s;
+}
+}  // namespace
+
+Layer* layer_create(Context& c, const bcn_layer_desc& d, int level) {
+  if (level < 1 || level > c.L) throw Error(-2, "bad level");
+  if (!d.weights) throw Error(-1, "layer weights missing");
+  if (d.in_c < 1 || d.in_h < 1 || d.in_w < 1 || d.out_c < 1) throw Error(-1, "bad layer shape");
+  auto L = std::make_unique<Layer>();
+  L->kind = d.kind;
+  L->packing = d.packing;
+  L->level = level;
+  L->square = d.square != 0;
+  L->modsw = d.square && d.modswitch && level >= 2;
+  L->level_out = L->modsw ? level - 1 : level;
+  L->features = d.has_features != 0;
+  L->fscale = d.feature_scale;
+  L->fclamp = d.feature_clamp;
+  const int N = c.n;
+  if (d.kind == BCN_CONV2D) {
+    if (d.k < 1 || d.stride < 1 || d.pad < 0) throw Error(-1, "bad convolution geometry");
+    L->oh = (d.in_h + 2 * d.pad - d.k) / d.stride + 1;
+    L->ow = (d.in_w + 2 * d.pad - d.k) / d.stride + 1;
+    if (L->oh < 1 || L->ow < 1) throw Error(-1, "convolution output is empty");
+  }
+  if (d.packing == BCN_PACK_BATCH) {
+    if (d.batch < 1 || d.batch > N) throw Error(-1, "batch must be 1..N");
+    L->batch = d.batch;
+    if (d.kind == BCN_CONV2D) {
+      L->n_in = d.in_c * d.in_h * d.in_w;
+      L->n_out = d.out_c * L->oh * L->ow;
+      std::vector<int32_t> W((size_t)L->n_out * L->n_in, 0);
+      for (int o = 0; o < d.out_c; ++o)
+        for (int i = 0; i < L->oh; ++i)
+          for (int j = 0; j < L->ow; ++j) {
+            const int row = (o * L->oh + i) * L->ow + j;
+            for (int ci = 0; ci < d.in_c; ++ci)
+              for (int di = 0; di < d.k; ++di)
+                for (int dj = 0; dj < d.k; ++dj) {
+                  const int y = d.stride * i + di - d.pad, x = d.stride * j + dj - d.pad;
+                  if (y < 0 || y >= d.in_h || x < 0 || x >= d.in_w) continue;
+                  W[(size_t)row * L->n_in + (ci * d.in_h + y) * d.in_w + x] =
+                      d.weights[((o * d.in_c + ci) * d.k + di) * d.k + dj];
+                }
+          }
+      L->mac = make_mac_plan(c, W, L->n_out, L->n_in);
+    } else {
+      L->n_in = d.in_c * d.in_h * d.in_w;
+      L->n_out = d.out_c;
+      std::vector<int32_t> W(d.weights, d.weights + (size_t)L->n_out * L->n_in);
+      L->mac = make_mac_plan(c, W, L->n_out, L->n_in);
+    }
+    L->stride_b = L->n_out;
+    if (d.sum) throw Error(-1, "global sum needs HW packing");
+    return L.release();
+  }
+  if (d.packing != BCN_PACK_HW) throw Error(-1, "unknown packing");
+  if (d.row < 1 || d.pos_stride < 1) throw Error(-1, "HW packing needs row and pos_stride");
+  const int half = N / 2;
+  L->n_in = d.in_c;
+  L->n_out = d.out_c;
+  auto slot = [&](int ps, int y, int x) { return ps * (d.row * y + x); };
+  if (d.kind == BCN_CONV2D) {
+    if (d.pad != 0) throw Error(-1, "HW convolution is valid (pad 0)");
+    const int k2 = d.k * d.k;
+    // taps: index 0 = offset 0 (the input itself), then the nonzero offsets in (di, dj) order
+    std::vector<int> tap_of(k2);
+    for (int di = 0; di < d.k; ++di)
+      for (int dj = 0; dj < d.k; ++dj) {
+        const int off = slot(d.pos_stride, di, dj);
+        if (off >= half) throw Error(-1, "rotation offset beyond the slot row");
+        if (off == 0) {
+          tap_of[di * d.k + dj] = 0;
+        } else {
+          L->steps.push_back(off);
+          tap_of[di * d.k + dj] = (int)L->steps.size();
+        }
+      }
+    if ((int)L->steps.size() != k2 - 1) throw Error(-1, "duplicate convolution offsets");
+    L->k2 = k2;
+    std::vector<int32_t> W((size_t)d.out_c * d.in_c * k2, 0);
+    for (int o = 0; o < d.out_c; ++o)
+      for (int ci = 0; ci < d.in_c; ++ci)
+        for (int t = 0; t < k2; ++t)
+          W[(size_t)o * d.in_c * k2 + ci * k2 + tap_of[t]] = d.weights[(o * d.in_c + ci) * k2 + t];
+    L->mac = make_mac_plan(c, W, d.out_c, d.in_c * k2);
+    // valid output slots and their mask
+    const int ops = d.pos_stride * d.stride;
+    std::vector<int> so;
+    for (int i = 0; i < L->oh; ++i)
+      for (int j = 0; j < L->ow; ++j) so.push_back(slot(ops, i, j));
+    const int maxs = *std::max_element(so.begin(), so.end());
+    if (maxs >= half) throw Error(-1, "output positions beyond the slot row");
+    std::vector<int64_t> mask(N, 0);
+    for (int v : so) mask[v] = 1;
+    BCN_HIP(hipMalloc(&L->mask_hat, (size_t)level * N * sizeof(double)));
+    c.arena->reset();
+    encode_plain_ntt(c, mask.data(), 1, level, L->mask_hat, nullptr);
+    L->per = (int)so.size();
+    BCN_HIP(hipMalloc(&L->slot_of, so.size() * sizeof(int)));
+    BCN_HIP(hipMemcpy(L->slot_of, so.data(), so.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (d.sum) {
+      L->span = next_pow2(maxs + 1);
+      if (L->span > half) throw Error(-1, "sum span beyond the slot row");
+      for (int r = L->span / 2; r >= 1; r /= 2) L->all_steps.push_back(r);
+    }
+  } else {
+    // dense over spatially laid out channels: weight vectors, then rotate-and-sum
+    const int per = d.in_h * d.in_w;
+    std::vector<int> si;
+    for (int y = 0; y < d.in_h; ++y)
+      for (int x = 0; x < d.in_w; ++x) si.push_back(slot(d.pos_stride, y, x));
+    const int maxs = *std::max_element(si.begin(), si.end());
+    if (maxs >= half) throw Error(-1, "input positions beyond the slot row");
+    std::vector<int64_t> vec((size_t)d.out_c * d.in_c * N, 0);
+    for (int o = 0; o < d.out_c; ++o)
+      for (int ci = 0; ci < d.in_c; ++ci)
+        for (int p = 0; p < per; ++p)
+          vec[((size_t)o * d.in_c + ci) * N + si[p]] = d.weights[(size_t)o * d.in_c * per + ci * per + p];
+    BCN_HIP(hipMalloc(&L->ptv_hat, (size_t)d.out_c * d.in_c * level * N * sizeof(double)));
+    c.arena->reset();
+    encode_plain_ntt(c, vec.data(), d.out_c * d.in_c, level, L->ptv_hat, nullptr);
+    L->span = next_pow2(maxs + 1);
+    if (L->span < 2) L->span = 2;
+    for (int r = L->span / 2; r >= 1; r /= 2) L->all_steps.push_back(r);
+    if (d.has_features) throw Error(-1, "features are supported on convolutions");
+  }
+  for (int st : L->steps) L->all_steps.push_back(st);
+  std::sort(L->all_steps.begin(), L->all_steps.end());
+  L->all_steps.erase(std::unique(L->all_steps.begin(), L->all_steps.end()), L->all_steps.end());
+  return L.release();
+}
+
+void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, double* out, const float* features,
+                hipStream_t s) {
+  Arena& ar = *c.arena;
+  const size_t N = c.n;
+  const int level = L.level;
+  const size_t ctw = (size_t)2 * level * N;
+  if (L.features && !features) throw Error(-1, "layer expects features");
+  const bool direct = !L.square && !L.features && L.span == 0 && L.packing == BCN_PACK_BATCH;
+  double* A = direct ? out : ar.take((size_t)L.n_out * ctw);
+  if (L.packing == BCN_PACK_BATCH) {
+    mac(c, L.mac, in, A, level, s);
+  } else if (L.kind == BCN_CONV2D) {
+    // taps [n_in][k2]: tap 0 = input, taps 1.. = hoisted rotations
+    double* taps = ar.take((size_t)L.n_in * L.k2 * ctw);
+    BCN_HIP(hipMemcpy2DAsync(taps, L.k2 * ctw * sizeof(double), in, ctw * sizeof(double), ctw * sizeof(double), L.n_in,
+                             hipMemcpyDeviceToDevice, s));
+    rotate_hoisted(c, ek, in, L.n_in, level, L.steps, taps + ctw, s, (int)L.steps.size(), L.k2 * ctw);
+    mac(c, L.mac, taps, A, level, s);
+    ntt_forward(c, A, 2 * L.n_out, c.basis_Q(level), s);
+    mul_plain_ntt(c, A, A, L.n_out, level, L.mask_hat, false, s);
+    ntt_inverse(c, A, 2 * L.n_out, c.basis_Q(level), s);
+  } else {
+    double* H = ar.take((size_t)L.n_in * ctw);
+    BCN_HIP(hipMemcpyAsync(H, in, (size_t)L.n_in * ctw * sizeof(double), hipMemcpyDeviceToDevice, s));
+    ntt_forward(c, H, 2 * L.n_in, c.basis_Q(level), s);
+    ptvec_mac_ntt(c, H, L.n_in, A, L.n_out, level, L.ptv_hat, s);
+    ntt_inverse(c, A, 2 * L.n_out, c.basis_Q(level), s);
+  }
+  if (L.features) {
+    int64_t* sl = reinterpret_cast<int64_t*>(ar.take((size_t)L.n_out * N));
+    BCN_HIP(hipMemsetAsync(sl, 0, (size_t)L.n_out * N * sizeof(int64_t), s));
+    if (L.packing == BCN_PACK_BATCH)
+      quantise_features(c, features, L.n_out, 0, L.batch, L.stride_b, nullptr, 0, L.fscale, L.fclamp, sl, s);
+    else
+      quantise_features(c, features, L.n_out, 1, 0, 0, L.slot_of, L.per, L.fscale, L.fclamp, sl, s);
+    double* m = ar.take((size_t)L.n_out * N);
+    encode_device(c, sl, m, L.n_out, s);
+    add_delta(c, A, L.n_out, level, m, s);
+  }
+  if (direct) return;
+  const bool hw_dense = L.packing == BCN_PACK_HW && L.kind == BCN_DENSE;
+  if (hw_dense) {
+    // rotate-and-sum before the (optional) square
+    rotate_sum(c, ek, A, L.n_out, level, L.span, s);
+    if (L.square) {
+      square_relin(c, ek, A, out, L.n_out, level, L.modsw, s);
+    } else {
+      BCN_HIP(hipMemcpyAsync(out, A, (size_t)L.n_out * ctw * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    return;
+  }
+  if (L.square) {
+    square_relin(c, ek, A, out, L.n_out, level, L.modsw, s);
+  } else {
+    BCN_HIP(hipMemcpyAsync(out, A, (size_t)L.n_out * ctw * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  if (L.span > 0) rotate_sum(c, ek, out, L.n_out, L.level_out, L.span, s);
+}
+
+}  // namespace bcn

@@ -1,0 +1,58 @@
+// Scheme-level objects and operations built from the kernels.
+#pragma once
+
+#include "internal.h"
+
+namespace bcn {
+
+struct SecretKey {
+  const Context* ctx = nullptr;
+  double* s_hat = nullptr;    // [L+K][N] transform of s over Q then P
+  double* s_coef = nullptr;   // [L+K][N] residues of s
+  ~SecretKey();
+};
+
+struct KeyTable {
+  const double** keys = nullptr;  // device
+  int* galois = nullptr;          // device
+  int* kinv = nullptr;            // device
+  int nk = 0;
+};
+
+struct EvalKeys {
+  const Context* ctx = nullptr;
+  double* relin = nullptr;                 // [dnum][2][L+K][N], transform domain
+  std::map<int, double*> rot;              // step -> key
+  std::map<std::vector<int>, KeyTable> tables;
+  ~EvalKeys();
+  size_t key_doubles() const;
+  const double* rot_key(int step) const;
+  const KeyTable& table(const std::vector<int>& steps);   // cached device arrays for a step list
+};
+
+int galois_element(const Context& c, int step);
+int galois_inverse(const Context& c, int k);
+
+SecretKey* secret_key_create(Context& c, const int8_t* s_host);
+void keygen(Context& c, const SecretKey& sk, EvalKeys& ek, int kind, int step, const uint64_t* a_host,
+            const int8_t* e_host, hipStream_t s);
+void encrypt(Context& c, const SecretKey& sk, const int64_t* slots_host, const uint64_t* a_host, const int8_t* e_host,
+             int n, int level, double* ct, hipStream_t s);
+void decrypt(Context& c, const SecretKey& sk, const double* ct, int n, int level, int64_t* slots_host, hipStream_t s);
+
+// m [n][N] in [0, t) from slot vectors already on the device (int64 [n][N])
+void encode_device(Context& c, const int64_t* slots_dev, double* m, int n, hipStream_t s);
+// NTT over Q_level of lift_c(encode(slots)) for host slot vectors [n][N] -> out [n][level][N]
+void encode_plain_ntt(Context& c, const int64_t* slots_host, int n, int level, double* out, hipStream_t s);
+
+void square_relin(Context& c, const EvalKeys& ek, const double* in, double* out, int n, int level, bool modsw,
+                  hipStream_t s);
+// out placement as in moddown (out_div = 0: contiguous [n_in][n_steps])
+void rotate_hoisted(Context& c, EvalKeys& ek, const double* in, int n_in, int level, const std::vector<int>& steps,
+                    double* out, hipStream_t s, int out_div = 0, size_t out_outer = 0);
+void rotate_sum(Context& c, const EvalKeys& ek, double* ct, int n, int level, int span, hipStream_t s);
+
+MacPlan make_mac_plan(const Context& c, const std::vector<int32_t>& w, int n_out, int n_in);
+void free_mac_plan(MacPlan& p);
+
+}  // namespace bcn

@@ -1,0 +1,147 @@
+"""Drives a synthetic workload through the HIP library: keys, encryption,
+layer-by-layer evaluation of the ciphertext branch, decryption.
+
+Slot layouts (client-side data placement):
+  batch packing: one ciphertext per crop pixel (c, y, x); slot b = image b.
+  HW packing: one ciphertext per channel; crop pixel (y, x) at slot row*y + x
+  of slot row 0, with row the crop width.
+Every homomorphic step is a call into libbcn.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import synthetic
+from synthetic import workloads as W
+
+from . import bcn
+
+
+def layer_descs(name: str):
+    """Layer descriptions of a workload's ciphertext branch (dicts for bcn.Layer)."""
+    wl = W.WORKLOADS[name]
+    shapes = W.layer_shapes(name)
+    hw = wl["packing"] == "hw"
+    row = wl["crop"][1]
+    ps = 1
+    spatial = True
+    out = []
+    for li, lay in enumerate(wl["layers"]):
+        (inp, outp) = shapes[li]
+        d = dict(square=lay["square"], modswitch=lay["square"], batch=wl["batch"])
+        if lay["kind"] == "conv":
+            c, h, w = inp
+            d.update(kind=bcn.BCN_CONV2D, packing=bcn.BCN_PACK_HW if hw else bcn.BCN_PACK_BATCH,
+                     in_c=c, in_h=h, in_w=w, out_c=lay["out"], k=lay["k"], stride=lay["stride"],
+                     pad=lay["pad"], row=row, pos_stride=ps, features=lay.get("features", False),
+                     sum=lay.get("sum", False))
+            if hw:
+                ps *= lay["stride"]
+                if lay.get("sum"):
+                    spatial = False
+        else:
+            if hw and spatial:
+                c, h, w = shapes[li - 1][1]
+                d.update(kind=bcn.BCN_DENSE, packing=bcn.BCN_PACK_HW, in_c=c, in_h=h, in_w=w,
+                         out_c=lay["out"], row=row, pos_stride=ps)
+                spatial = False
+            else:
+                d.update(kind=bcn.BCN_DENSE, packing=bcn.BCN_PACK_BATCH, in_c=inp[0], in_h=1, in_w=1,
+                         out_c=lay["out"], batch=max(1, wl["batch"]))
+        out.append(d)
+    return out
+
+
+class GpuSession:
+    """Keys, encryptions and evaluation of one workload on the GPU."""
+
+    def __init__(self, name: str, seeds=None, device: int = 0):
+        import torch
+        self.torch = torch
+        self.name = name
+        self.wl = W.WORKLOADS[name]
+        self.seeds = dict(W.SEEDS if seeds is None else seeds)
+        spec = W.PARAMS[self.wl["params"]]
+        self.ctx = bcn.Context(spec["n"], spec["bits"], spec["L"], spec["K"], spec["alpha"], spec["t"], device)
+        n = spec["n"]
+        self.n = n
+        self.s = synthetic.ternary_secret(self.seeds["keys"], n)
+        self.sk = self.ctx.secret_key(self.s)
+        self.ek = self.ctx.eval_keys()
+        self.inputs = W.make_inputs(name, self.seeds)
+        self.descs = layer_descs(name)
+        for d, w in zip(self.descs, self.inputs["weights"]):
+            d["weights"] = w
+        self.layers = []
+        level = self.ctx.L
+        for d in self.descs:
+            lay = self.ctx.layer(d, level)
+            self.layers.append(lay)
+            level = lay.level_out
+        self.features = []
+        for li, f in enumerate(self.inputs["features"]):
+            if f is None:
+                self.features.append(None)
+            elif self.wl["packing"] == "batch":
+                self.features.append(torch.from_numpy(np.ascontiguousarray(f.reshape(f.shape[0], -1))).cuda())
+            else:
+                self.features.append(torch.from_numpy(np.ascontiguousarray(f)).cuda())
+        self.steps = sorted({s for lay in self.layers for s in lay.steps})
+        self._keygen()
+
+    def key_randomness(self, key_id: int):
+        moduli = self.ctx.q + self.ctx.p_primes
+        d = self.ctx.dnum()
+        a = np.stack([synthetic.uniform_residues(self.seeds["keys"], "ksk_a", (key_id, j), moduli, self.n)
+                      for j in range(d)])
+        e = np.stack([synthetic.gaussian_error(self.seeds["keys"], "ksk_e", (key_id, j), self.n) for j in range(d)])
+        return a, e
+
+    def _keygen(self):
+        a, e = self.key_randomness(W.RELIN_KEY_ID)
+        self.ctx.keygen(self.sk, self.ek, bcn.BCN_KEY_RELIN, 0, a, e)
+        for r in self.steps:
+            a, e = self.key_randomness(W.rotation_key_id(r))
+            self.ctx.keygen(self.sk, self.ek, bcn.BCN_KEY_ROTATION, r, a, e)
+
+    # ------------------------------------------------------------ inputs
+    def input_slots(self) -> np.ndarray:
+        wl, n = self.wl, self.n
+        y0, size = wl["crop"]
+        crop = self.inputs["images"][:, :, y0:y0 + size, y0:y0 + size].astype(np.int64)
+        if wl["packing"] == "batch":
+            b = crop.shape[0]
+            flat = crop.reshape(b, -1).T
+            out = np.zeros((flat.shape[0], n), dtype=np.int64)
+            out[:, :b] = flat
+            return out
+        c = crop.shape[1]
+        out = np.zeros((c, n), dtype=np.int64)
+        for ch in range(c):
+            out[ch, :size * size] = crop[0, ch].reshape(-1)
+        return out
+
+    def encryption_randomness(self, indices, level=None):
+        level = self.ctx.L if level is None else level
+        q = self.ctx.q[:level]
+        a = np.stack([synthetic.uniform_residues(self.seeds["enc"], "enc_a", (i,), q, self.n) for i in indices])
+        e = np.stack([synthetic.gaussian_error(self.seeds["enc"], "enc_e", (i,), self.n) for i in indices])
+        return a, e
+
+    def encrypt_inputs(self):
+        slots = self.input_slots()
+        a, e = self.encryption_randomness(range(len(slots)))
+        return self.ctx.encrypt(self.sk, slots, a, e)
+
+    # ------------------------------------------------------------ evaluation
+    def run(self, ct, upto=None):
+        """Evaluates the layers (all, or the first ``upto``); returns the last output batch."""
+        for li, lay in enumerate(self.layers[:upto]):
+            ct = lay(self.ek, ct, self.features[li])
+        return ct
+
+    def output_values(self, ct) -> np.ndarray:
+        vals = self.ctx.decrypt(self.sk, ct)
+        if self.wl["packing"] == "batch":
+            return vals[:, :self.wl["batch"]].T
+        return vals[:, 0][None, :]

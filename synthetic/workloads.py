@@ -17,6 +17,30 @@ from __future__ import annotations
 
 SEEDS = dict(keys=1, enc=2, weights=3, images=4, features=5)
 
+# Parameter sets: ring degree, prime size, ciphertext primes L, special primes
+# K, primes per key-switching digit, plaintext modulus t.
+PARAMS = {
+    # the three workloads
+    "cfg1": dict(n=4096, bits=30, L=2, K=1, alpha=1, t=65537),
+    "cfg2": dict(n=8192, bits=36, L=4, K=1, alpha=1, t=1032193),
+    "cfg3": dict(n=16384, bits=40, L=6, K=2, alpha=2, t=65537),
+    # workload 1 with five primes so that its output still decrypts (insecure)
+    "cfg1d": dict(n=4096, bits=30, L=5, K=1, alpha=1, t=65537, insecure=True),
+    # reduced sizes for tests the oracle finishes in seconds (insecure)
+    "t1k": dict(n=1024, bits=36, L=3, K=1, alpha=1, t=65537, insecure=True),
+    "t2k": dict(n=2048, bits=40, L=4, K=2, alpha=2, t=65537, insecure=True),
+    "t1k5": dict(n=1024, bits=30, L=5, K=1, alpha=1, t=65537, insecure=True),
+    "t2k3": dict(n=2048, bits=40, L=6, K=2, alpha=2, t=65537, insecure=True),
+    "t4k": dict(n=4096, bits=36, L=4, K=1, alpha=1, t=40961, insecure=True),
+}
+
+# key ids of the key-switching-key randomness streams
+RELIN_KEY_ID = 0
+
+
+def rotation_key_id(step: int) -> int:
+    return 1000 + step
+
 WORKLOADS = {
     # one 28x28 image, HW packing, central 12x12 crop
     "cfg1": dict(params="cfg1", packing="hw", batch=1, image=(1, 28, 28), crop=(8, 12),

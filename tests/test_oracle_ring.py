@@ -44,6 +44,7 @@ def test_negacyclic_root_is_smallest_primitive():
         assert pow(psi, 2 * n, q) == 1
         for x in range(2, psi):
             assert pow(x, n, q) != q - 1
+        assert psi == nt.negacyclic_root_search(q, n)
 
 
 def test_crt_and_centered():
