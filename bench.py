@@ -1,0 +1,278 @@
+#!/usr/bin/env python3
+"""Throughput of the encrypted ciphertext branch of bi-CryptoNets on one MI355X.
+
+A step is one homomorphic evaluation of the whole ciphertext branch over one
+batch: for the default workload (MNIST-shaped slot-batched inference: N=8192,
+four 36-bit primes, t=1032193, 8192 images, one image per slot, 16x16
+sensitive crop) that is conv 5x5/2 (5 maps) + feature injection + square +
+relinearisation + modulus switch, dense 100 + square + relinearisation +
+modulus switch, dense 10.  Inputs (ciphertexts, features, keys) are resident
+in HBM before the timed region.
+
+Prints one JSON line.  `value` is encrypted inferences (images) per second.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD_TEXT = {
+    "cfg2": "MNIST-shaped slot-batched inference: N=8192, 4x36-bit primes, t=1032193, 8192 images/batch, "
+            "conv5x5s2(5)+features+square, dense100+square, dense10",
+    "cfg1": "tiny HW-packed branch: N=4096, 2x30-bit primes, t=65537, one 28x28 image",
+    "cfg3": "CIFAR-shaped HW-packed branch: N=16384, 6x40-bit primes, dnum=3, one 32x32x3 image",
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (for HBM counter scaling)")
+    ap.add_argument("--kernel", choices=["ntt"], default=None,
+                    help="microbenchmark one kernel on the workload's shapes instead of the whole step")
+    return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 27                                   # 1 GiB of float64
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
+
+
+def ntt_microbench(args):
+    """Forward + inverse transforms of the square's batch shape (limbs over Q + aux primes)."""
+    import numpy as np
+    import torch
+
+    from paper_2402_01296_amd import bcn
+    from synthetic import workloads as W
+    spec = W.PARAMS[W.WORKLOADS[args.workload]["params"]]
+    ctx = bcn.Context(spec["n"], spec["bits"], spec["L"], spec["K"], spec["alpha"], spec["t"])
+    tuning = None if args.no_autotune else ctx.autotune()
+    nl = ctx.n_q + ctx.n_aux
+    polys = 490                                   # 245 ciphertexts x 2 parts, as in the first square
+    x = torch.zeros((polys, nl, spec["n"]), dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        ctx.ntt(x, 0)
+        ctx.ntt(x, 0, inverse=True)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.ntt(x, 0)
+        ctx.ntt(x, 0, inverse=True)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    ctx.profile(False)
+    prof = ctx.profile_read()
+    limb_ntts = 2 * polys * nl * args.steps
+    out = {"kernel": "ntt", "n": spec["n"], "limbs_per_launch": polys * nl, "steps": args.steps,
+           "limb_ntts_per_s": limb_ntts / total, "tuning": tuning}
+    for k, (la, ms, by) in prof.items():
+        out[k] = {"launches": la, "avg_launch_us": ms * 1000.0 / la, "gbs": by / (ms * 1e-3) / 1e9,
+                  "frac_of_hbm_peak": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(workload: str):
+    """The oracle on a bounded sample of one step, scaled to inferences/s.
+
+    Sample: one output ciphertext of each layer (conv output with its feature
+    add, square, relinearisation and modulus switch; one dense-100 output with
+    its square and modulus switch; one dense-10 output), on random ciphertexts
+    of the right level.  The step time is the sum of each sample times the
+    number of outputs of its layer (245, 100, 10).
+    """
+    import numpy as np
+
+    import synthetic
+    from oracle import bfv, network, programs
+    from synthetic import workloads as W
+
+    assert workload == "cfg2"
+    t_all = time.perf_counter()
+    O = programs.OracleSession(workload, with_galois=False)
+    prm = O.prm
+
+    def rand_cts(level, count, seed):
+        out = []
+        for i in range(count):
+            r0 = synthetic.test_poly(seed, 2 * i, prm.q[:level], prm.n)
+            r1 = synthetic.test_poly(seed, 2 * i + 1, prm.q[:level], prm.n)
+            out.append(bfv.Ct(bfv.from_rns(r0, prm.q[:level]), bfv.from_rns(r1, prm.q[:level]), level))
+        return out
+
+    w = O.inputs["weights"]
+    # layer 1: output (0, 3, 3), 25 taps
+    cts = rand_cts(prm.L, 25, 101)
+    t0 = time.perf_counter()
+    ct = bfv.mac(prm, cts, w[0][0, 0].reshape(-1))
+    fq = network.quantise(O.inputs["features"][0])[:, 0, 3, 3]
+    ct = bfv.add_plain(prm, ct, O.enc.encode(fq))
+    ct = bfv.modswitch(prm, bfv.square(prm, ct, O.rk))
+    t1 = time.perf_counter() - t0
+    # layer 2: one of 100 outputs over 245 inputs at level L-1
+    cts = rand_cts(prm.L - 1, 245, 102)
+    t0 = time.perf_counter()
+    ct = bfv.mac(prm, cts, w[1][0])
+    ct = bfv.modswitch(prm, bfv.square(prm, ct, O.rk))
+    t2 = time.perf_counter() - t0
+    # layer 3: one of 10 outputs over 100 inputs at level L-2
+    cts = rand_cts(prm.L - 2, 100, 103)
+    t0 = time.perf_counter()
+    ct = bfv.mac(prm, cts, w[2][0])
+    t3 = time.perf_counter() - t0
+    shapes = W.layer_shapes(workload)
+    n1 = shapes[0][1][0] * shapes[0][1][1] * shapes[0][1][2]
+    n2, n3 = shapes[1][1][0], shapes[2][1][0]
+    step_s = n1 * t1 + n2 * t2 + n3 * t3
+    batch = W.WORKLOADS[workload]["batch"]
+    return {
+        "value": batch / step_s,
+        "unit": "encrypted inferences/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": "one output ciphertext per layer on random ciphertexts (layer1 %.2fs, layer2 %.2fs, layer3 %.2fs), "
+                  "scaled by the outputs per layer (%d, %d, %d) to one step of %d images: %.0f s/step; "
+                  "wall time incl. setup %.1fs" % (t1, t2, t3, n1, n2, n3, batch, step_s,
+                                                   time.perf_counter() - t_all),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.kernel == "ntt":
+        ntt_microbench(args)
+        return
+    from paper_2402_01296_amd.workload import GpuSession
+    from synthetic import workloads as W
+
+    wl = W.WORKLOADS[args.workload]
+    g = GpuSession(args.workload)
+    tuning = None if args.no_autotune else g.autotune()
+    ct_in = g.encrypt_inputs()
+    torch.cuda.synchronize()
+    print("bench: %s keys+encryption ready, %d input ciphertexts" % (args.workload, ct_in.shape[0]),
+          file=sys.stderr, flush=True)
+
+    def step():
+        return g.run(ct_in)
+
+    for _ in range(args.warmup):
+        out = step()
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record()
+        out = step()
+        ends[i].record()
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    lat = sorted(s.elapsed_time(e) for s, e in zip(starts, ends))
+    ms_per_step = total * 1000.0 / args.steps
+    batch = wl["batch"]
+    value = batch * args.steps / total
+    print("bench: timed %d steps, %.3f ms/step" % (args.steps, ms_per_step), file=sys.stderr, flush=True)
+
+    # instrumented pass over the same steps: per-kernel launch durations on the launch stream
+    g.ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = step()
+    torch.cuda.synchronize()
+    inst_ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+    g.ctx.profile(False)
+    prof = g.ctx.profile_read()
+    kern = {k: dict(launches=v[0], ms=v[1], bytes=v[2], gbs=(v[2] / (v[1] * 1e-3) / 1e9) if v[1] > 0 else 0.0)
+            for k, v in prof.items()}
+    dom = max(kern, key=lambda k: kern[k]["ms"])
+    d = kern[dom]
+    achieved = d["gbs"]
+    ntt_bytes = sum(kern[k]["bytes"] for k in kern if k.startswith("ntt"))
+    ntt_ms = sum(kern[k]["ms"] for k in kern if k.startswith("ntt"))
+    roof = {
+        "kernel": dom,
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "launches": d["launches"],
+        "avg_launch_us": round(d["ms"] * 1000.0 / max(1, d["launches"]), 2),
+        "bytes_per_launch": d["bytes"] / max(1, d["launches"]),
+    }
+    verified = None
+    if not args.no_verify:
+        from oracle import network   # test-only check of this run's outputs
+        vals = g.output_values(out)
+        want = network.run_mod_t(args.workload, g.inputs, g.ctx.t)
+        verified = bool((vals == want).all())
+    line = {
+        "metric": "encrypted inferences/sec + p50/p99 latency; NTT HBM GB/s vs peak",
+        "value": round(value, 1),
+        "unit": "encrypted inferences/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT.get(args.workload, args.workload), "name": args.workload,
+                   "n": g.n, "limbs": g.ctx.L, "batch": batch, "requests_per_s": round(args.steps / total, 3)},
+        "latency_ms": {"p50": round(statistics.median(lat), 3),
+                       "p99": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 3)},
+        "ntt": {"gbs": round(ntt_bytes / (ntt_ms * 1e-3) / 1e9, 1) if ntt_ms else None,
+                "frac_of_peak": round(ntt_bytes / (ntt_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ntt_ms else None,
+                "ms_per_step": round(ntt_ms / args.steps, 3)},
+        "roofline": roof,
+        "kernels": {k: {"ms_per_step": round(v["ms"] / args.steps, 3), "launches": v["launches"],
+                        "gbs": round(v["gbs"], 1)} for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])},
+        "instrumented_ms_per_step": round(inst_ms, 3),
+        "autotune": [ln for ln in (tuning or "").splitlines() if "chosen" in ln],
+        "verified_vs_integer_network": verified,
+    }
+    if not args.no_cpu_baseline and args.workload == "cfg2":
+        print("bench: timing the oracle sample on the host", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -202,6 +202,29 @@ int bcn_layer_shape(const bcn_layer* layer, int* n_in, int* n_out, int* level_ou
 int bcn_layer_eval(bcn_context* ctx, const bcn_eval_keys* ek, const bcn_layer* layer, const double* in,
                    double* out, const float* features, bcn_stream stream);
 
+/* ---- tuning ---- */
+/* Times the candidate transform shapes (registers per thread, hence LDS passes
+ * per transform) on this device and keeps the fastest for the context.  A text
+ * report of the timings is written to report[cap] (may be NULL).  Results are
+ * unaffected: every shape computes the same exact transform. */
+int bcn_autotune(bcn_context* ctx, char* report, int cap, bcn_stream stream);
+/* Times the layer's multiply-accumulate with each candidate output-tile size and
+ * keeps the fastest (exact for every tile size). */
+int bcn_layer_autotune(bcn_context* ctx, bcn_layer* layer, char* report, int cap, bcn_stream stream);
+
+/* ---- measurement ---- */
+/* While enabled, launches of the main kernels are bracketed by hipEvents on
+ * their stream and their algorithmic HBM bytes are accumulated per kernel
+ * name (ntt_forward, ntt_inverse, mac, extend_qb, scale_round, modup,
+ * ks_inner, moddown, tensor_square). */
+int bcn_profile_enable(bcn_context* ctx, int on);
+/* Resolves and clears the recorded timings (synchronises their events).  Writes
+ * newline-separated kernel names into names[names_cap] and, per name, the launch
+ * count, summed launch time (ms) and algorithmic bytes into the arrays (cap
+ * entries).  Returns the number of names, or an error code. */
+int bcn_profile_read(bcn_context* ctx, char* names, int names_cap, int* launches, double* total_ms, double* bytes,
+                     int cap);
+
 #ifdef __cplusplus
 }
 #endif

@@ -72,6 +72,10 @@ _SIGS = {
     "bcn_layer_rotation_steps": (_I, [_VP, _I32P, _I]),
     "bcn_layer_shape": (_I, [_VP, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)]),
     "bcn_layer_eval": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "bcn_profile_enable": (_I, [_VP, _I]),
+    "bcn_autotune": (_I, [_VP, C.c_char_p, _I, _VP]),
+    "bcn_layer_autotune": (_I, [_VP, _VP, C.c_char_p, _I, _VP]),
+    "bcn_profile_read": (_I, [_VP, C.c_char_p, _I, _VP, _VP, _VP, _I]),
 }
 
 
@@ -258,6 +262,34 @@ class Context:
 
     def layer(self, desc: dict, level: int):
         return Layer(self, desc, level)
+
+    def autotune(self):
+        buf = C.create_string_buffer(4096)
+        _check(lib().bcn_autotune(self.h, buf, 4096, _stream()))
+        return buf.value.decode()
+
+    def autotune_layer(self, layer):
+        buf = C.create_string_buffer(4096)
+        _check(lib().bcn_layer_autotune(self.h, layer.h, buf, 4096, _stream()))
+        return buf.value.decode()
+
+    # ------------------------------------------------------------ measurement
+    def profile(self, on: bool):
+        _check(lib().bcn_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self):
+        """{kernel: (launches, total_ms, algorithmic_bytes)} since the last read."""
+        cap = 64
+        names = C.create_string_buffer(4096)
+        la = np.zeros(cap, dtype=np.int32)
+        ms = np.zeros(cap, dtype=np.float64)
+        by = np.zeros(cap, dtype=np.float64)
+        cnt = lib().bcn_profile_read(self.h, names, 4096, la.ctypes.data_as(C.c_void_p),
+                                     ms.ctypes.data_as(C.c_void_p), by.ctypes.data_as(C.c_void_p), cap)
+        if cnt < 0:
+            _check(cnt)
+        keys = names.value.decode().split("\n")[:cnt]
+        return {k: (int(la[i]), float(ms[i]), float(by[i])) for i, k in enumerate(keys)}
 
 
 class SecretKey:

@@ -376,6 +376,70 @@ int bcn_modswitch(bcn_context* ctx, const double* in, double* out, int n, int le
   });
 }
 
+int bcn_autotune(bcn_context* ctx, char* report, int cap, bcn_stream stream) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    const std::string r = bcn::autotune_ntt(c, (hipStream_t)stream);
+    if (report && cap > 0) {
+      std::strncpy(report, r.c_str(), (size_t)cap - 1);
+      report[cap - 1] = 0;
+    }
+  });
+}
+
+int bcn_layer_autotune(bcn_context* ctx, bcn_layer* layer, char* report, int cap, bcn_stream stream) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    check_ptr(layer, "layer");
+    const std::string r = bcn::autotune_layer_mac(c, *layer->l, (hipStream_t)stream);
+    if (report && cap > 0) {
+      std::strncpy(report, r.c_str(), (size_t)cap - 1);
+      report[cap - 1] = 0;
+    }
+  });
+}
+
+int bcn_profile_enable(bcn_context* ctx, int on) {
+  return guard([&] {
+    if (!ctx || !ctx->c) throw bcn::Error(BCN_ERR_INVALID, "null context");
+    ctx->c->prof = on != 0;
+  });
+}
+
+int bcn_profile_read(bcn_context* ctx, char* names, int names_cap, int* launches, double* total_ms, double* bytes,
+                     int cap) {
+  int count = 0;
+  int rc = guard([&] {
+    if (!ctx || !ctx->c) throw bcn::Error(BCN_ERR_INVALID, "null context");
+    bcn::Context& c = *ctx->c;
+    std::string joined;
+    for (auto& kv : c.prof_data) {
+      double ms = 0;
+      for (auto& pr : kv.second.ev) {
+        BCN_HIP(hipEventSynchronize(pr.second));
+        float x = 0;
+        BCN_HIP(hipEventElapsedTime(&x, pr.first, pr.second));
+        ms += x;
+        c.event_pool.push_back(pr.first);
+        c.event_pool.push_back(pr.second);
+      }
+      if (count < cap) {
+        launches[count] = (int)kv.second.launches;
+        total_ms[count] = ms;
+        bytes[count] = kv.second.bytes;
+      }
+      joined += kv.first + "\n";
+      ++count;
+    }
+    c.prof_data.clear();
+    if (names && names_cap > 0) {
+      std::strncpy(names, joined.c_str(), (size_t)names_cap - 1);
+      names[names_cap - 1] = 0;
+    }
+  });
+  return rc < 0 ? rc : count;
+}
+
 int bcn_layer_create(bcn_context* ctx, const bcn_layer_desc* desc, int level, bcn_layer** out) {
   return guard([&] {
     bcn::Context& c = ctxof(ctx);

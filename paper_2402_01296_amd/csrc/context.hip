@@ -2,6 +2,7 @@
 // conversion constants and the scratch arena.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 
@@ -53,6 +54,33 @@ double* Arena::take(size_t doubles) {
   used_total_ += doubles;
   high_ = std::max(high_, used_total_);
   return p;
+}
+
+hipEvent_t Context::get_event() const {
+  if (!event_pool.empty()) {
+    hipEvent_t e = event_pool.back();
+    event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  BCN_HIP(hipEventCreate(&e));
+  return e;
+}
+
+ProfScope::ProfScope(const Context& c, const char* name, hipStream_t s, double bytes) : c_(c), s_(s) {
+  if (!c.prof) return;
+  e_ = &c.prof_data[name];
+  start_ = c.get_event();
+  BCN_HIP(hipEventRecord(start_, s));
+  e_->bytes += bytes;
+  e_->launches += 1;
+}
+
+ProfScope::~ProfScope() {
+  if (!e_) return;
+  hipEvent_t stop = c_.get_event();
+  (void)hipEventRecord(stop, s_);
+  e_->ev.push_back({start_, stop});
 }
 
 Basis Context::basis_Q(int level) const {
@@ -221,6 +249,16 @@ Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uin
   BCN_HIP(hipMalloc(&c->d_slot_pos, N * sizeof(uint32_t)));
   BCN_HIP(hipMemcpy(c->d_slot_pos, pos.data(), N * sizeof(uint32_t), hipMemcpyHostToDevice));
   c->arena = std::make_unique<Arena>();
+  // default transform shape (bcn_autotune may replace it by a measured choice)
+  c->ntt_loge = logn >= 14 ? 5 : 4;
+  if (const char* env = std::getenv("BCN_NTT_LOGE")) {
+    const int v = std::atoi(env);
+    for (int o : c->ntt_loge_options())
+      if (o == v) c->ntt_loge = v;
+  }
+  // the fused square keeps three register sets live; above N = 8192 it would spill
+  c->fuse_square = logn <= 13;
+  if (const char* env = std::getenv("BCN_FUSE_SQUARE")) c->fuse_square = logn <= 13 && std::atoi(env) != 0;
   ntt_setup(*c);
   return c.release();
 }
@@ -229,6 +267,12 @@ void destroy_context(Context* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
+  for (auto& kv : c->prof_data)
+    for (auto& pr : kv.second.ev) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+  for (auto e : c->event_pool) (void)hipEventDestroy(e);
   release_convs(*c);
   if (c->d_tables) (void)hipFree(c->d_tables);
   if (c->d_slot_pos) (void)hipFree(c->d_slot_pos);

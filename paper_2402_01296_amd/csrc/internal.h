@@ -64,8 +64,21 @@ class Arena {
   size_t cur_ = 0, off_ = 0, used_total_ = 0, high_ = 0;
 };
 
+// Optional per-kernel timing: hipEvents recorded around launches on the
+// launch stream while profiling is enabled; algorithmic bytes accumulate per
+// kernel name.
+struct ProfEntry {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  double bytes = 0;
+  long launches = 0;
+};
+
 struct Context {
   int device = 0;
+  mutable bool prof = false;
+  mutable std::map<std::string, ProfEntry> prof_data;
+  mutable std::vector<hipEvent_t> event_pool;
+  hipEvent_t get_event() const;
   int n = 0, logn = 0;
   int L = 0, K = 0, alpha = 0, m = 0;   // Q primes, P primes, digit size, aux primes
   uint64_t t = 0;
@@ -77,6 +90,10 @@ struct Context {
   uint32_t* d_slot_pos = nullptr;        // [N] position of slot s in the transform of R_t
   std::unique_ptr<Arena> arena;
 
+  int ntt_loge = 0;                      // registers per thread = 2^ntt_loge in the transform
+  bool fuse_square = true;               // square's transforms and tensor in one kernel
+  std::vector<int> ntt_loge_options() const;
+
   int idQ(int i) const { return i; }
   int idP(int i) const { return L + i; }
   int idB(int i) const { return L + K + i; }
@@ -87,11 +104,28 @@ struct Context {
   Mod mod(int id) const { return hmods[id]; }
 };
 
+class ProfScope {
+ public:
+  ProfScope(const Context& c, const char* name, hipStream_t s, double bytes);
+  ~ProfScope();
+  ProfScope(const ProfScope&) = delete;
+  ProfScope& operator=(const ProfScope&) = delete;
+
+ private:
+  const Context& c_;
+  hipStream_t s_;
+  ProfEntry* e_ = nullptr;
+  hipEvent_t start_ = nullptr;
+};
+
 // ---- transforms (ntt.hip)
 // data: [n_polys][basis.n][N]; each limb transformed in place with its prime.
 void ntt_forward(const Context& c, double* data, int n_polys, const Basis& b, hipStream_t s);
 void ntt_inverse(const Context& c, double* data, int n_polys, const Basis& b, hipStream_t s);
 void ntt_setup(const Context& c);
+// in [n][2][b.n][N] coefficient form -> out [n][3][b.n][N]: the square's tensor
+// d0 = a0^2, d1 = 2 a0 a1, d2 = a1^2 in R_q for every limb, via fused transforms
+void square_transform_fused(const Context& c, const double* in, double* out, int n, const Basis& b, hipStream_t s);
 
 }  // namespace bcn
 
@@ -118,11 +152,11 @@ Conv make_conv(const Context& c, const std::vector<int>& src, const std::vector<
 // tiles: per tile of TO rows the list of columns with a nonzero weight.
 struct MacPlan {
   int n_in = 0, n_out = 0, tile = 0, n_tiles = 0;
-  double* W = nullptr;          // device [n_tiles*tile][n_in]
+  double* W = nullptr;          // device [entries][tile]: weights of each tile column entry
+  int* rows = nullptr;          // device [n_tiles*tile]: output row of each tile slot, -1 = none
   int* tile_ptr = nullptr;      // device [n_tiles+1]
-  int* tile_cols = nullptr;     // device
+  int* tile_cols = nullptr;     // device: columns with a nonzero weight in the tile
   int chunk = 0;                // inputs between two partial reductions
-  double* host_owned[1] = {nullptr};
 };
 void mac(const Context& c, const MacPlan& p, const double* in, double* out, int level, hipStream_t s);
 

@@ -45,10 +45,15 @@ __device__ __forceinline__ bool above_half(const double (&v)[NS], int n, const C
 
 // ------------------------------------------------------------------ MAC
 
+// out[rows[tile*TO + o]] = sum over the tile's column entries e of Wp[e][o] * in[cols[e]].
+// Wp holds, per column entry, the TO weights of the tile contiguously, so the
+// uniform weights of one column arrive as a few wide scalar loads.  Inputs are
+// centred (|x| <= (q-1)/2) so every partial sum is an exact FP64 integer;
+// `chunk` bounds the inputs between two partial reductions.
 template <int TO>
 __global__ void __launch_bounds__(TPB)
 k_mac(const double* __restrict__ in, double* __restrict__ out, int words, int logn, int level,
-      const double* __restrict__ W, int n_in, int n_out, const int* __restrict__ tptr,
+      const double* __restrict__ Wp, const int* __restrict__ rows, const int* __restrict__ tptr,
       const int* __restrict__ tcols, int chunk, Basis b, const Mod* __restrict__ mods) {
   const int w = blockIdx.x * TPB + threadIdx.x;
   if (w >= words) return;
@@ -59,24 +64,44 @@ k_mac(const double* __restrict__ in, double* __restrict__ out, int words, int lo
 #pragma unroll
   for (int o = 0; o < TO; ++o) acc[o] = 0.0;
   const int beg = tptr[tile], end = tptr[tile + 1];
-  const double* wt = W + (size_t)tile * TO * n_in;
+  const double* __restrict__ xin = in + w;
   int cnt = 0;
-  for (int e = beg; e < end; ++e) {
-    const int j = tcols[e];
-    double x = in[(size_t)j * words + w];
-    x = x > halfq ? x - m.q : x;          // centred: |x| <= (q-1)/2
-#pragma unroll
-    for (int o = 0; o < TO; ++o) acc[o] = fma(wt[(size_t)o * n_in + j], x, acc[o]);
-    if (++cnt == chunk) {
-      cnt = 0;
+  int e = beg;
+  for (; e + 4 <= end; e += 4) {
+    if (cnt > chunk - 4) {
 #pragma unroll
       for (int o = 0; o < TO; ++o) acc[o] = reduce_lazy(acc[o], m);
+      cnt = 0;
     }
+    double x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = xin[(size_t)tcols[e + u] * words];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double xv = x[u] > halfq ? x[u] - m.q : x[u];
+      const double* __restrict__ wr = Wp + (size_t)(e + u) * TO;
+#pragma unroll
+      for (int o = 0; o < TO; ++o) acc[o] = fma(wr[o], xv, acc[o]);
+    }
+    cnt += 4;
+  }
+  for (; e < end; ++e) {
+    if (cnt >= chunk) {
+#pragma unroll
+      for (int o = 0; o < TO; ++o) acc[o] = reduce_lazy(acc[o], m);
+      cnt = 0;
+    }
+    double x = xin[(size_t)tcols[e] * words];
+    x = x > halfq ? x - m.q : x;
+    const double* __restrict__ wr = Wp + (size_t)e * TO;
+#pragma unroll
+    for (int o = 0; o < TO; ++o) acc[o] = fma(wr[o], x, acc[o]);
+    ++cnt;
   }
 #pragma unroll
   for (int o = 0; o < TO; ++o) {
-    const int oo = tile * TO + o;
-    if (oo < n_out) out[(size_t)oo * words + w] = reduce(acc[o], m);
+    const int row = rows[tile * TO + o];
+    if (row >= 0) out[(size_t)row * words + w] = reduce(acc[o], m);
   }
 }
 
@@ -544,13 +569,15 @@ __global__ void k_quantise(const float* __restrict__ f, int n_pt, int mode, int 
 void mac(const Context& c, const MacPlan& p, const double* in, double* out, int level, hipStream_t s) {
   const int words = 2 * level * c.n;
   if (p.n_out == 0) return;
+  ProfScope ps(c, "mac", s, 8.0 * words * ((double)p.n_in + p.n_out));
   dim3 grid(nblocks(words), p.n_tiles);
   const Basis b = c.basis_Q(level);
   switch (p.tile) {
 #define BCN_MAC_CASE(TO) \
-  case TO: hipLaunchKernelGGL(k_mac<TO>, grid, dim3(TPB), 0, s, in, out, words, c.logn, level, p.W, p.n_in, p.n_out, \
+  case TO: hipLaunchKernelGGL(k_mac<TO>, grid, dim3(TPB), 0, s, in, out, words, c.logn, level, p.W, p.rows, \
                               p.tile_ptr, p.tile_cols, p.chunk, b, c.tab.mods); break;
     BCN_MAC_CASE(1) BCN_MAC_CASE(2) BCN_MAC_CASE(4) BCN_MAC_CASE(8) BCN_MAC_CASE(16) BCN_MAC_CASE(32)
+    BCN_MAC_CASE(64)
 #undef BCN_MAC_CASE
     default: throw Error(-1, "bad MAC tile");
   }
@@ -591,6 +618,7 @@ void ptvec_mac_ntt(const Context& c, const double* in, int n_in, double* out, in
 
 void tensor_square(const Context& c, const double* in, double* out, int n, const Basis& b, hipStream_t s) {
   if (n == 0) return;
+  ProfScope ps(c, "tensor_square", s, 8.0 * n * (double)b.n * c.n * 5);
   hipLaunchKernelGGL(k_tensor_square, dim3(nblocks((size_t)n * b.n * c.n)), dim3(TPB), 0, s, in, out, n, b.n, c.logn,
                      b, c.tab.mods);
   BCN_HIP(hipGetLastError());
@@ -605,6 +633,7 @@ void extend_qb(const Context& c, const double* in, double* out, int n, int level
   for (int i = 0; i < c.m; ++i) dst.push_back(c.idB(i));
   const Conv* cv = conv_device(c, "ext" + std::to_string(level), make_conv(c, src, dst));
   const int npoly = 2 * n;
+  ProfScope ps(c, "extend_qb", s, 8.0 * npoly * (double)c.n * (2 * level + c.m));
 #define BCN_EXT(NS) hipLaunchKernelGGL(k_extend_qb<NS>, dim3(nblocks((size_t)npoly * c.n)), dim3(TPB), 0, s, in, out, \
                                        npoly, c.logn, cv, c.tab.mods)
   BCN_DISPATCH_NS(level, BCN_EXT)
@@ -629,6 +658,7 @@ void scale_round(const Context& c, const double* in, double* out, int n, int lev
   const Conv* dcv = conv_device(c, key, cv);
   const int npoly = 3 * n;
   const int ns = level + c.m;
+  ProfScope ps(c, "scale_round", s, 8.0 * npoly * (double)c.n * (ns + level));
 #define BCN_SR(NS) hipLaunchKernelGGL(k_scale_round<NS>, dim3(nblocks((size_t)npoly * c.n)), dim3(TPB), 0, s, in, out, \
                                       npoly, c.logn, level, dcv, c.tab.mods)
   BCN_DISPATCH_NS(ns, BCN_SR)
@@ -641,6 +671,7 @@ void decompose_modup(const Context& c, const double* in, size_t in_stride, doubl
   if (n == 0) return;
   const int dnum = c.dnum(level);
   const Basis dstb = c.basis_QP(level);
+  ProfScope ps(c, "modup", s, 8.0 * n * (double)c.n * (level + dnum * dstb.n));
   for (int j = 0; j < dnum; ++j) {
     const int lo = j * c.alpha, hi = std::min((j + 1) * c.alpha, level);
     std::vector<int> src, dst;
@@ -665,6 +696,7 @@ void ks_inner(const Context& c, const double* D, int d_div, const KeySel& ka, in
               hipStream_t s) {
   if (n == 0) return;
   const Basis b = c.basis_QP(level);
+  ProfScope ps(c, "ks_inner", s, 8.0 * n * (double)c.n * b.n * (2 + (double)c.dnum(level) * 2));
   hipLaunchKernelGGL(k_ks_inner, dim3(nblocks((size_t)n * b.n * c.n)), dim3(TPB), 0, s, D, ka, n, d_div,
                      level, b.n, c.dnum(level), c.L, c.logn, b, c.tab.mods, out);
   BCN_HIP(hipGetLastError());
@@ -687,6 +719,7 @@ void moddown(const Context& c, const double* u, int n, int level, const double* 
   }
   const Conv* dcv = conv_device(c, "md" + std::to_string(level), cv);
   const size_t work = (size_t)n * 2 * c.n;
+  ProfScope ps(c, "moddown", s, 8.0 * work * ((double)level + c.K + (add_mode ? level : 0) + (modsw ? level - 1 : level)));
 #define BCN_MD(NK, NQ) hipLaunchKernelGGL((k_moddown<NK, NQ>), dim3(nblocks(work)), dim3(TPB), 0, s, u, n, c.logn, add, \
                                           add_div, add_stride, add_mode, ks, modsw ? 1 : 0, dcv, c.tab.mods, out, \
                                           out_div > 0 ? out_div : 1, \

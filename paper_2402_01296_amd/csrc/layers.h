@@ -1,6 +1,9 @@
 #pragma once
 
 #include "../../include/bcn.h"
+#include <functional>
+#include <string>
+
 #include "scheme.h"
 
 namespace bcn {
@@ -14,6 +17,8 @@ struct Layer {
   int fclamp = 127;
   int batch = 0, stride_b = 0;
   MacPlan mac;
+  std::vector<int32_t> mac_weights;  // host copy of the MAC matrix (for retuning)
+  std::vector<int> mac_order;
   std::vector<int> steps;        // HW conv: nonzero tap offsets, tap index = position + 1
   std::vector<int> all_steps;    // every Galois step the layer needs
   double* mask_hat = nullptr;    // [level][N]
@@ -25,6 +30,8 @@ struct Layer {
 };
 
 Layer* layer_create(Context& c, const bcn_layer_desc& d, int level);
+std::string autotune_ntt(Context& c, hipStream_t s);
+std::string autotune_layer_mac(Context& c, Layer& L, hipStream_t s);
 void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, double* out, const float* features,
                 hipStream_t s);
 

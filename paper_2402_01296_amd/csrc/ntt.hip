@@ -7,7 +7,7 @@
 //
 // One workgroup transforms one limb.  Each thread keeps E = 2^LOGE residues in
 // registers and applies LOGE butterfly stages per pass; passes exchange data
-// through LDS (the whole limb, padded, is LDS-resident).  The first pass reads
+// through LDS (the whole limb is LDS-resident, bank-swizzled).  The first pass reads
 // HBM and the last pass writes HBM, so a limb costs one read and one write of
 // N words.  Values grow additively inside the transform (|x| < (LOGN+1) q <
 // 2^45), which the lazy FP64 product tolerates; one reduction at the end
@@ -17,7 +17,12 @@
 namespace bcn {
 namespace {
 
-__device__ __forceinline__ int lds_pad(int g) { return g + (g >> 5); }
+// LDS word of transform index g: an XOR swizzle of the low five bits by the
+// five bits above the register-set size.  It is a bijection on every block of
+// 2^(LOGE+5) words and makes all the kernel's lane patterns (consecutive
+// indices, or per-lane contiguous sets of 2^LOGE) hit distinct banks.
+template <int LOGE>
+__device__ __forceinline__ int lds_sw(int g) { return g ^ ((g >> LOGE) & 31); }
 
 template <int LOGN, int LOGE>
 struct Shape {
@@ -36,10 +41,14 @@ struct Sched {
   static constexpr int s0(int p) { return INV ? p * LOGE : (p == 0 ? 0 : S::C0 + (p - 1) * LOGE); }
 };
 
-template <int LOGN, int LOGE, bool INV, int P>
-__device__ __forceinline__ void run_pass(double (&x)[1 << LOGE], double* lds, double* __restrict__ a,
-                                         const double* __restrict__ tw, const double* __restrict__ post,
-                                         const Mod m, const int tid) {
+// One pass of the transform.  FROM_REGS: the first pass starts from the
+// registers (already in this pass's layout) instead of reading HBM.  TO_REGS:
+// the last pass leaves its results in the registers (lazy form, no final
+// reduction or untwist) instead of writing HBM.
+template <int LOGN, int LOGE, bool INV, int P, bool FROM_REGS = false, bool TO_REGS = false>
+__device__ __forceinline__ void run_pass(double (&x)[1 << LOGE], double* lds, const double* __restrict__ src,
+                                         double* __restrict__ a, const double* __restrict__ tw,
+                                         const double* __restrict__ post, const Mod m, const int tid) {
   using S = Shape<LOGN, LOGE>;
   constexpr int N = S::N, T = S::T;
   constexpr int C = Sched<LOGN, LOGE, INV>::c(P);
@@ -58,61 +67,87 @@ __device__ __forceinline__ void run_pass(double (&x)[1 << LOGE], double* lds, do
 
   // gather
   if constexpr (P == 0) {
+    if constexpr (!FROM_REGS) {
 #pragma unroll
-    for (int g = 0; g < G; ++g)
+      for (int g = 0; g < G; ++g)
 #pragma unroll
-      for (int j = 0; j < SZ; ++j) x[g * SZ + j] = a[base[g] + j * SMIN];
+        for (int j = 0; j < SZ; ++j) x[g * SZ + j] = src[base[g] + j * SMIN];
+    }
   } else {
 #pragma unroll
     for (int g = 0; g < G; ++g)
 #pragma unroll
-      for (int j = 0; j < SZ; ++j) x[g * SZ + j] = lds[lds_pad(base[g] + j * SMIN)];
+      for (int j = 0; j < SZ; ++j) x[g * SZ + j] = lds[lds_sw<LOGE>(base[g] + j * SMIN)];
   }
 
-  // butterflies
+  // butterflies: one twiddle load per group of butterflies that share it
 #pragma unroll
   for (int l = 0; l < C; ++l) {
     const int s = S0 + l;
-    const int sh = INV ? l : (C - 1 - l);
-    const int half = 1 << sh;
+    if (!INV) {
+      // forward stage: local blocks of 2*half elements, one twiddle per block
+      const int sh = C - 1 - l;
+      const int half = 1 << sh;
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
+      for (int g = 0; g < G; ++g) {
 #pragma unroll
-      for (int jj = 0; jj < SZ / 2; ++jj) {
-        const int j = ((jj >> sh) << (sh + 1)) | (jj & (half - 1));
-        const int gi = base[g] + j * SMIN;
-        double w;
-        if (INV)
-          w = tw[(gi & ((1 << s) - 1)) * (N >> (s + 1))];
-        else
-          w = tw[(1 << s) + (gi >> (LOGN - s))];
-        const double u = x[g * SZ + j];
-        const double v = mul_lazy(w, x[g * SZ + j + half], m);
-        x[g * SZ + j] = u + v;
-        x[g * SZ + j + half] = u - v;
+        for (int kb = 0; kb < (SZ >> (sh + 1)); ++kb) {
+          const int j0 = kb << (sh + 1);
+          const int gi = base[g] + j0 * SMIN;
+          const double w = tw[(1 << s) + (gi >> (LOGN - s))];
+#pragma unroll
+          for (int jj = 0; jj < half; ++jj) {
+            const int j = g * SZ + j0 + jj;
+            const double u = x[j];
+            const double v = mul_lazy(w, x[j + half], m);
+            x[j] = u + v;
+            x[j + half] = u - v;
+          }
+        }
+      }
+    } else {
+      // inverse stage: the twiddle depends only on the position inside a block
+      const int half = 1 << l;
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int r = base[g] & (SMIN - 1);
+#pragma unroll
+        for (int jl = 0; jl < half; ++jl) {
+          const double w = tw[(r + jl * SMIN) * (N >> (s + 1))];
+#pragma unroll
+          for (int kb = 0; kb < (SZ >> (l + 1)); ++kb) {
+            const int j = g * SZ + (kb << (l + 1)) + jl;
+            const double u = x[j];
+            const double v = mul_lazy(w, x[j + half], m);
+            x[j] = u + v;
+            x[j + half] = u - v;
+          }
+        }
       }
     }
   }
 
   if constexpr (P == S::NP - 1) {
-    // scatter to HBM in canonical form
+    if constexpr (!TO_REGS) {
+      // scatter to HBM in canonical form
 #pragma unroll
-    for (int g = 0; g < G; ++g)
+      for (int g = 0; g < G; ++g)
 #pragma unroll
-      for (int j = 0; j < SZ; ++j) {
-        const int gi = base[g] + j * SMIN;
-        double v = x[g * SZ + j];
-        v = INV ? norm(mul_lazy(post[gi], v, m), m) : reduce(v, m);
-        a[gi] = v;
-      }
+        for (int j = 0; j < SZ; ++j) {
+          const int gi = base[g] + j * SMIN;
+          double v = x[g * SZ + j];
+          v = INV ? norm(mul_lazy(post[gi], v, m), m) : reduce(v, m);
+          a[gi] = v;
+        }
+    }
   } else {
-    if constexpr (P > 0) __syncthreads();   // everyone has finished reading this pass's LDS data
+    if constexpr (P > 0 || FROM_REGS) __syncthreads();   // previous LDS readers are done
 #pragma unroll
     for (int g = 0; g < G; ++g)
 #pragma unroll
-      for (int j = 0; j < SZ; ++j) lds[lds_pad(base[g] + j * SMIN)] = x[g * SZ + j];
+      for (int j = 0; j < SZ; ++j) lds[lds_sw<LOGE>(base[g] + j * SMIN)] = x[g * SZ + j];
     __syncthreads();
-    run_pass<LOGN, LOGE, INV, P + 1>(x, lds, a, tw, post, m, tid);
+    run_pass<LOGN, LOGE, INV, P + 1, FROM_REGS, TO_REGS>(x, lds, src, a, tw, post, m, tid);
   }
 }
 
@@ -128,13 +163,62 @@ k_ntt(double* __restrict__ data, Basis basis, Tables tb) {
   const double* tw = INV ? tb.inv + (size_t)pid * (N / 2) : tb.fwd + (size_t)pid * N;
   const double* post = tb.post + (size_t)pid * N;
   double x[1 << LOGE];
-  run_pass<LOGN, LOGE, INV, 0>(x, lds, a, tw, post, m, threadIdx.x);
+  run_pass<LOGN, LOGE, INV, 0>(x, lds, a, a, tw, post, m, threadIdx.x);
+}
+
+// Square in the transform domain, fused: for one limb of one ciphertext
+// (a0, a1 in coefficient form over Q then the auxiliary primes) computes the
+// forward transforms of a0 and a1, the products d0 = a0^2, d1 = 2 a0 a1,
+// d2 = a1^2 and their inverse transforms, writing d0, d1, d2 in coefficient
+// form.  The forward transform ends in the register layout the inverse
+// transform starts from, so nothing between the two loads and three stores
+// goes through HBM.
+template <int LOGN, int LOGE>
+__global__ void __launch_bounds__(1 << (LOGN - LOGE))
+k_square_fused(const double* __restrict__ in, double* __restrict__ out, Basis basis, Tables tb) {
+  constexpr int N = 1 << LOGN;
+  constexpr int E = 1 << LOGE;
+  extern __shared__ double lds[];
+  const int nb = basis.n;
+  const int ct = blockIdx.x / nb, limb = blockIdx.x % nb;
+  const int pid = basis.id[limb];
+  const Mod m = tb.mods[pid];
+  const double* fw = tb.fwd + (size_t)pid * N;
+  const double* iw = tb.inv + (size_t)pid * (N / 2);
+  const double* post = tb.post + (size_t)pid * N;
+  const double* a0 = in + ((size_t)(ct * 2) * nb + limb) * N;
+  const double* a1 = in + ((size_t)(ct * 2 + 1) * nb + limb) * N;
+  double x0[E], x1[E], x[E];
+  run_pass<LOGN, LOGE, false, 0, false, true>(x0, lds, a0, nullptr, fw, post, m, threadIdx.x);
+  __syncthreads();
+  run_pass<LOGN, LOGE, false, 0, false, true>(x1, lds, a1, nullptr, fw, post, m, threadIdx.x);
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    x0[i] = reduce(x0[i], m);
+    x1[i] = reduce(x1[i], m);
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      if (k == 0) {
+        x[i] = mul_mod(x0[i], x0[i], m);
+      } else if (k == 1) {
+        const double p = mul_mod(x0[i], x1[i], m);
+        x[i] = add_mod(p, p, m);
+      } else {
+        x[i] = mul_mod(x1[i], x1[i], m);
+      }
+    }
+    double* dst = out + ((size_t)(ct * 3 + k) * nb + limb) * N;
+    run_pass<LOGN, LOGE, true, 0, true, false>(x, lds, nullptr, dst, iw, post, m, threadIdx.x);
+  }
 }
 
 template <int LOGN, int LOGE, bool INV>
 void launch(const Context& c, double* data, int n_polys, const Basis& b, hipStream_t s) {
   constexpr int N = 1 << LOGN;
-  const size_t lds = (size_t)(N + N / 32) * sizeof(double);
+  const size_t lds = (size_t)N * sizeof(double);
   const unsigned blocks = (unsigned)n_polys * b.n;
   if (blocks == 0) return;
   hipLaunchKernelGGL((k_ntt<LOGN, LOGE, INV>), dim3(blocks), dim3(N >> LOGE), lds, s, data, b, c.tab);
@@ -143,33 +227,79 @@ void launch(const Context& c, double* data, int n_polys, const Basis& b, hipStre
 
 template <int LOGN, int LOGE>
 void set_attr() {
-  const int lds = (int)((1 << LOGN) + (1 << LOGN) / 32) * (int)sizeof(double);
+  const int lds = (1 << LOGN) * (int)sizeof(double);
   BCN_HIP(hipFuncSetAttribute((const void*)k_ntt<LOGN, LOGE, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
   BCN_HIP(hipFuncSetAttribute((const void*)k_ntt<LOGN, LOGE, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+  BCN_HIP(hipFuncSetAttribute((const void*)k_square_fused<LOGN, LOGE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              lds));
+}
+
+template <int LOGN, int LOGE>
+void launch_square(const Context& c, const double* in, double* out, int n, const Basis& b, hipStream_t s) {
+  constexpr int N = 1 << LOGN;
+  const unsigned blocks = (unsigned)n * b.n;
+  if (blocks == 0) return;
+  hipLaunchKernelGGL((k_square_fused<LOGN, LOGE>), dim3(blocks), dim3(N >> LOGE), (size_t)N * sizeof(double), s, in,
+                     out, b, c.tab);
+  BCN_HIP(hipGetLastError());
 }
 
 template <bool INV>
 void dispatch(const Context& c, double* data, int n_polys, const Basis& b, hipStream_t s) {
-  switch (c.logn) {
-    case 10: launch<10, 3, INV>(c, data, n_polys, b, s); break;
-    case 11: launch<11, 3, INV>(c, data, n_polys, b, s); break;
-    case 12: launch<12, 4, INV>(c, data, n_polys, b, s); break;
-    case 13: launch<13, 4, INV>(c, data, n_polys, b, s); break;
-    case 14: launch<14, 5, INV>(c, data, n_polys, b, s); break;
-    default: throw Error(-1, "unsupported ring degree");
+  // algorithmic traffic: each limb read once and written once
+  ProfScope ps(c, INV ? "ntt_inverse" : "ntt_forward", s, 16.0 * c.n * (double)n_polys * b.n);
+  const int key = c.logn * 16 + c.ntt_loge;
+  switch (key) {
+#define BCN_NTT_CASE(LN, LE) \
+  case LN * 16 + LE: launch<LN, LE, INV>(c, data, n_polys, b, s); break;
+    BCN_NTT_CASE(10, 3) BCN_NTT_CASE(10, 4)
+    BCN_NTT_CASE(11, 3) BCN_NTT_CASE(11, 4)
+    BCN_NTT_CASE(12, 4) BCN_NTT_CASE(12, 5)
+    BCN_NTT_CASE(13, 4) BCN_NTT_CASE(13, 5)
+    BCN_NTT_CASE(14, 4) BCN_NTT_CASE(14, 5)
+#undef BCN_NTT_CASE
+    default: throw Error(-1, "unsupported ring degree / transform shape");
   }
 }
 
 }  // namespace
 
+std::vector<int> Context::ntt_loge_options() const {
+  switch (logn) {
+    case 10: return {3, 4};
+    case 11: return {3, 4};
+    case 12: return {4, 5};
+    case 13: return {4, 5};
+    case 14: return {4, 5};
+    default: return {};
+  }
+}
+
 void ntt_setup(const Context& c) {
   switch (c.logn) {
-    case 10: set_attr<10, 3>(); break;
-    case 11: set_attr<11, 3>(); break;
-    case 12: set_attr<12, 4>(); break;
-    case 13: set_attr<13, 4>(); break;
-    case 14: set_attr<14, 5>(); break;
+    case 10: set_attr<10, 3>(); set_attr<10, 4>(); break;
+    case 11: set_attr<11, 3>(); set_attr<11, 4>(); break;
+    case 12: set_attr<12, 4>(); set_attr<12, 5>(); break;
+    case 13: set_attr<13, 4>(); set_attr<13, 5>(); break;
+    case 14: set_attr<14, 4>(); set_attr<14, 5>(); break;
     default: throw Error(-1, "unsupported ring degree");
+  }
+}
+
+void square_transform_fused(const Context& c, const double* in, double* out, int n, const Basis& b, hipStream_t s) {
+  // algorithmic traffic: two limbs in, three limbs out per (ciphertext, limb)
+  ProfScope ps(c, "square_fused", s, 8.0 * c.n * (double)n * b.n * 5);
+  const int key = c.logn * 16 + c.ntt_loge;
+  switch (key) {
+#define BCN_SQ_CASE(LN, LE) \
+  case LN * 16 + LE: launch_square<LN, LE>(c, in, out, n, b, s); break;
+    BCN_SQ_CASE(10, 3) BCN_SQ_CASE(10, 4)
+    BCN_SQ_CASE(11, 3) BCN_SQ_CASE(11, 4)
+    BCN_SQ_CASE(12, 4) BCN_SQ_CASE(12, 5)
+    BCN_SQ_CASE(13, 4) BCN_SQ_CASE(13, 5)
+    BCN_SQ_CASE(14, 4) BCN_SQ_CASE(14, 5)
+#undef BCN_SQ_CASE
+    default: throw Error(-1, "unsupported ring degree / transform shape");
   }
 }
 

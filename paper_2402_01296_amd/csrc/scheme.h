@@ -52,7 +52,10 @@ void rotate_hoisted(Context& c, EvalKeys& ek, const double* in, int n_in, int le
                     double* out, hipStream_t s, int out_div = 0, size_t out_outer = 0);
 void rotate_sum(Context& c, const EvalKeys& ek, double* ct, int n, int level, int span, hipStream_t s);
 
-MacPlan make_mac_plan(const Context& c, const std::vector<int32_t>& w, int n_out, int n_in);
+// w: [n_out][n_in]; order: output rows in tiling order (empty = natural); tile: outputs per
+// tile (power of two <= 64, 0 = automatic)
+MacPlan make_mac_plan(const Context& c, const std::vector<int32_t>& w, int n_out, int n_in,
+                      const std::vector<int>& order = {}, int tile = 0);
 void free_mac_plan(MacPlan& p);
 
 }  // namespace bcn

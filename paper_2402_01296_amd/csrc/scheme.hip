@@ -239,10 +239,14 @@ void square_relin(Context& c, const EvalKeys& ek, const double* in, double* out,
   const int nb = qb.n, nbp = qp.n, dn = c.dnum(level);
   double* X = ar.take((size_t)n * 2 * nb * N);
   extend_qb(c, in, X, n, level, s);
-  ntt_forward(c, X, 2 * n, qb, s);
   double* Y = ar.take((size_t)n * 3 * nb * N);
-  tensor_square(c, X, Y, n, qb, s);
-  ntt_inverse(c, Y, 3 * n, qb, s);
+  if (c.fuse_square) {
+    square_transform_fused(c, X, Y, n, qb, s);
+  } else {
+    ntt_forward(c, X, 2 * n, qb, s);
+    tensor_square(c, X, Y, n, qb, s);
+    ntt_inverse(c, Y, 3 * n, qb, s);
+  }
   double* Z = ar.take((size_t)n * 3 * level * N);
   scale_round(c, Y, Z, n, level, s);
   double* D = ar.take((size_t)n * dn * nbp * N);
@@ -303,27 +307,46 @@ void rotate_sum(Context& c, const EvalKeys& ek, double* ct, int n, int level, in
   }
 }
 
-MacPlan make_mac_plan(const Context& c, const std::vector<int32_t>& w, int n_out, int n_in) {
+MacPlan make_mac_plan(const Context& c, const std::vector<int32_t>& w, int n_out, int n_in,
+                      const std::vector<int>& order_in, int tile) {
   MacPlan p;
   p.n_in = n_in;
   p.n_out = n_out;
-  int tile = 16;
-  while (tile > 1 && tile / 2 >= n_out) tile /= 2;
+  std::vector<int> order = order_in;
+  if (order.empty())
+    for (int o = 0; o < n_out; ++o) order.push_back(o);
+  if ((int)order.size() != n_out) throw Error(-1, "MAC row order has the wrong length");
+  if (tile == 0) {
+    tile = 1;
+    while (tile < 64 && tile < n_out) tile *= 2;
+  }
   p.tile = tile;
   p.n_tiles = (n_out + tile - 1) / tile;
-  std::vector<double> W((size_t)p.n_tiles * tile * n_in, 0.0);
+  const size_t slots = (size_t)p.n_tiles * tile;
+  std::vector<int> rows(slots, -1);
   std::vector<int> ptr(1, 0), cols;
+  std::vector<double> W;   // [entry][tile]
   int32_t wmax = 1;
   for (int t = 0; t < p.n_tiles; ++t) {
+    for (int o = 0; o < tile && t * tile + o < n_out; ++o) {
+      const int row = order[t * tile + o];
+      if (row < 0 || row >= n_out) throw Error(-1, "MAC row order out of range");
+      rows[t * tile + o] = row;
+    }
     for (int j = 0; j < n_in; ++j) {
       bool any = false;
-      for (int o = t * tile; o < std::min(n_out, (t + 1) * tile); ++o) {
-        const int32_t v = w[(size_t)o * n_in + j];
-        W[(size_t)o * n_in + j] = (double)v;
-        wmax = std::max(wmax, v < 0 ? -v : v);
-        any |= v != 0;
+      for (int o = 0; o < tile; ++o) {
+        const int row = rows[t * tile + o];
+        if (row >= 0 && w[(size_t)row * n_in + j] != 0) any = true;
       }
-      if (any) cols.push_back(j);
+      if (!any) continue;
+      cols.push_back(j);
+      for (int o = 0; o < tile; ++o) {
+        const int row = rows[t * tile + o];
+        const int32_t v = row >= 0 ? w[(size_t)row * n_in + j] : 0;
+        wmax = std::max(wmax, v < 0 ? -v : v);
+        W.push_back((double)v);
+      }
     }
     ptr.push_back((int)cols.size());
   }
@@ -332,11 +355,14 @@ MacPlan make_mac_plan(const Context& c, const std::vector<int32_t>& w, int n_out
   for (int i = 0; i < c.L; ++i) qmax = std::max(qmax, (double)c.primes[i]);
   // |acc| <= q/2 + 1 + chunk * wmax * (q-1)/2 must stay below 2^53
   const double room = 9007199254740992.0 - qmax;
-  p.chunk = std::max(1, (int)std::min(1e6, std::floor(room / ((double)wmax * qmax * 0.5))));
+  p.chunk = std::max(4, (int)std::min(1e6, std::floor(room / ((double)wmax * qmax * 0.5))));
+  if ((double)p.chunk * wmax * qmax * 0.5 >= room) throw Error(-1, "weights too large for exact accumulation");
   BCN_HIP(hipMalloc(&p.W, std::max<size_t>(1, W.size()) * sizeof(double)));
+  BCN_HIP(hipMalloc(&p.rows, rows.size() * sizeof(int)));
   BCN_HIP(hipMalloc(&p.tile_ptr, ptr.size() * sizeof(int)));
   BCN_HIP(hipMalloc(&p.tile_cols, std::max<size_t>(1, cols.size()) * sizeof(int)));
   BCN_HIP(hipMemcpy(p.W, W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice));
+  BCN_HIP(hipMemcpy(p.rows, rows.data(), rows.size() * sizeof(int), hipMemcpyHostToDevice));
   BCN_HIP(hipMemcpy(p.tile_ptr, ptr.data(), ptr.size() * sizeof(int), hipMemcpyHostToDevice));
   if (!cols.empty()) BCN_HIP(hipMemcpy(p.tile_cols, cols.data(), cols.size() * sizeof(int), hipMemcpyHostToDevice));
   return p;
@@ -344,10 +370,10 @@ MacPlan make_mac_plan(const Context& c, const std::vector<int32_t>& w, int n_out
 
 void free_mac_plan(MacPlan& p) {
   if (p.W) (void)hipFree(p.W);
+  if (p.rows) (void)hipFree(p.rows);
   if (p.tile_ptr) (void)hipFree(p.tile_ptr);
   if (p.tile_cols) (void)hipFree(p.tile_cols);
   p.W = nullptr;
-  p.tile_ptr = p.tile_cols = nullptr;
+  p.rows = p.tile_ptr = p.tile_cols = nullptr;
 }
-
 }  // namespace bcn

@@ -1,0 +1,121 @@
+// Autotuner: times the candidate transform shapes and MAC tile sizes on the
+// device with hipEvents and keeps the fastest.
+#include <algorithm>
+#include <cstdio>
+#include <string>
+
+#include "layers.h"
+
+namespace bcn {
+
+namespace {
+float time_ms(hipStream_t s, int reps, const std::function<void()>& f) {
+  hipEvent_t a, b;
+  BCN_HIP(hipEventCreate(&a));
+  BCN_HIP(hipEventCreate(&b));
+  f();  // warm-up
+  BCN_HIP(hipEventRecord(a, s));
+  for (int i = 0; i < reps; ++i) f();
+  BCN_HIP(hipEventRecord(b, s));
+  BCN_HIP(hipEventSynchronize(b));
+  float ms = 0;
+  BCN_HIP(hipEventElapsedTime(&ms, a, b));
+  BCN_HIP(hipEventDestroy(a));
+  BCN_HIP(hipEventDestroy(b));
+  return ms / reps;
+}
+}  // namespace
+
+std::string autotune_ntt(Context& c, hipStream_t s) {
+  // a batch shaped like the square's transforms: many polynomials over Q_L + aux
+  const Basis b = c.basis_QB(c.L);
+  const int polys = std::max(16, 2048 / b.n);
+  double* buf = c.arena->take((size_t)polys * b.n * c.n);
+  BCN_HIP(hipMemsetAsync(buf, 0, (size_t)polys * b.n * c.n * sizeof(double), s));
+  std::string report;
+  int best = c.ntt_loge;
+  float best_ms = 1e30f;
+  for (int loge : c.ntt_loge_options()) {
+    c.ntt_loge = loge;
+    const float ms = time_ms(s, 5, [&] {
+      ntt_forward(c, buf, polys, b, s);
+      ntt_inverse(c, buf, polys, b, s);
+    });
+    char line[128];
+    std::snprintf(line, sizeof line, "ntt logn=%d loge=%d: %.3f ms for %d limbs fwd+inv\n", c.logn, loge, ms,
+                  polys * b.n);
+    report += line;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = loge;
+    }
+  }
+  c.ntt_loge = best;
+  report += "ntt chosen loge=" + std::to_string(best) + "\n";
+  // square's transform segment: fused kernel vs forward + tensor + inverse
+  if (c.logn <= 13) {
+    const int n = std::max(8, polys / 2);
+    double* in = buf;
+    double* out = c.arena->take((size_t)n * 3 * b.n * c.n);
+    double* tmp = c.arena->take((size_t)n * 2 * b.n * c.n);
+    const float unfused = time_ms(s, 5, [&] {
+      BCN_HIP(hipMemcpyAsync(tmp, in, (size_t)n * 2 * b.n * c.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      ntt_forward(c, tmp, 2 * n, b, s);
+      tensor_square(c, tmp, out, n, b, s);
+      ntt_inverse(c, out, 3 * n, b, s);
+    });
+    const float copy = time_ms(s, 5, [&] {
+      BCN_HIP(hipMemcpyAsync(tmp, in, (size_t)n * 2 * b.n * c.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    });
+    const float fused = time_ms(s, 5, [&] { square_transform_fused(c, in, out, n, b, s); });
+    char line[160];
+    std::snprintf(line, sizeof line, "square transforms (%d ciphertexts, %d limbs): fused %.3f ms, unfused %.3f ms\n",
+                  n, b.n, fused, unfused - copy);
+    report += line;
+    c.fuse_square = fused < unfused - copy;
+  } else {
+    c.fuse_square = false;
+  }
+  report += std::string("square chosen fused=") + (c.fuse_square ? "1" : "0") + "\n";
+  return report;
+}
+
+std::string autotune_layer_mac(Context& c, Layer& L, hipStream_t s) {
+  if (L.mac_weights.empty()) return "";
+  const size_t ctw = (size_t)2 * L.level * c.n;
+  const int n_in_mac = L.mac.n_in;
+  double* in = c.arena->take((size_t)n_in_mac * ctw);
+  double* out = c.arena->take((size_t)L.mac.n_out * ctw);
+  BCN_HIP(hipMemsetAsync(in, 0, (size_t)n_in_mac * ctw * sizeof(double), s));
+  std::string report;
+  float best_ms = 1e30f;
+  int best_tile = L.mac.tile;
+  for (int tile : {8, 16, 32, 64}) {
+    if (tile / 2 >= L.mac.n_out && tile > 8) break;
+    MacPlan p = make_mac_plan(c, L.mac_weights, L.mac.n_out, n_in_mac, L.mac_order, tile);
+    float ms = 0;
+    try {
+      ms = time_ms(s, 5, [&] { mac(c, p, in, out, L.level, s); });
+    } catch (...) {
+      free_mac_plan(p);
+      throw;
+    }
+    free_mac_plan(p);
+    char line[128];
+    std::snprintf(line, sizeof line, "mac %dx%d tile=%d: %.3f ms\n", L.mac.n_out, n_in_mac, tile, ms);
+    report += line;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_tile = tile;
+    }
+  }
+  if (best_tile != L.mac.tile) {
+    BCN_HIP(hipStreamSynchronize(s));
+    free_mac_plan(L.mac);
+    L.mac = make_mac_plan(c, L.mac_weights, L.mac.n_out, n_in_mac, L.mac_order, best_tile);
+  }
+  report += "mac chosen tile=" + std::to_string(best_tile) + "\n";
+  return report;
+}
+
+}  // namespace bcn

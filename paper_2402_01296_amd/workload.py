@@ -89,6 +89,13 @@ class GpuSession:
         self.steps = sorted({s for lay in self.layers for s in lay.steps})
         self._keygen()
 
+    def autotune(self) -> str:
+        """Measured choice of transform shape and MAC tile sizes (results unchanged)."""
+        report = self.ctx.autotune()
+        for lay in self.layers:
+            report += self.ctx.autotune_layer(lay)
+        return report
+
     def key_randomness(self, key_id: int):
         moduli = self.ctx.q + self.ctx.p_primes
         d = self.ctx.dnum()

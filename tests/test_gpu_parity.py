@@ -130,17 +130,20 @@ def test_import_export_roundtrip(env_t1k):
     assert (ev["ctx"].export(ev["ctx"].import_(res)) == res).all()
 
 
-def test_mac_parity(env_t1k):
+@pytest.mark.parametrize("n_in,n_out,bound", [(37, 19, 31), (7, 100, 15), (300, 3, 1000)])
+def test_mac_parity(env_t1k, n_in, n_out, bound):
+    # (7, 100): two 64-row tiles, the second partial, column count not a multiple of 4;
+    # (300, 3): large weights force partial reductions inside the accumulation
     ev = env_t1k
     prm, ctx = ev["prm"], ev["ctx"]
     level = prm.L
-    res = random_ct_residues(prm, level, 37, 12)
-    w = np.random.default_rng(4).integers(-31, 32, (19, 37)).astype(np.int32)
-    w[3] = 0                                   # an all-zero row
-    w[:, 5] = 0                                # an unused input
+    res = random_ct_residues(prm, level, n_in, 12)
+    w = np.random.default_rng(4).integers(-bound, bound + 1, (n_out, n_in)).astype(np.int32)
+    w[min(3, n_out - 1)] = 0                   # an all-zero row
+    w[:, min(5, n_in - 1)] = 0                 # an unused input
     out = ctx.export(ctx.mac(ctx.import_(res), w))
     cts = [oracle_ct(prm, r) for r in res]
-    for o in range(19):
+    for o in range(n_out):
         ref = bfv.ct_to_rns(prm, bfv.mac(prm, cts, w[o]))
         assert (out[o] == ref).all(), "output %d" % o
 
@@ -238,3 +241,46 @@ def test_errors_are_reported(env_t1k):
     bad[0, 0, 0, 0] = ev["prm"].q[0]             # residue not below its prime
     with pytest.raises(bcn.BcnError):
         ctx.import_(bad)
+
+
+@pytest.mark.parametrize("pname", ["t1k", "cfg2"])
+def test_transform_shapes_agree(pname, monkeypatch):
+    """Every transform shape the autotuner may pick computes the same exact transform."""
+    torch = torch_cuda()
+    from oracle import params
+    from paper_2402_01296_amd import bcn
+    spec = params.get(pname)
+    outs = []
+    for loge in (3, 4, 5):
+        monkeypatch.setenv("BCN_NTT_LOGE", str(loge))
+        ctx = bcn.Context(spec.n, spec.q[0].bit_length(), spec.L, spec.K, spec.alpha, spec.t)
+        x = np.stack([synthetic.test_poly(3, i, ctx.q, spec.n) for i in range(3)])
+        d = torch.from_numpy(x.astype(np.float64)).cuda()
+        ctx.ntt(d, 0)
+        f = d.cpu().numpy().copy()
+        ctx.ntt(d, 0, inverse=True)
+        assert (d.cpu().numpy().astype(np.uint64) == x).all()
+        outs.append(f)
+        ctx.close()
+    assert all((o == outs[0]).all() for o in outs)
+
+
+@pytest.mark.parametrize("fuse", ["0", "1"])
+def test_square_paths_agree(fuse, monkeypatch):
+    """The fused and the unfused square transform segments give the same exact ciphertexts."""
+    torch_cuda()
+    from oracle import params
+    from paper_2402_01296_amd import bcn
+    monkeypatch.setenv("BCN_FUSE_SQUARE", fuse)
+    prm, ctx = context("t1k")
+    s = synthetic.ternary_secret(31, prm.n)
+    sk = ctx.secret_key(s)
+    ek = ctx.eval_keys()
+    a, e = key_randomness(prm, 31, 0)
+    ctx.keygen(sk, ek, bcn.BCN_KEY_RELIN, 0, np.stack(a), np.stack(e))
+    rk = bfv.relin_key(prm, [int(v) for v in s], a, e)
+    res = random_ct_residues(prm, prm.L, 2, 77)
+    got = ctx.export(ctx.square_relin(ek, ctx.import_(res), modswitch=True))
+    for i in range(2):
+        ref = bfv.modswitch(prm, bfv.square(prm, oracle_ct(prm, res[i]), rk))
+        assert (got[i] == bfv.ct_to_rns(prm, ref)).all()
