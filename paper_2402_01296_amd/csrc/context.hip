@@ -259,6 +259,8 @@ Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uin
   // the fused square keeps three register sets live; above N = 8192 it would spill
   c->fuse_square = logn <= 13;
   if (const char* env = std::getenv("BCN_FUSE_SQUARE")) c->fuse_square = logn <= 13 && std::atoi(env) != 0;
+  c->fuse_ks = logn <= 13 && alpha <= 2;
+  if (const char* env = std::getenv("BCN_FUSE_KS")) c->fuse_ks = logn <= 13 && alpha <= 2 && std::atoi(env) != 0;
   ntt_setup(*c);
   return c.release();
 }

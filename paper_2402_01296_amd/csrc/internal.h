@@ -92,6 +92,7 @@ struct Context {
 
   int ntt_loge = 0;                      // registers per thread = 2^ntt_loge in the transform
   bool fuse_square = true;               // square's transforms and tensor in one kernel
+  bool fuse_ks = true;                   // key switching's digits, transforms and products in one kernel
   std::vector<int> ntt_loge_options() const;
 
   int idQ(int i) const { return i; }
@@ -126,6 +127,11 @@ void ntt_setup(const Context& c);
 // in [n][2][b.n][N] coefficient form -> out [n][3][b.n][N]: the square's tensor
 // d0 = a0^2, d1 = 2 a0 a1, d2 = a1^2 in R_q for every limb, via fused transforms
 void square_transform_fused(const Context& c, const double* in, double* out, int n, const Basis& b, hipStream_t s);
+// key switching of n source polynomials (coefficient form, [level][N] at src + i*src_stride) with one
+// key ([dnum][2][L+K][N], transform domain); galois = k applies X -> X^k to the source first.
+// u [n][2][level+K][N] coefficient form (before the division by P).
+void ks_fused(const Context& c, const double* src, size_t src_stride, int n, int level, const double* key, int galois,
+              double* u, hipStream_t s);
 
 }  // namespace bcn
 

@@ -4,7 +4,7 @@
 // [0, q).  Per-coefficient kernels (base conversion, rounding, modulus
 // switching) give one thread one coefficient of one polynomial and read its
 // limbs at stride N, so consecutive threads touch consecutive words.
-#include "internal.h"
+#include "convert.h"
 
 namespace bcn {
 namespace {
@@ -12,36 +12,6 @@ namespace {
 constexpr int TPB = 256;
 
 inline unsigned nblocks(size_t work) { return (unsigned)((work + TPB - 1) / TPB); }
-
-// Mixed-radix digits of x over the first NS limbs of cv.src.
-template <int NS>
-__device__ __forceinline__ void garner(const double (&x)[NS], double (&v)[NS], const Conv& cv, const Mod* mods) {
-#pragma unroll
-  for (int i = 0; i < NS; ++i) {
-    const Mod mi = mods[cv.src[i]];
-    double u = x[i];
-#pragma unroll
-    for (int k = 0; k < i; ++k) u = mul_lazy(u - v[k], cv.ginv[i][k], mi);
-    v[i] = norm(u, mi);
-  }
-}
-
-// true when sum_{k<n} v_k M_k > (M-1)/2, i.e. the centred value is negative
-template <int NS>
-__device__ __forceinline__ bool above_half(const double (&v)[NS], int n, const Conv& cv, const Mod* mods) {
-  bool decided = false, neg = false;
-#pragma unroll
-  for (int k = NS - 1; k >= 0; --k) {
-    if (k < n) {
-      const double h = (mods[cv.src[k]].q - 1.0) * 0.5;
-      if (!decided && v[k] != h) {
-        neg = v[k] > h;
-        decided = true;
-      }
-    }
-  }
-  return neg;
-}
 
 // ------------------------------------------------------------------ MAC
 

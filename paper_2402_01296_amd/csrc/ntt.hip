@@ -12,7 +12,10 @@
 // N words.  Values grow additively inside the transform (|x| < (LOGN+1) q <
 // 2^45), which the lazy FP64 product tolerates; one reduction at the end
 // brings them back to [0, q).
-#include "internal.h"
+#include <algorithm>
+#include <string>
+
+#include "convert.h"
 
 namespace bcn {
 namespace {
@@ -175,7 +178,7 @@ k_ntt(double* __restrict__ data, Basis basis, Tables tb) {
 // goes through HBM.
 template <int LOGN, int LOGE>
 __global__ void __launch_bounds__(1 << (LOGN - LOGE))
-k_square_fused(const double* __restrict__ in, double* __restrict__ out, Basis basis, Tables tb) {
+k_square_fused(const double* __restrict__ in, double* __restrict__ out, Basis basis, Tables tb, int zero) {
   constexpr int N = 1 << LOGN;
   constexpr int E = 1 << LOGE;
   extern __shared__ double lds[];
@@ -197,7 +200,7 @@ k_square_fused(const double* __restrict__ in, double* __restrict__ out, Basis ba
     x0[i] = reduce(x0[i], m);
     x1[i] = reduce(x1[i], m);
   }
-#pragma unroll
+#pragma unroll 1
   for (int k = 0; k < 3; ++k) {
 #pragma unroll
     for (int i = 0; i < E; ++i) {
@@ -211,7 +214,8 @@ k_square_fused(const double* __restrict__ in, double* __restrict__ out, Basis ba
       }
     }
     double* dst = out + ((size_t)(ct * 3 + k) * nb + limb) * N;
-    run_pass<LOGN, LOGE, true, 0, true, false>(x, lds, nullptr, dst, iw, post, m, threadIdx.x);
+    // `zero` is 0 at run time: keeps the transform's address arithmetic inside the loop
+    run_pass<LOGN, LOGE, true, 0, true, false>(x, lds + (k & zero), nullptr, dst, iw, post, m, threadIdx.x + (k & zero));
   }
 }
 
@@ -225,6 +229,98 @@ void launch(const Context& c, double* data, int n_polys, const Basis& b, hipStre
   BCN_HIP(hipGetLastError());
 }
 
+// Key switching, fused: for one target limb (prime p of Q_level + P) of one
+// source polynomial x (coefficient form over Q_level), accumulates
+//   u_k = sum_j NTT(D_j mod p) * key_j[k]   (k = 0, 1)
+// over the digits D_j = lift_c([sigma(x)]_{Q_j}) and writes INTT(u_0), INTT(u_1).
+// The digits are formed in registers from the source residues (with the
+// Galois automorphism sigma folded into the gather; kinv = 1 means none), so
+// neither the digits nor the transform-domain products go through HBM.
+struct KsDigits {
+  const Conv* cv[8];   // digit j: source primes -> Q_level + P (used when the digit has 2 primes)
+  int lo[8];           // first Q limb of digit j
+  int na[8];           // primes of digit j present at this level
+};
+
+template <int LOGN, int LOGE, int NA, bool GAL>
+__global__ void __launch_bounds__(1 << (LOGN - LOGE))
+k_ks_fused(const double* __restrict__ src, size_t src_stride, int level, int L, int dnum, KsDigits dg,
+           const double* __restrict__ key, int kinv, double* __restrict__ u, Basis qp, Tables tb, int zero) {
+  using S = Shape<LOGN, LOGE>;
+  constexpr int N = S::N, E = S::E, T = S::T;
+  constexpr int C0 = S::C0;
+  constexpr int SMIN0 = N >> C0, SZ0 = 1 << C0, G0 = E >> C0;
+  extern __shared__ double lds[];
+  const int nb = qp.n;
+  const int ct = blockIdx.x / nb, limb = blockIdx.x % nb;
+  const int pid = qp.id[limb];
+  const Mod m = tb.mods[pid];
+  const double* fw = tb.fwd + (size_t)pid * N;
+  const double* iw = tb.inv + (size_t)pid * (N / 2);
+  const double* post = tb.post + (size_t)pid * N;
+  const double* xs = src + (size_t)ct * src_stride;
+  const int KL = L + (nb - level);
+  const int klimb = limb < level ? limb : L + (limb - level);
+  const int tid = threadIdx.x;
+  double acc0[E], acc1[E], x[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) acc0[i] = acc1[i] = 0.0;
+  for (int j = 0; j < dnum; ++j) {
+    const int lo = dg.lo[j], na = dg.na[j];
+    const bool inside = limb >= lo && limb < lo + na;
+    const Mod mq = tb.mods[lo];                      // Q prime ids equal their limb index
+#pragma unroll
+    for (int g = 0; g < G0; ++g)
+#pragma unroll
+      for (int jj = 0; jj < SZ0; ++jj) {
+        const int pos = g * T + tid + jj * SMIN0;
+        int sp = pos;
+        bool flip = false;
+        if (GAL) {
+          const int i2 = (int)(((long long)pos * kinv) & (2 * N - 1));
+          flip = i2 >= N;
+          sp = flip ? i2 - N : i2;
+        }
+        double v;
+        if (inside) {
+          v = xs[(size_t)limb * N + sp];
+        } else if (NA == 1 || na == 1) {
+          const double xv = xs[(size_t)lo * N + sp];
+          const double c = xv > (mq.q - 1.0) * 0.5 ? xv - mq.q : xv;   // |c| < q_j / 2 < p
+          v = c < 0.0 ? c + m.q : c;
+        } else {
+          const Conv& cv = *dg.cv[j];
+          const double xa[2] = {xs[(size_t)lo * N + sp], xs[(size_t)(lo + 1) * N + sp]};
+          double va[2];
+          garner<2>(xa, va, cv, tb.mods);
+          double a = mul_lazy(va[1], cv.pm[limb][0], m) + va[0];
+          if (above_half<2>(va, 2, cv, tb.mods)) a -= cv.Mmod[limb];
+          v = reduce(a, m);
+        }
+        if (flip) v = v == 0.0 ? 0.0 : m.q - v;
+        x[g * SZ0 + jj] = v;
+      }
+    // `zero` is 0 at run time; indexing through it keeps the per-pass address
+    // arithmetic inside the digit loop instead of hoisting it into registers
+    run_pass<LOGN, LOGE, false, 0, true, true>(x, lds + (j & zero), nullptr, nullptr, fw, post, m, tid + (j & zero));
+    const double* k0 = key + ((size_t)(j * 2) * KL + klimb) * N + (size_t)tid * E;
+    const double* k1 = key + ((size_t)(j * 2 + 1) * KL + klimb) * N + (size_t)tid * E;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      acc0[i] += mul_lazy(k0[i], x[i], m);
+      acc1[i] += mul_lazy(k1[i], x[i], m);
+    }
+  }
+  double* u0 = u + ((size_t)(ct * 2) * nb + limb) * N;
+  double* u1 = u + ((size_t)(ct * 2 + 1) * nb + limb) * N;
+#pragma unroll
+  for (int i = 0; i < E; ++i) x[i] = reduce(acc0[i], m);
+  run_pass<LOGN, LOGE, true, 0, true, false>(x, lds, nullptr, u0, iw, post, m, tid);
+#pragma unroll
+  for (int i = 0; i < E; ++i) x[i] = reduce(acc1[i], m);
+  run_pass<LOGN, LOGE, true, 0, true, false>(x, lds, nullptr, u1, iw, post, m, tid);
+}
+
 template <int LOGN, int LOGE>
 void set_attr() {
   const int lds = (1 << LOGN) * (int)sizeof(double);
@@ -232,6 +328,32 @@ void set_attr() {
   BCN_HIP(hipFuncSetAttribute((const void*)k_ntt<LOGN, LOGE, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
   BCN_HIP(hipFuncSetAttribute((const void*)k_square_fused<LOGN, LOGE>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               lds));
+  BCN_HIP(hipFuncSetAttribute((const void*)k_ks_fused<LOGN, LOGE, 1, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              lds));
+  BCN_HIP(hipFuncSetAttribute((const void*)k_ks_fused<LOGN, LOGE, 2, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              lds));
+  BCN_HIP(hipFuncSetAttribute((const void*)k_ks_fused<LOGN, LOGE, 1, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              lds));
+  BCN_HIP(hipFuncSetAttribute((const void*)k_ks_fused<LOGN, LOGE, 2, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              lds));
+}
+
+template <int LOGN, int LOGE>
+void launch_ks(const Context& c, const double* src, size_t stride, int n, int level, const KsDigits& dg,
+               const double* key, int kinv, double* u, const Basis& qp, hipStream_t s) {
+  constexpr int N = 1 << LOGN;
+  const unsigned blocks = (unsigned)n * qp.n;
+  if (blocks == 0) return;
+#define BCN_KSL(NA, GAL)                                                                                 \
+  hipLaunchKernelGGL((k_ks_fused<LOGN, LOGE, NA, GAL>), dim3(blocks), dim3(N >> LOGE), (size_t)N * sizeof(double), s, \
+                     src, stride, level, c.L, c.dnum(level), dg, key, kinv, u, qp, c.tab, 0)
+  if (c.alpha == 1) {
+    if (kinv == 1) BCN_KSL(1, false); else BCN_KSL(1, true);
+  } else {
+    if (kinv == 1) BCN_KSL(2, false); else BCN_KSL(2, true);
+  }
+#undef BCN_KSL
+  BCN_HIP(hipGetLastError());
 }
 
 template <int LOGN, int LOGE>
@@ -240,7 +362,7 @@ void launch_square(const Context& c, const double* in, double* out, int n, const
   const unsigned blocks = (unsigned)n * b.n;
   if (blocks == 0) return;
   hipLaunchKernelGGL((k_square_fused<LOGN, LOGE>), dim3(blocks), dim3(N >> LOGE), (size_t)N * sizeof(double), s, in,
-                     out, b, c.tab);
+                     out, b, c.tab, 0);
   BCN_HIP(hipGetLastError());
 }
 
@@ -300,6 +422,41 @@ void square_transform_fused(const Context& c, const double* in, double* out, int
     BCN_SQ_CASE(14, 4) BCN_SQ_CASE(14, 5)
 #undef BCN_SQ_CASE
     default: throw Error(-1, "unsupported ring degree / transform shape");
+  }
+}
+
+const Conv* conv_device(const Context& c, const std::string& key, const Conv& cv);
+
+void ks_fused(const Context& c, const double* src, size_t src_stride, int n, int level, const double* key, int galois,
+              double* u, hipStream_t s) {
+  if (c.alpha > 2) throw Error(-1, "fused key switching supports digits of at most two primes");
+  const int dnum = c.dnum(level);
+  if (dnum > 8) throw Error(-1, "too many digits");
+  const Basis qp = c.basis_QP(level);
+  KsDigits dg{};
+  for (int j = 0; j < dnum; ++j) {
+    const int lo = j * c.alpha, hi = std::min((j + 1) * c.alpha, level);
+    dg.lo[j] = lo;
+    dg.na[j] = hi - lo;
+    dg.cv[j] = nullptr;
+    if (hi - lo == 2) {
+      std::vector<int> src_ids, dst;
+      for (int i = lo; i < hi; ++i) src_ids.push_back(c.idQ(i));
+      for (int i = 0; i < qp.n; ++i) dst.push_back(qp.id[i]);
+      dg.cv[j] = conv_device(c, "ksd" + std::to_string(level) + "_" + std::to_string(j), make_conv(c, src_ids, dst));
+    }
+  }
+  const int kinv = galois == 1 ? 1 : (int)host::inv_pow2((uint64_t)galois, c.logn + 1);
+  // algorithmic traffic: digit sources (level limbs per target limb), two key limbs per digit, two outputs
+  ProfScope ps(c, "ks_fused", s, 8.0 * c.n * (double)n * qp.n * (level + 2.0 * dnum + 2));
+  // two accumulators and the working set stay in registers (sixteen residues per
+  // thread; spill-free up to N = 8192)
+  switch (c.logn) {
+    case 10: launch_ks<10, 4>(c, src, src_stride, n, level, dg, key, kinv, u, qp, s); break;
+    case 11: launch_ks<11, 4>(c, src, src_stride, n, level, dg, key, kinv, u, qp, s); break;
+    case 12: launch_ks<12, 4>(c, src, src_stride, n, level, dg, key, kinv, u, qp, s); break;
+    case 13: launch_ks<13, 4>(c, src, src_stride, n, level, dg, key, kinv, u, qp, s); break;
+    default: throw Error(-1, "fused key switching supports N <= 8192");
   }
 }
 

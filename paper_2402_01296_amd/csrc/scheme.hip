@@ -249,14 +249,18 @@ void square_relin(Context& c, const EvalKeys& ek, const double* in, double* out,
   }
   double* Z = ar.take((size_t)n * 3 * level * N);
   scale_round(c, Y, Z, n, level, s);
-  double* D = ar.take((size_t)n * dn * nbp * N);
-  decompose_modup(c, Z + 2 * level * N, (size_t)3 * level * N, D, n, level, s);
-  ntt_forward(c, D, n * dn, qp, s);
   double* U = ar.take((size_t)n * 2 * nbp * N);
   KeySel ks;
   ks.key1 = ek.relin;
-  ks_inner(c, D, 1, ks, n, level, U, s);
-  ntt_inverse(c, U, 2 * n, qp, s);
+  if (c.fuse_ks) {
+    ks_fused(c, Z + 2 * level * N, (size_t)3 * level * N, n, level, ek.relin, 1, U, s);
+  } else {
+    double* D = ar.take((size_t)n * dn * nbp * N);
+    decompose_modup(c, Z + 2 * level * N, (size_t)3 * level * N, D, n, level, s);
+    ntt_forward(c, D, n * dn, qp, s);
+    ks_inner(c, D, 1, ks, n, level, U, s);
+    ntt_inverse(c, U, 2 * n, qp, s);
+  }
   moddown(c, U, n, level, Z, 1, (size_t)3 * level * N, 1, ks, modsw, out, s);
 }
 
@@ -298,10 +302,14 @@ void rotate_sum(Context& c, const EvalKeys& ek, double* ct, int n, int level, in
     ks.key1 = ek.rot_key(r);
     ks.galois1 = galois_element(c, r);
     ks.kinv1 = galois_inverse(c, ks.galois1);
-    decompose_modup(c, ct + level * N, (size_t)2 * level * N, D, n, level, s);
-    ntt_forward(c, D, n * dn, qp, s);
-    ks_inner(c, D, 1, ks, n, level, U, s);
-    ntt_inverse(c, U, 2 * n, qp, s);
+    if (c.fuse_ks) {
+      ks_fused(c, ct + level * N, (size_t)2 * level * N, n, level, ks.key1, ks.galois1, U, s);
+    } else {
+      decompose_modup(c, ct + level * N, (size_t)2 * level * N, D, n, level, s);
+      ntt_forward(c, D, n * dn, qp, s);
+      ks_inner(c, D, 1, ks, n, level, U, s);
+      ntt_inverse(c, U, 2 * n, qp, s);
+    }
     moddown(c, U, n, level, ct, 1, (size_t)2 * level * N, 2, ks, false, R, s);
     add_inplace(c, ct, R, 2 * n, level, s);
   }

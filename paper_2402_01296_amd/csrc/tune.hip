@@ -77,6 +77,36 @@ std::string autotune_ntt(Context& c, hipStream_t s) {
     c.fuse_square = false;
   }
   report += std::string("square chosen fused=") + (c.fuse_square ? "1" : "0") + "\n";
+  // key switching: fused digits/transforms/products vs modup + transforms + inner product
+  if (c.logn <= 13 && c.alpha <= 2) {
+    const int level = c.L;
+    const Basis qp = c.basis_QP(level);
+    const int dn = c.dnum(level);
+    const int n = std::max(8, 2048 / (qp.n * (dn + 2)));
+    double* src = c.arena->take((size_t)n * level * c.n);
+    double* key = c.arena->take((size_t)dn * 2 * (c.L + c.K) * c.n);
+    double* D = c.arena->take((size_t)n * dn * qp.n * c.n);
+    double* U = c.arena->take((size_t)n * 2 * qp.n * c.n);
+    BCN_HIP(hipMemsetAsync(src, 0, (size_t)n * level * c.n * sizeof(double), s));
+    BCN_HIP(hipMemsetAsync(key, 0, (size_t)dn * 2 * (c.L + c.K) * c.n * sizeof(double), s));
+    KeySel ks;
+    ks.key1 = key;
+    const float unfused = time_ms(s, 5, [&] {
+      decompose_modup(c, src, (size_t)level * c.n, D, n, level, s);
+      ntt_forward(c, D, n * dn, qp, s);
+      ks_inner(c, D, 1, ks, n, level, U, s);
+      ntt_inverse(c, U, 2 * n, qp, s);
+    });
+    const float fused = time_ms(s, 5, [&] { ks_fused(c, src, (size_t)level * c.n, n, level, key, 1, U, s); });
+    char line[160];
+    std::snprintf(line, sizeof line, "key switch (%d polynomials, %d digits): fused %.3f ms, unfused %.3f ms\n", n, dn,
+                  fused, unfused);
+    report += line;
+    c.fuse_ks = fused < unfused;
+  } else {
+    c.fuse_ks = false;
+  }
+  report += std::string("key switch chosen fused=") + (c.fuse_ks ? "1" : "0") + "\n";
   return report;
 }
 

@@ -265,14 +265,16 @@ def test_transform_shapes_agree(pname, monkeypatch):
     assert all((o == outs[0]).all() for o in outs)
 
 
-@pytest.mark.parametrize("fuse", ["0", "1"])
-def test_square_paths_agree(fuse, monkeypatch):
-    """The fused and the unfused square transform segments give the same exact ciphertexts."""
+@pytest.mark.parametrize("fuse_sq,fuse_ks", [("0", "0"), ("1", "0"), ("0", "1"), ("1", "1")])
+@pytest.mark.parametrize("pname", ["t1k", "t2k"])
+def test_square_paths_agree(pname, fuse_sq, fuse_ks, monkeypatch):
+    """Fused and unfused square / key-switching paths give the oracle's exact ciphertexts."""
     torch_cuda()
     from oracle import params
     from paper_2402_01296_amd import bcn
-    monkeypatch.setenv("BCN_FUSE_SQUARE", fuse)
-    prm, ctx = context("t1k")
+    monkeypatch.setenv("BCN_FUSE_SQUARE", fuse_sq)
+    monkeypatch.setenv("BCN_FUSE_KS", fuse_ks)
+    prm, ctx = context(pname)
     s = synthetic.ternary_secret(31, prm.n)
     sk = ctx.secret_key(s)
     ek = ctx.eval_keys()
@@ -284,3 +286,30 @@ def test_square_paths_agree(fuse, monkeypatch):
     for i in range(2):
         ref = bfv.modswitch(prm, bfv.square(prm, oracle_ct(prm, res[i]), rk))
         assert (got[i] == bfv.ct_to_rns(prm, ref)).all()
+
+
+@pytest.mark.parametrize("fuse_ks", ["0", "1"])
+def test_rotate_sum_paths_agree(fuse_ks, monkeypatch):
+    """Rotate-and-sum through the fused key switch (automorphism folded into the digit gather)."""
+    torch_cuda()
+    from paper_2402_01296_amd import bcn
+    monkeypatch.setenv("BCN_FUSE_KS", fuse_ks)
+    prm, ctx = context("t2k")
+    s = synthetic.ternary_secret(33, prm.n)
+    sk = ctx.secret_key(s)
+    ek = ctx.eval_keys()
+    gk = {}
+    for r in (1, 2, 4):
+        a, e = key_randomness(prm, 33, 1000 + r)
+        ctx.keygen(sk, ek, bcn.BCN_KEY_ROTATION, r, np.stack(a), np.stack(e))
+        gk[r] = bfv.galois_key(prm, [int(v) for v in s], r, a, e)
+    for level in (prm.L, 3):
+        res = random_ct_residues(prm, level, 2, 90 + level)
+        ct = ctx.import_(res)
+        ctx.rotate_sum(ek, ct, 8)
+        got = ctx.export(ct)
+        for i in range(2):
+            c = oracle_ct(prm, res[i])
+            for r in (4, 2, 1):
+                c = bfv.add(prm, c, bfv.rotate(prm, c, r, gk[r]))
+            assert (got[i] == bfv.ct_to_rns(prm, c)).all(), "ct %d level %d" % (i, level)
