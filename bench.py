@@ -45,6 +45,12 @@ def parse():
                     help="only run a plain device copy of known size (for HBM counter scaling)")
     ap.add_argument("--kernel", choices=["ntt"], default=None,
                     help="microbenchmark one kernel on the workload's shapes instead of the whole step")
+    ap.add_argument("--mix", type=int, default=0,
+                    help="batched uneven workload: this many requests drawn from the three parameter sets")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving loop: Poisson arrivals at --rates, continuous batching vs unbatched")
+    ap.add_argument("--rates", default="50,200,800")
+    ap.add_argument("--serve-requests", type=int, default=2000)
     return ap.parse_args()
 
 
@@ -92,6 +98,99 @@ def ntt_microbench(args):
         out[k] = {"launches": la, "avg_launch_us": ms * 1000.0 / la, "gbs": by / (ms * 1e-3) / 1e9,
                   "frac_of_hbm_peak": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     print(json.dumps(out), flush=True)
+
+
+def mix_bench(args):
+    """Requests/s of the batched path (stacked per parameter set, concurrent streams, hipGraphs)
+    against the per-request launch loop on the same requests."""
+    import torch
+
+    from paper_2402_01296_amd.batch import Mix
+    t0 = time.perf_counter()
+    m = Mix(args.mix, autotune=not args.no_autotune)
+    setup = time.perf_counter() - t0
+    counts = {k: len(g) for k, g in m.groups.items()}
+    print("bench: mix ready %s in %.1fs" % (counts, setup), file=sys.stderr, flush=True)
+    chunks = {"cfg2": 8, "cfg3": 16}
+    # per-request loop
+    m.run_per_request()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        alone = m.run_per_request()
+    t_alone = (time.perf_counter() - t0) / args.steps
+    print("bench: per-request loop %.3f s" % t_alone, file=sys.stderr, flush=True)
+    m.run_batched(chunks)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = m.run_batched(chunks)
+    t_batched = (time.perf_counter() - t0) / args.steps
+    print("bench: batched %.3f s" % t_batched, file=sys.stderr, flush=True)
+    per_group = {}
+    for name, grp in m.groups.items():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(len(grp)):
+            grp.run_alone(k)
+        torch.cuda.synchronize()
+        ta = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        grp.run_batched(chunks.get(name))
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        per_group[name] = {"requests": len(grp), "alone_s": round(ta, 4), "batched_s": round(tb, 4)}
+    m.capture(chunks)
+    m.run_batched(graphs=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        outg = m.run_batched(graphs=True)
+    t_graph = (time.perf_counter() - t0) / args.steps
+    same = all(bool((alone[r] == m.request_output(outg, r)).all()) for r in range(len(m.names)))
+    n = len(m.names)
+    print(json.dumps({
+        "metric": "encrypted inferences/sec (batched uneven mix)",
+        "value": round(n / t_graph, 2), "unit": "requests/s", "n_gpus": 1, "steps": args.steps,
+        "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "%d requests drawn uniformly from (N, limbs) in {(4096,2), (8192,4), (16384,6)}"
+                               % n, "counts": counts, "chunks": chunks},
+        "per_request_loop": {"requests_per_s": round(n / t_alone, 2), "s_per_mix": round(t_alone, 4)},
+        "batched_eager": {"requests_per_s": round(n / t_batched, 2), "s_per_mix": round(t_batched, 4)},
+        "batched_graphs": {"requests_per_s": round(n / t_graph, 2), "s_per_mix": round(t_graph, 4)},
+        "speedup_vs_per_request": round(t_alone / t_graph, 2),
+        "per_group": per_group,
+        "bit_identical_alone_vs_batched": same,
+    }), flush=True)
+
+
+def serve_bench(args):
+    """p50/p99 latency and sustained throughput under Poisson arrivals, continuous batching
+    against the unbatched path (one request per launch group), same arrival trace."""
+    from paper_2402_01296_amd.serve import Server, poisson_arrivals
+    t0 = time.perf_counter()
+    srv = Server(autotune=not args.no_autotune, max_batch={"cfg1": 64, "cfg2": 8, "cfg3": 16})
+    print("bench: server ready in %.1fs, keys %.1f MB, per-request bytes %s" % (
+        time.perf_counter() - t0, srv.key_bytes / 1e6, {k: round(v / 1e6, 1) for k, v in srv.req_bytes.items()}),
+        file=sys.stderr, flush=True)
+    results = []
+    for rate in [float(r) for r in args.rates.split(",")]:
+        arr = poisson_arrivals(rate, args.serve_requests)
+        row = {"rate": rate, "requests": len(arr)}
+        for label, mb in (("batched", None), ("unbatched", {n: 1 for n in srv.mix})):
+            r = srv.serve(arr, max_batch=mb)
+            row[label] = {"p50_ms": round(r["p50_ms"], 3), "p99_ms": round(r["p99_ms"], 3),
+                          "throughput": round(r["throughput"], 1), "batches": r["batches"],
+                          "mean_batch": {k: round(v, 2) for k, v in r["mean_batch"].items()}}
+            print("bench: rate %g %s p50 %.2f ms p99 %.2f ms %.1f req/s" % (
+                rate, label, r["p50_ms"], r["p99_ms"], r["throughput"]), file=sys.stderr, flush=True)
+        results.append(row)
+    top = results[-1]["batched"]
+    print(json.dumps({
+        "metric": "encrypted inferences/sec + p50/p99 latency (serving)",
+        "value": top["throughput"], "unit": "requests/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "Poisson arrivals, uniform mix of (N, limbs) in {(4096,2), (8192,4), (16384,6)}, "
+                               "HBM budget 200 GB", "max_batch": srv.max_batch},
+        "rates": results,
+    }), flush=True)
 
 
 def cpu_baseline(workload: str):
@@ -172,6 +271,12 @@ def main():
         return
     if args.kernel == "ntt":
         ntt_microbench(args)
+        return
+    if args.mix:
+        mix_bench(args)
+        return
+    if args.serve:
+        serve_bench(args)
         return
     from paper_2402_01296_amd.workload import GpuSession
     from synthetic import workloads as W

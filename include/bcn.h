@@ -201,6 +201,14 @@ int bcn_layer_shape(const bcn_layer* layer, int* n_in, int* n_out, int* level_ou
  * features: device float or NULL when the layer has none. */
 int bcn_layer_eval(bcn_context* ctx, const bcn_eval_keys* ek, const bcn_layer* layer, const double* in,
                    double* out, const float* features, bcn_stream stream);
+/* The same layer over n_requests independent requests in one set of launches:
+ * in [n_requests][n_in][2][level][N], out [n_requests][n_out][2][level_out][N],
+ * features [n_requests][...] in the per-request layout above.  Request r's
+ * results are bit-identical to evaluating it alone.  Issues no host
+ * synchronisation, allocation (after a first call of the same shape) or
+ * memset, so it can be captured into a hipGraph. */
+int bcn_layer_eval_batch(bcn_context* ctx, const bcn_eval_keys* ek, const bcn_layer* layer, const double* in,
+                         double* out, const float* features, int n_requests, bcn_stream stream);
 
 /* ---- tuning ---- */
 /* Times the candidate transform shapes (registers per thread, hence LDS passes

@@ -72,6 +72,7 @@ _SIGS = {
     "bcn_layer_rotation_steps": (_I, [_VP, _I32P, _I]),
     "bcn_layer_shape": (_I, [_VP, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)]),
     "bcn_layer_eval": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "bcn_layer_eval_batch": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _I, _VP]),
     "bcn_profile_enable": (_I, [_VP, _I]),
     "bcn_autotune": (_I, [_VP, C.c_char_p, _I, _VP]),
     "bcn_layer_autotune": (_I, [_VP, _VP, C.c_char_p, _I, _VP]),
@@ -359,6 +360,15 @@ class Layer:
             out = self.ctx.empty_ct(self.n_out, self.level_out)
         fp = _dptr(features) if features is not None else None
         _check(lib().bcn_layer_eval(self.ctx.h, ek.h, self.h, _dptr(ct), _dptr(out), fp, _stream()))
+        return out
+
+    def batch(self, ek, ct, n_requests, features=None, out=None):
+        """R requests at once: ct [R*n_in][2][level][N] -> [R*n_out][2][level_out][N]."""
+        if out is None:
+            out = self.ctx.empty_ct(n_requests * self.n_out, self.level_out)
+        fp = _dptr(features) if features is not None else None
+        _check(lib().bcn_layer_eval_batch(self.ctx.h, ek.h, self.h, _dptr(ct), _dptr(out), fp, n_requests,
+                                          _stream()))
         return out
 
     def __del__(self):

@@ -478,16 +478,23 @@ int bcn_layer_shape(const bcn_layer* layer, int* n_in, int* n_out, int* level_ou
 
 int bcn_layer_eval(bcn_context* ctx, const bcn_eval_keys* ek, const bcn_layer* layer, const double* in, double* out,
                    const float* features, bcn_stream stream) {
+  return bcn_layer_eval_batch(ctx, ek, layer, in, out, features, 1, stream);
+}
+
+int bcn_layer_eval_batch(bcn_context* ctx, const bcn_eval_keys* ek, const bcn_layer* layer, const double* in,
+                         double* out, const float* features, int n_requests, bcn_stream stream) {
   return guard([&] {
     bcn::Context& c = ctxof(ctx);
     check_ptr(ek, "eval keys");
     check_ptr(layer, "layer");
+    if (n_requests < 0) throw bcn::Error(BCN_ERR_INVALID, "negative request count");
+    if (n_requests == 0) return;
     check_ptr(in, "in");
     check_ptr(out, "out");
     const bcn::Layer& L = *layer->l;
     if (L.square && !ek->k->relin) throw bcn::Error(BCN_ERR_KEY, "missing relinearisation key");
     for (int st : L.all_steps) ek->k->rot_key(st);
-    bcn::layer_eval(c, *ek->k, L, in, out, features, (hipStream_t)stream);
+    bcn::layer_eval(c, *ek->k, L, in, out, features, (hipStream_t)stream, n_requests);
   });
 }
 

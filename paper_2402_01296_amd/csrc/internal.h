@@ -164,7 +164,9 @@ struct MacPlan {
   int* tile_cols = nullptr;     // device: columns with a nonzero weight in the tile
   int chunk = 0;                // inputs between two partial reductions
 };
-void mac(const Context& c, const MacPlan& p, const double* in, double* out, int level, hipStream_t s);
+// requests > 1: independent requests at in + r*in_req, out + r*out_req (doubles)
+void mac(const Context& c, const MacPlan& p, const double* in, double* out, int level, hipStream_t s, int requests = 1,
+         size_t in_req = 0, size_t out_req = 0);
 
 // c0 of each ciphertext += Delta(m_i), m_i in [0, t) coefficient form, [n][N]
 void add_delta(const Context& c, double* ct, int n, int level, const double* m, hipStream_t s);
@@ -173,7 +175,7 @@ void mul_plain_ntt(const Context& c, const double* in, double* out, int n, int l
                    bool per_ct, hipStream_t s);
 // out[k] = sum_c in[c] (.) pt[k][c]  (NTT domain); pt [n_out][n_in][level][N]
 void ptvec_mac_ntt(const Context& c, const double* in, int n_in, double* out, int n_out, int level,
-                   const double* pt, hipStream_t s);
+                   const double* pt, hipStream_t s, int requests = 1);
 // square in the NTT domain over `nb` limbs: [n][2][nb][N] -> [n][3][nb][N]
 void tensor_square(const Context& c, const double* in, double* out, int n, const Basis& b, hipStream_t s);
 // exact centred extension of [n][2][level][N] (coeff) into [n][2][level+m][N] over Q_level then B
@@ -229,12 +231,15 @@ void pointwise_mul(const Context& c, const double* a, const double* b, double* o
                    bool b_shared, hipStream_t s);
 void small_to_rns(const Context& c, const int8_t* e, double* out, int n, const Basis& b, hipStream_t s);
 void u64_to_f64(const uint64_t* in, double* out, size_t count, hipStream_t s);
+// graph-capturable fills and strided copies (kernels, not memset / memcpy nodes)
+void fill(double* p, size_t count, double v, hipStream_t s);
+void copy_rows(const double* src, size_t spitch, double* dst, size_t dpitch, size_t width, size_t rows, hipStream_t s);
 void f64_to_u64(const double* in, uint64_t* out, size_t count, hipStream_t s);
 // out = -x + e (+ g * sp on the limbs in [g_lo, g_hi)) elementwise over [limbs][N]; g_val per limb
 void combine_keypart(const Context& c, const double* x, const double* e, const double* sp, double* out,
                      const Basis& b, int g_lo, int g_hi, const double* g_val_host, hipStream_t s);
 // quantise FP32 features: q(f) = clamp(rint(8 f), -127, 127), gathered into slot vectors.
-// mode 0 (batch packing): slots[p][b] = q(f[b*stride_b + p]) for b < batch;
+// mode 0 (batch packing): plaintext p = r*stride_b + j, slots[p][b] = q(f[(r*batch + b)*stride_b + j]);
 // mode 1 (HW packing): slots[p][slot_of[k]] = q(f[p*per + k]) for k < per.
 void quantise_features(const Context& c, const float* f, int n_pt, int mode, int batch, int stride_b,
                        const int* slot_of, int per, float scale, int clampv, int64_t* slots, hipStream_t s);

@@ -24,9 +24,12 @@ template <int TO>
 __global__ void __launch_bounds__(TPB)
 k_mac(const double* __restrict__ in, double* __restrict__ out, int words, int logn, int level,
       const double* __restrict__ Wp, const int* __restrict__ rows, const int* __restrict__ tptr,
-      const int* __restrict__ tcols, int chunk, Basis b, const Mod* __restrict__ mods) {
+      const int* __restrict__ tcols, int chunk, Basis b, const Mod* __restrict__ mods, size_t in_req,
+      size_t out_req) {
   const int w = blockIdx.x * TPB + threadIdx.x;
   if (w >= words) return;
+  in += blockIdx.z * in_req;     // request blockIdx.z of a batch of independent requests
+  out += blockIdx.z * out_req;
   const int tile = blockIdx.y;
   const Mod m = mods[b.id[(w >> logn) % level]];
   const double halfq = (m.q - 1.0) * 0.5;
@@ -111,17 +114,19 @@ __global__ void k_mul_plain(const double* __restrict__ in, double* __restrict__ 
 
 __global__ void k_ptvec_mac(const double* __restrict__ in, int n_in, double* __restrict__ out, int n_out,
                             int level, int logn, const double* __restrict__ pt, Basis b,
-                            const Mod* __restrict__ mods) {
+                            const Mod* __restrict__ mods, int requests) {
   const size_t N = (size_t)1 << logn;
   const size_t words = 2 * level * N;
   const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
-  if (idx >= (size_t)n_out * words) return;
-  const size_t ko = idx / words, w = idx % words;
+  if (idx >= (size_t)requests * n_out * words) return;
+  const size_t kr = idx / words, w = idx % words;
+  const size_t req = kr / n_out, ko = kr % n_out;
   const size_t lk = w % (level * N);
   const Mod m = mods[b.id[lk >> logn]];
+  const double* inr = in + req * n_in * words;
   double acc = 0.0;
   for (int cc = 0; cc < n_in; ++cc) {
-    acc += mul_lazy(in[(size_t)cc * words + w], pt[(ko * n_in + cc) * level * N + lk], m);
+    acc += mul_lazy(inr[(size_t)cc * words + w], pt[(ko * n_in + cc) * level * N + lk], m);
     if ((cc & 1023) == 1023) acc = reduce_lazy(acc, m);
   }
   out[idx] = reduce(acc, m);
@@ -479,6 +484,19 @@ __global__ void k_add_inplace(double* __restrict__ a, const double* __restrict__
   a[idx] = add_mod(a[idx], b[idx], m);
 }
 
+__global__ void k_fill(double* __restrict__ p, size_t count, double v) {
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx < count) p[idx] = v;
+}
+
+__global__ void k_copy(const double* __restrict__ src, double* __restrict__ dst, size_t width, size_t spitch,
+                       size_t dpitch, size_t rows) {
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx >= width * rows) return;
+  const size_t r = idx / width, c = idx % width;
+  dst[r * dpitch + c] = src[r * spitch + c];
+}
+
 __global__ void k_u64_to_f64(const uint64_t* __restrict__ in, double* __restrict__ out, size_t count) {
   const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
   if (idx < count) out[idx] = (double)in[idx];
@@ -508,9 +526,11 @@ __global__ void k_quantise(const float* __restrict__ f, int n_pt, int mode, int 
   const size_t N = (size_t)1 << logn;
   const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
   if (mode == 0) {
+    // plaintext p = r * stride_b + j of request r reads f[r][b][j] (image-major features)
     if (idx >= (size_t)n_pt * batch) return;
     const size_t p = idx / batch, bi = idx % batch;
-    float q = rintf(scale * f[bi * (size_t)stride_b + p]);
+    const size_t r = p / stride_b, j = p % stride_b;
+    float q = rintf(scale * f[(r * batch + bi) * (size_t)stride_b + j]);
     q = fminf(fmaxf(q, (float)-clampv), (float)clampv);
     slots[p * N + bi] = (int64_t)q;
   } else {
@@ -536,16 +556,17 @@ __global__ void k_quantise(const float* __restrict__ f, int n_pt, int mode, int 
 
 // ------------------------------------------------------------------ host wrappers
 
-void mac(const Context& c, const MacPlan& p, const double* in, double* out, int level, hipStream_t s) {
+void mac(const Context& c, const MacPlan& p, const double* in, double* out, int level, hipStream_t s, int requests,
+         size_t in_req, size_t out_req) {
   const int words = 2 * level * c.n;
-  if (p.n_out == 0) return;
-  ProfScope ps(c, "mac", s, 8.0 * words * ((double)p.n_in + p.n_out));
-  dim3 grid(nblocks(words), p.n_tiles);
+  if (p.n_out == 0 || requests == 0) return;
+  ProfScope ps(c, "mac", s, 8.0 * words * ((double)p.n_in + p.n_out) * requests);
+  dim3 grid(nblocks(words), p.n_tiles, requests);
   const Basis b = c.basis_Q(level);
   switch (p.tile) {
 #define BCN_MAC_CASE(TO) \
   case TO: hipLaunchKernelGGL(k_mac<TO>, grid, dim3(TPB), 0, s, in, out, words, c.logn, level, p.W, p.rows, \
-                              p.tile_ptr, p.tile_cols, p.chunk, b, c.tab.mods); break;
+                              p.tile_ptr, p.tile_cols, p.chunk, b, c.tab.mods, in_req, out_req); break;
     BCN_MAC_CASE(1) BCN_MAC_CASE(2) BCN_MAC_CASE(4) BCN_MAC_CASE(8) BCN_MAC_CASE(16) BCN_MAC_CASE(32)
     BCN_MAC_CASE(64)
 #undef BCN_MAC_CASE
@@ -579,10 +600,10 @@ void mul_plain_ntt(const Context& c, const double* in, double* out, int n, int l
 }
 
 void ptvec_mac_ntt(const Context& c, const double* in, int n_in, double* out, int n_out, int level, const double* pt,
-                   hipStream_t s) {
-  if (n_out == 0) return;
-  hipLaunchKernelGGL(k_ptvec_mac, dim3(nblocks((size_t)n_out * 2 * level * c.n)), dim3(TPB), 0, s, in, n_in, out,
-                     n_out, level, c.logn, pt, c.basis_Q(level), c.tab.mods);
+                   hipStream_t s, int requests) {
+  if (n_out == 0 || requests == 0) return;
+  hipLaunchKernelGGL(k_ptvec_mac, dim3(nblocks((size_t)requests * n_out * 2 * level * c.n)), dim3(TPB), 0, s, in, n_in,
+                     out, n_out, level, c.logn, pt, c.basis_Q(level), c.tab.mods, requests);
   BCN_HIP(hipGetLastError());
 }
 
@@ -783,6 +804,18 @@ void add_inplace(const Context& c, double* a, const double* b, int npoly, int le
   if (count == 0) return;
   hipLaunchKernelGGL(k_add_inplace, dim3(nblocks(count)), dim3(TPB), 0, s, a, b, count, level, c.logn, c.basis_Q(level),
                      c.tab.mods);
+  BCN_HIP(hipGetLastError());
+}
+
+void fill(double* p, size_t count, double v, hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_fill, dim3(nblocks(count)), dim3(TPB), 0, s, p, count, v);
+  BCN_HIP(hipGetLastError());
+}
+
+void copy_rows(const double* src, size_t spitch, double* dst, size_t dpitch, size_t width, size_t rows, hipStream_t s) {
+  if (width == 0 || rows == 0) return;
+  hipLaunchKernelGGL(k_copy, dim3(nblocks(width * rows)), dim3(TPB), 0, s, src, dst, width, spitch, dpitch, rows);
   BCN_HIP(hipGetLastError());
 }
 

@@ -33,6 +33,6 @@ Layer* layer_create(Context& c, const bcn_layer_desc& d, int level);
 std::string autotune_ntt(Context& c, hipStream_t s);
 std::string autotune_layer_mac(Context& c, Layer& L, hipStream_t s);
 void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, double* out, const float* features,
-                hipStream_t s);
+                hipStream_t s, int requests = 1);
 
 }  // namespace bcn

@@ -164,62 +164,64 @@ Layer* layer_create(Context& c, const bcn_layer_desc& d, int level) {
 }
 
 void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, double* out, const float* features,
-                hipStream_t s) {
+                hipStream_t s, int R) {
+  // R independent requests: in [R][n_in][2][level][N] -> out [R][n_out][2][level_out][N]; every step
+  // below runs once over all R requests' ciphertexts (one launch per kernel).
   Arena& ar = *c.arena;
   const size_t N = c.n;
   const int level = L.level;
   const size_t ctw = (size_t)2 * level * N;
+  const int nin = R * L.n_in, nout = R * L.n_out;
   if (L.features && !features) throw Error(-1, "layer expects features");
   const bool direct = !L.square && !L.features && L.span == 0 && L.packing == BCN_PACK_BATCH;
-  double* A = direct ? out : ar.take((size_t)L.n_out * ctw);
+  double* A = direct ? out : ar.take((size_t)nout * ctw);
   if (L.packing == BCN_PACK_BATCH) {
-    mac(c, L.mac, in, A, level, s);
+    mac(c, L.mac, in, A, level, s, R, (size_t)L.n_in * ctw, (size_t)L.n_out * ctw);
   } else if (L.kind == BCN_CONV2D) {
-    // taps [n_in][k2]: tap 0 = input, taps 1.. = hoisted rotations
-    double* taps = ar.take((size_t)L.n_in * L.k2 * ctw);
-    BCN_HIP(hipMemcpy2DAsync(taps, L.k2 * ctw * sizeof(double), in, ctw * sizeof(double), ctw * sizeof(double), L.n_in,
-                             hipMemcpyDeviceToDevice, s));
-    rotate_hoisted(c, ek, in, L.n_in, level, L.steps, taps + ctw, s, (int)L.steps.size(), L.k2 * ctw);
-    mac(c, L.mac, taps, A, level, s);
-    ntt_forward(c, A, 2 * L.n_out, c.basis_Q(level), s);
-    mul_plain_ntt(c, A, A, L.n_out, level, L.mask_hat, false, s);
-    ntt_inverse(c, A, 2 * L.n_out, c.basis_Q(level), s);
+    // taps [R*n_in][k2]: tap 0 = the input, taps 1.. = hoisted rotations
+    double* taps = ar.take((size_t)nin * L.k2 * ctw);
+    copy_rows(in, ctw, taps, L.k2 * ctw, ctw, nin, s);
+    rotate_hoisted(c, ek, in, nin, level, L.steps, taps + ctw, s, (int)L.steps.size(), L.k2 * ctw);
+    mac(c, L.mac, taps, A, level, s, R, (size_t)L.n_in * L.k2 * ctw, (size_t)L.n_out * ctw);
+    ntt_forward(c, A, 2 * nout, c.basis_Q(level), s);
+    mul_plain_ntt(c, A, A, nout, level, L.mask_hat, false, s);
+    ntt_inverse(c, A, 2 * nout, c.basis_Q(level), s);
   } else {
-    double* H = ar.take((size_t)L.n_in * ctw);
-    BCN_HIP(hipMemcpyAsync(H, in, (size_t)L.n_in * ctw * sizeof(double), hipMemcpyDeviceToDevice, s));
-    ntt_forward(c, H, 2 * L.n_in, c.basis_Q(level), s);
-    ptvec_mac_ntt(c, H, L.n_in, A, L.n_out, level, L.ptv_hat, s);
-    ntt_inverse(c, A, 2 * L.n_out, c.basis_Q(level), s);
+    double* H = ar.take((size_t)nin * ctw);
+    copy_rows(in, 0, H, 0, (size_t)nin * ctw, 1, s);
+    ntt_forward(c, H, 2 * nin, c.basis_Q(level), s);
+    ptvec_mac_ntt(c, H, L.n_in, A, L.n_out, level, L.ptv_hat, s, R);
+    ntt_inverse(c, A, 2 * nout, c.basis_Q(level), s);
   }
   if (L.features) {
-    int64_t* sl = reinterpret_cast<int64_t*>(ar.take((size_t)L.n_out * N));
-    BCN_HIP(hipMemsetAsync(sl, 0, (size_t)L.n_out * N * sizeof(int64_t), s));
+    int64_t* sl = reinterpret_cast<int64_t*>(ar.take((size_t)nout * N));
+    fill(reinterpret_cast<double*>(sl), (size_t)nout * N, 0.0, s);   // all-zero bits = int64 zeros
     if (L.packing == BCN_PACK_BATCH)
-      quantise_features(c, features, L.n_out, 0, L.batch, L.stride_b, nullptr, 0, L.fscale, L.fclamp, sl, s);
+      quantise_features(c, features, nout, 0, L.batch, L.stride_b, nullptr, 0, L.fscale, L.fclamp, sl, s);
     else
-      quantise_features(c, features, L.n_out, 1, 0, 0, L.slot_of, L.per, L.fscale, L.fclamp, sl, s);
-    double* m = ar.take((size_t)L.n_out * N);
-    encode_device(c, sl, m, L.n_out, s);
-    add_delta(c, A, L.n_out, level, m, s);
+      quantise_features(c, features, nout, 1, 0, 0, L.slot_of, L.per, L.fscale, L.fclamp, sl, s);
+    double* m = ar.take((size_t)nout * N);
+    encode_device(c, sl, m, nout, s);
+    add_delta(c, A, nout, level, m, s);
   }
   if (direct) return;
   const bool hw_dense = L.packing == BCN_PACK_HW && L.kind == BCN_DENSE;
   if (hw_dense) {
     // rotate-and-sum before the (optional) square
-    rotate_sum(c, ek, A, L.n_out, level, L.span, s);
+    rotate_sum(c, ek, A, nout, level, L.span, s);
     if (L.square) {
-      square_relin(c, ek, A, out, L.n_out, level, L.modsw, s);
+      square_relin(c, ek, A, out, nout, level, L.modsw, s);
     } else {
-      BCN_HIP(hipMemcpyAsync(out, A, (size_t)L.n_out * ctw * sizeof(double), hipMemcpyDeviceToDevice, s));
+      copy_rows(A, 0, out, 0, (size_t)nout * ctw, 1, s);
     }
     return;
   }
   if (L.square) {
-    square_relin(c, ek, A, out, L.n_out, level, L.modsw, s);
+    square_relin(c, ek, A, out, nout, level, L.modsw, s);
   } else {
-    BCN_HIP(hipMemcpyAsync(out, A, (size_t)L.n_out * ctw * sizeof(double), hipMemcpyDeviceToDevice, s));
+    copy_rows(A, 0, out, 0, (size_t)nout * ctw, 1, s);
   }
-  if (L.span > 0) rotate_sum(c, ek, out, L.n_out, L.level_out, L.span, s);
+  if (L.span > 0) rotate_sum(c, ek, out, nout, L.level_out, L.span, s);
 }
 
 }  // namespace bcn

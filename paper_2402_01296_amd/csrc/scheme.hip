@@ -161,7 +161,7 @@ void keygen(Context& c, const SecretKey& sk, EvalKeys& ek, int kind, int step, c
 }
 
 void encode_device(Context& c, const int64_t* slots_dev, double* m, int n, hipStream_t s) {
-  BCN_HIP(hipMemsetAsync(m, 0, (size_t)n * c.n * sizeof(double), s));
+  fill(m, (size_t)n * c.n, 0.0, s);
   slots_to_tdomain(c, slots_dev, m, n, s);
   ntt_inverse(c, m, n, basis_t(c), s);
 }

@@ -53,7 +53,12 @@ def layer_descs(name: str):
 
 
 class GpuSession:
-    """Keys, encryptions and evaluation of one workload on the GPU."""
+    """Keys, encryptions and evaluation of one workload on the GPU.
+
+    The model part (context, keys, prepared layers) is shared by every request
+    of the workload; request_inputs() / encrypt_request() give independent
+    requests their own images, features and encryption randomness.
+    """
 
     def __init__(self, name: str, seeds=None, device: int = 0):
         import torch
@@ -146,6 +151,57 @@ class GpuSession:
         for li, lay in enumerate(self.layers[:upto]):
             ct = lay(self.ek, ct, self.features[li])
         return ct
+
+    # ------------------------------------------------------------ independent requests
+    def request_seeds(self, rid: int) -> dict:
+        """Seeds of request rid: the model's keys and weights, the request's own data."""
+        s = dict(self.seeds)
+        s.update(images=100000 + rid, features=200000 + rid, enc=300000 + rid)
+        return s
+
+    def request_inputs(self, rid: int):
+        return W.make_inputs(self.name, self.request_seeds(rid))
+
+    def request_slots(self, inputs) -> np.ndarray:
+        saved = self.inputs
+        self.inputs = inputs
+        try:
+            return self.input_slots()
+        finally:
+            self.inputs = saved
+
+    def request_features(self, inputs):
+        """Device feature tensors of one request, per layer (None where a layer has none)."""
+        out = []
+        for f in inputs["features"]:
+            if f is None:
+                out.append(None)
+            elif self.wl["packing"] == "batch":
+                out.append(self.torch.from_numpy(np.ascontiguousarray(f.reshape(f.shape[0], -1))).cuda())
+            else:
+                out.append(self.torch.from_numpy(np.ascontiguousarray(f)).cuda())
+        return out
+
+    def encrypt_request(self, rid: int, inputs=None):
+        inputs = self.request_inputs(rid) if inputs is None else inputs
+        slots = self.request_slots(inputs)
+        seeds = self.request_seeds(rid)
+        q = self.ctx.q
+        a = np.stack([synthetic.uniform_residues(seeds["enc"], "enc_a", (i,), q, self.n) for i in range(len(slots))])
+        e = np.stack([synthetic.gaussian_error(seeds["enc"], "enc_e", (i,), self.n) for i in range(len(slots))])
+        return self.ctx.encrypt(self.sk, slots, a, e)
+
+    def run_batch(self, ct, features, n_requests):
+        """All layers over n_requests stacked requests (features: per layer, stacked or None)."""
+        for li, lay in enumerate(self.layers):
+            ct = lay.batch(self.ek, ct, n_requests, features[li])
+        return ct
+
+    def n_inputs(self) -> int:
+        return self.layers[0].n_in
+
+    def n_outputs(self) -> int:
+        return self.layers[-1].n_out
 
     def output_values(self, ct) -> np.ndarray:
         vals = self.ctx.decrypt(self.sk, ct)
