@@ -24,6 +24,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP64 vector peak in lane operations: 256 CUs x 64 FP64 lanes per clock x 2.4 GHz (the published
+# 78.6 TFLOP/s counts each fused multiply-add as two flops; every FP64 instruction here counts one)
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 WORKLOAD_TEXT = {
     "cfg2": "MNIST-shaped slot-batched inference: N=8192, 4x36-bit primes, t=1032193, 8192 images/batch, "
             "conv5x5s2(5)+features+square, dense100+square, dense10",
@@ -94,9 +97,10 @@ def ntt_microbench(args):
     limb_ntts = 2 * polys * nl * args.steps
     out = {"kernel": "ntt", "n": spec["n"], "limbs_per_launch": polys * nl, "steps": args.steps,
            "limb_ntts_per_s": limb_ntts / total, "tuning": tuning}
-    for k, (la, ms, by) in prof.items():
+    for k, (la, ms, by, ops) in prof.items():
         out[k] = {"launches": la, "avg_launch_us": ms * 1000.0 / la, "gbs": by / (ms * 1e-3) / 1e9,
-                  "frac_of_hbm_peak": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                  "frac_of_hbm_peak": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                  "fp64_tops": ops / (ms * 1e-3) / 1e12, "frac_of_alu_peak": ops / (ms * 1e-3) / 1e12 / ALU_PEAK_TOPS}
     print(json.dumps(out), flush=True)
 
 
@@ -321,27 +325,40 @@ def main():
     inst_ms = (time.perf_counter() - t0) * 1000.0 / args.steps
     g.ctx.profile(False)
     prof = g.ctx.profile_read()
-    kern = {k: dict(launches=v[0], ms=v[1], bytes=v[2], gbs=(v[2] / (v[1] * 1e-3) / 1e9) if v[1] > 0 else 0.0)
-            for k, v in prof.items()}
+    kern = {}
+    for k, (la, ms, by, ops) in prof.items():
+        sec = ms * 1e-3
+        kern[k] = dict(launches=la, ms=ms, bytes=by, ops=ops,
+                       gbs=by / sec / 1e9 if sec > 0 else 0.0, tops=ops / sec / 1e12 if sec > 0 else 0.0)
     dom = max(kern, key=lambda k: kern[k]["ms"])
     d = kern[dom]
-    achieved = d["gbs"]
-    ntt_bytes = sum(kern[k]["bytes"] for k in kern if k.startswith("ntt"))
-    ntt_ms = sum(kern[k]["ms"] for k in kern if k.startswith("ntt"))
-    roof = {
-        "kernel": dom,
-        "bound": "hbm",
-        "achieved": round(achieved, 1),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4),
+    # the kernel's bound is the larger of its two floors: algorithmic bytes at the HBM peak and
+    # algorithmic FP64 operations at the vector peak
+    hbm_floor = d["bytes"] / (HBM_PEAK_GBS * 1e9)
+    alu_floor = d["ops"] / (ALU_PEAK_TOPS * 1e12)
+    la = max(1, d["launches"])
+    if alu_floor > hbm_floor:
+        roof = {"kernel": dom, "bound": "alu", "achieved": round(d["tops"], 3), "peak": round(ALU_PEAK_TOPS, 3),
+                "unit": "T fp64 op/s", "frac": round(d["tops"] / ALU_PEAK_TOPS, 4)}
+    else:
+        roof = {"kernel": dom, "bound": "hbm", "achieved": round(d["gbs"], 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(d["gbs"] / HBM_PEAK_GBS, 4)}
+    roof.update({
         "traffic": None,
         "launches": d["launches"],
-        "avg_launch_us": round(d["ms"] * 1000.0 / max(1, d["launches"]), 2),
-        "bytes_per_launch": d["bytes"] / max(1, d["launches"]),
-    }
+        "avg_launch_us": round(d["ms"] * 1000.0 / la, 2),
+        "bytes_per_launch": d["bytes"] / la,
+        "fp64_ops_per_launch": d["ops"] / la,
+        "hbm_gbs": round(d["gbs"], 1),
+        "hbm_frac": round(d["gbs"] / HBM_PEAK_GBS, 4),
+        "alu_frac": round(d["tops"] / ALU_PEAK_TOPS, 4),
+    })
+    ntt_bytes = sum(kern[k]["bytes"] for k in kern if k.startswith("ntt"))
+    ntt_ms = sum(kern[k]["ms"] for k in kern if k.startswith("ntt"))
     verified = None
-    if not args.no_verify:
+    if not wl.get("decrypts", True):
+        verified = "n/a: two 30-bit limbs leave no noise budget after the square, so the output does not decrypt"
+    elif not args.no_verify:
         from oracle import network   # test-only check of this run's outputs
         vals = g.output_values(out)
         want = network.run_mod_t(args.workload, g.inputs, g.ctx.t)
@@ -368,7 +385,8 @@ def main():
                 "ms_per_step": round(ntt_ms / args.steps, 3)},
         "roofline": roof,
         "kernels": {k: {"ms_per_step": round(v["ms"] / args.steps, 3), "launches": v["launches"],
-                        "gbs": round(v["gbs"], 1)} for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])},
+                        "gbs": round(v["gbs"], 1), "fp64_tops": round(v["tops"], 3)}
+                    for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])},
         "instrumented_ms_per_step": round(inst_ms, 3),
         "autotune": [ln for ln in (tuning or "").splitlines() if "chosen" in ln],
         "verified_vs_integer_network": verified,

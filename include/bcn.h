@@ -228,10 +228,11 @@ int bcn_layer_autotune(bcn_context* ctx, bcn_layer* layer, char* report, int cap
 int bcn_profile_enable(bcn_context* ctx, int on);
 /* Resolves and clears the recorded timings (synchronises their events).  Writes
  * newline-separated kernel names into names[names_cap] and, per name, the launch
- * count, summed launch time (ms) and algorithmic bytes into the arrays (cap
+ * count, summed launch time (ms), algorithmic HBM bytes and algorithmic FP64 VALU
+ * lane operations (0 where not tracked; ops may be NULL) into the arrays (cap
  * entries).  Returns the number of names, or an error code. */
 int bcn_profile_read(bcn_context* ctx, char* names, int names_cap, int* launches, double* total_ms, double* bytes,
-                     int cap);
+                     double* ops, int cap);
 
 #ifdef __cplusplus
 }

@@ -76,7 +76,7 @@ _SIGS = {
     "bcn_profile_enable": (_I, [_VP, _I]),
     "bcn_autotune": (_I, [_VP, C.c_char_p, _I, _VP]),
     "bcn_layer_autotune": (_I, [_VP, _VP, C.c_char_p, _I, _VP]),
-    "bcn_profile_read": (_I, [_VP, C.c_char_p, _I, _VP, _VP, _VP, _I]),
+    "bcn_profile_read": (_I, [_VP, C.c_char_p, _I, _VP, _VP, _VP, _VP, _I]),
 }
 
 
@@ -279,18 +279,20 @@ class Context:
         _check(lib().bcn_profile_enable(self.h, 1 if on else 0))
 
     def profile_read(self):
-        """{kernel: (launches, total_ms, algorithmic_bytes)} since the last read."""
+        """{kernel: (launches, total_ms, algorithmic_bytes, algorithmic_fp64_ops)} since the last read."""
         cap = 64
         names = C.create_string_buffer(4096)
         la = np.zeros(cap, dtype=np.int32)
         ms = np.zeros(cap, dtype=np.float64)
         by = np.zeros(cap, dtype=np.float64)
+        op = np.zeros(cap, dtype=np.float64)
         cnt = lib().bcn_profile_read(self.h, names, 4096, la.ctypes.data_as(C.c_void_p),
-                                     ms.ctypes.data_as(C.c_void_p), by.ctypes.data_as(C.c_void_p), cap)
+                                     ms.ctypes.data_as(C.c_void_p), by.ctypes.data_as(C.c_void_p),
+                                     op.ctypes.data_as(C.c_void_p), cap)
         if cnt < 0:
             _check(cnt)
         keys = names.value.decode().split("\n")[:cnt]
-        return {k: (int(la[i]), float(ms[i]), float(by[i])) for i, k in enumerate(keys)}
+        return {k: (int(la[i]), float(ms[i]), float(by[i]), float(op[i])) for i, k in enumerate(keys)}
 
 
 class SecretKey:

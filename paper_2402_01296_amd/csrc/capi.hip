@@ -407,7 +407,7 @@ int bcn_profile_enable(bcn_context* ctx, int on) {
 }
 
 int bcn_profile_read(bcn_context* ctx, char* names, int names_cap, int* launches, double* total_ms, double* bytes,
-                     int cap) {
+                     double* ops, int cap) {
   int count = 0;
   int rc = guard([&] {
     if (!ctx || !ctx->c) throw bcn::Error(BCN_ERR_INVALID, "null context");
@@ -427,6 +427,7 @@ int bcn_profile_read(bcn_context* ctx, char* names, int names_cap, int* launches
         launches[count] = (int)kv.second.launches;
         total_ms[count] = ms;
         bytes[count] = kv.second.bytes;
+        if (ops) ops[count] = kv.second.ops;
       }
       joined += kv.first + "\n";
       ++count;

@@ -67,12 +67,13 @@ hipEvent_t Context::get_event() const {
   return e;
 }
 
-ProfScope::ProfScope(const Context& c, const char* name, hipStream_t s, double bytes) : c_(c), s_(s) {
+ProfScope::ProfScope(const Context& c, const char* name, hipStream_t s, double bytes, double ops) : c_(c), s_(s) {
   if (!c.prof) return;
   e_ = &c.prof_data[name];
   start_ = c.get_event();
   BCN_HIP(hipEventRecord(start_, s));
   e_->bytes += bytes;
+  e_->ops += ops;
   e_->launches += 1;
 }
 
@@ -261,6 +262,14 @@ Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uin
   if (const char* env = std::getenv("BCN_FUSE_SQUARE")) c->fuse_square = logn <= 13 && std::atoi(env) != 0;
   c->fuse_ks = logn <= 13 && alpha <= 2;
   if (const char* env = std::getenv("BCN_FUSE_KS")) c->fuse_ks = logn <= 13 && alpha <= 2 && std::atoi(env) != 0;
+  if (const char* env = std::getenv("BCN_NTT_PERSIST")) c->ntt_persist = std::atoi(env) != 0;
+  {
+    hipDeviceProp_t prop;
+    BCN_HIP(hipGetDeviceProperties(&prop, device));
+    const size_t lds = (size_t)n * sizeof(double);
+    const int per_cu = std::max(1, (int)(prop.maxSharedMemoryPerMultiProcessor / lds));
+    c->persist_blocks = prop.multiProcessorCount * per_cu;
+  }
   ntt_setup(*c);
   return c.release();
 }

@@ -69,7 +69,8 @@ class Arena {
 // kernel name.
 struct ProfEntry {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
-  double bytes = 0;
+  double bytes = 0;   // algorithmic HBM bytes
+  double ops = 0;     // algorithmic FP64 VALU lane operations (0 when not tracked)
   long launches = 0;
 };
 
@@ -92,6 +93,8 @@ struct Context {
 
   int ntt_loge = 0;                      // registers per thread = 2^ntt_loge in the transform
   bool fuse_square = true;               // square's transforms and tensor in one kernel
+  bool ntt_persist = false;              // persistent, prefetching transform kernel
+  int persist_blocks = 512;              // its grid: workgroups resident at once
   bool fuse_ks = true;                   // key switching's digits, transforms and products in one kernel
   std::vector<int> ntt_loge_options() const;
 
@@ -107,7 +110,7 @@ struct Context {
 
 class ProfScope {
  public:
-  ProfScope(const Context& c, const char* name, hipStream_t s, double bytes);
+  ProfScope(const Context& c, const char* name, hipStream_t s, double bytes, double ops = 0.0);
   ~ProfScope();
   ProfScope(const ProfScope&) = delete;
   ProfScope& operator=(const ProfScope&) = delete;
@@ -163,6 +166,7 @@ struct MacPlan {
   int* tile_ptr = nullptr;      // device [n_tiles+1]
   int* tile_cols = nullptr;     // device: columns with a nonzero weight in the tile
   int chunk = 0;                // inputs between two partial reductions
+  long nnz = 0;                 // nonzero weights
 };
 // requests > 1: independent requests at in + r*in_req, out + r*out_req (doubles)
 void mac(const Context& c, const MacPlan& p, const double* in, double* out, int level, hipStream_t s, int requests = 1,

@@ -560,7 +560,8 @@ void mac(const Context& c, const MacPlan& p, const double* in, double* out, int 
          size_t in_req, size_t out_req) {
   const int words = 2 * level * c.n;
   if (p.n_out == 0 || requests == 0) return;
-  ProfScope ps(c, "mac", s, 8.0 * words * ((double)p.n_in + p.n_out) * requests);
+  // algorithmic work: one FMA per word for each nonzero (output, input) weight
+  ProfScope ps(c, "mac", s, 8.0 * words * ((double)p.n_in + p.n_out) * requests, (double)words * p.nnz * requests);
   dim3 grid(nblocks(words), p.n_tiles, requests);
   const Basis b = c.basis_Q(level);
   switch (p.tile) {

@@ -169,6 +169,56 @@ k_ntt(double* __restrict__ data, Basis basis, Tables tb) {
   run_pass<LOGN, LOGE, INV, 0>(x, lds, a, a, tw, post, m, threadIdx.x);
 }
 
+// Register positions of the first pass: element (g, j) of a thread sits at
+// transform index base[g] + j*SMIN of pass 0 (the layout run_pass gathers).
+template <int LOGN, int LOGE, bool INV>
+__device__ __forceinline__ void gather_pass0(double (&x)[1 << LOGE], const double* __restrict__ src, const int tid) {
+  using S = Shape<LOGN, LOGE>;
+  constexpr int N = S::N, T = S::T;
+  constexpr int C = Sched<LOGN, LOGE, INV>::c(0);
+  constexpr int SZ = 1 << C;
+  constexpr int G = S::E >> C;
+  constexpr int SMIN = INV ? 1 : (N >> C);
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int sid = g * T + tid;
+    const int base = INV ? sid * SZ : sid;     // pass 0: one block (forward) / contiguous sets (inverse)
+#pragma unroll
+    for (int j = 0; j < SZ; ++j) x[g * SZ + j] = src[base + j * SMIN];
+  }
+}
+
+// Persistent transform: each workgroup walks limbs blockIdx.x, blockIdx.x +
+// gridDim.x, ... and prefetches the next limb into registers before
+// transforming the current one, so HBM latency overlaps the LDS passes.
+template <int LOGN, int LOGE, bool INV>
+__global__ void __launch_bounds__(1 << (LOGN - LOGE))
+k_ntt_persist(double* __restrict__ data, int total, Basis basis, Tables tb, int zero) {
+  constexpr int N = 1 << LOGN;
+  extern __shared__ double lds[];
+  const int tid = threadIdx.x;
+  double x[1 << LOGE], xn[1 << LOGE];
+  int limb = blockIdx.x;
+  if (limb >= total) return;
+  gather_pass0<LOGN, LOGE, INV>(x, data + (size_t)limb * N, tid);
+  while (limb < total) {
+    const int next = limb + gridDim.x;
+    // `zero` is 0 at run time: keeps per-pass address arithmetic inside the loop (no hoisting
+    // into registers, which would halve occupancy)
+    const int z = limb & zero;
+    if (next < total) gather_pass0<LOGN, LOGE, INV>(xn, data + (size_t)next * N, tid + z);
+    const int pid = basis.id[limb % basis.n];
+    const Mod m = tb.mods[pid];
+    const double* tw = INV ? tb.inv + (size_t)pid * (N / 2) : tb.fwd + (size_t)pid * N;
+    const double* post = tb.post + (size_t)pid * N;
+    double* a = data + (size_t)limb * N;
+    run_pass<LOGN, LOGE, INV, 0, true, false>(x, lds + z, nullptr, a, tw, post, m, tid + z);
+#pragma unroll
+    for (int i = 0; i < (1 << LOGE); ++i) x[i] = xn[i];
+    limb = next;
+  }
+}
+
 // Square in the transform domain, fused: for one limb of one ciphertext
 // (a0, a1 in coefficient form over Q then the auxiliary primes) computes the
 // forward transforms of a0 and a1, the products d0 = a0^2, d1 = 2 a0 a1,
@@ -321,9 +371,24 @@ k_ks_fused(const double* __restrict__ src, size_t src_stride, int level, int L, 
   run_pass<LOGN, LOGE, true, 0, true, false>(x, lds, nullptr, u1, iw, post, m, tid);
 }
 
+template <int LOGN, int LOGE, bool INV>
+void launch_persist(const Context& c, double* data, int n_polys, const Basis& b, hipStream_t s) {
+  constexpr int N = 1 << LOGN;
+  const int total = n_polys * b.n;
+  if (total == 0) return;
+  const int grid = std::min(total, c.persist_blocks);
+  hipLaunchKernelGGL((k_ntt_persist<LOGN, LOGE, INV>), dim3(grid), dim3(N >> LOGE), (size_t)N * sizeof(double), s, data,
+                     total, b, c.tab, 0);
+  BCN_HIP(hipGetLastError());
+}
+
 template <int LOGN, int LOGE>
 void set_attr() {
   const int lds = (1 << LOGN) * (int)sizeof(double);
+  BCN_HIP(hipFuncSetAttribute((const void*)k_ntt_persist<LOGN, LOGE, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              lds));
+  BCN_HIP(hipFuncSetAttribute((const void*)k_ntt_persist<LOGN, LOGE, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              lds));
   BCN_HIP(hipFuncSetAttribute((const void*)k_ntt<LOGN, LOGE, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
   BCN_HIP(hipFuncSetAttribute((const void*)k_ntt<LOGN, LOGE, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
   BCN_HIP(hipFuncSetAttribute((const void*)k_square_fused<LOGN, LOGE>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -368,9 +433,25 @@ void launch_square(const Context& c, const double* in, double* out, int n, const
 
 template <bool INV>
 void dispatch(const Context& c, double* data, int n_polys, const Basis& b, hipStream_t s) {
-  // algorithmic traffic: each limb read once and written once
-  ProfScope ps(c, INV ? "ntt_inverse" : "ntt_forward", s, 16.0 * c.n * (double)n_polys * b.n);
+  // algorithmic traffic: each limb read once and written once; algorithmic VALU work: 8 FP64
+  // operations per butterfly (exact lazy product 6, add, subtract) and 4 per word at the end
+  const double limbs = (double)n_polys * b.n;
+  ProfScope ps(c, INV ? "ntt_inverse" : "ntt_forward", s, 16.0 * c.n * limbs,
+               limbs * (8.0 * (c.n / 2) * c.logn + 4.0 * c.n));
   const int key = c.logn * 16 + c.ntt_loge;
+  if (c.ntt_persist) {
+    switch (key) {
+#define BCN_NTTP_CASE(LN, LE) \
+  case LN * 16 + LE: launch_persist<LN, LE, INV>(c, data, n_polys, b, s); return;
+      BCN_NTTP_CASE(10, 3) BCN_NTTP_CASE(10, 4)
+      BCN_NTTP_CASE(11, 3) BCN_NTTP_CASE(11, 4)
+      BCN_NTTP_CASE(12, 4) BCN_NTTP_CASE(12, 5)
+      BCN_NTTP_CASE(13, 4) BCN_NTTP_CASE(13, 5)
+      BCN_NTTP_CASE(14, 4) BCN_NTTP_CASE(14, 5)
+#undef BCN_NTTP_CASE
+      default: throw Error(-1, "unsupported ring degree / transform shape");
+    }
+  }
   switch (key) {
 #define BCN_NTT_CASE(LN, LE) \
   case LN * 16 + LE: launch<LN, LE, INV>(c, data, n_polys, b, s); break;
@@ -409,8 +490,11 @@ void ntt_setup(const Context& c) {
 }
 
 void square_transform_fused(const Context& c, const double* in, double* out, int n, const Basis& b, hipStream_t s) {
-  // algorithmic traffic: two limbs in, three limbs out per (ciphertext, limb)
-  ProfScope ps(c, "square_fused", s, 8.0 * c.n * (double)n * b.n * 5);
+  // algorithmic traffic: two limbs in, three limbs out per (ciphertext, limb); work: five
+  // transforms, three products, two normalisations
+  const double units = (double)n * b.n;
+  ProfScope ps(c, "square_fused", s, 8.0 * c.n * units * 5,
+               units * (5.0 * (8.0 * (c.n / 2) * c.logn + 4.0 * c.n) + 3.0 * 8.0 * c.n + 2.0 * 4.0 * c.n));
   const int key = c.logn * 16 + c.ntt_loge;
   switch (key) {
 #define BCN_SQ_CASE(LN, LE) \
@@ -448,7 +532,9 @@ void ks_fused(const Context& c, const double* src, size_t src_stride, int n, int
   }
   const int kinv = galois == 1 ? 1 : (int)host::inv_pow2((uint64_t)galois, c.logn + 1);
   // algorithmic traffic: digit sources (level limbs per target limb), two key limbs per digit, two outputs
-  ProfScope ps(c, "ks_fused", s, 8.0 * c.n * (double)n * qp.n * (level + 2.0 * dnum + 2));
+  const double units = (double)n * qp.n;
+  ProfScope ps(c, "ks_fused", s, 8.0 * c.n * units * (level + 2.0 * dnum + 2),
+               units * ((dnum + 2.0) * (8.0 * (c.n / 2) * c.logn + 4.0 * c.n) + dnum * 2.0 * 7.0 * c.n));
   // two accumulators and the working set stay in registers (sixteen residues per
   // thread; spill-free up to N = 8192)
   switch (c.logn) {

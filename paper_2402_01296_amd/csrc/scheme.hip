@@ -353,6 +353,7 @@ MacPlan make_mac_plan(const Context& c, const std::vector<int32_t>& w, int n_out
         const int row = rows[t * tile + o];
         const int32_t v = row >= 0 ? w[(size_t)row * n_in + j] : 0;
         wmax = std::max(wmax, v < 0 ? -v : v);
+        p.nnz += v != 0;
         W.push_back((double)v);
       }
     }

@@ -52,6 +52,21 @@ std::string autotune_ntt(Context& c, hipStream_t s) {
   }
   c.ntt_loge = best;
   report += "ntt chosen loge=" + std::to_string(best) + "\n";
+  {
+    float t[2];
+    for (int pers = 0; pers < 2; ++pers) {
+      c.ntt_persist = pers != 0;
+      t[pers] = time_ms(s, 5, [&] {
+        ntt_forward(c, buf, polys, b, s);
+        ntt_inverse(c, buf, polys, b, s);
+      });
+    }
+    c.ntt_persist = t[1] < t[0];
+    char line[160];
+    std::snprintf(line, sizeof line, "ntt per-limb %.3f ms, persistent prefetching %.3f ms\n", t[0], t[1]);
+    report += line;
+    report += std::string("ntt chosen persistent=") + (c.ntt_persist ? "1" : "0") + "\n";
+  }
   // square's transform segment: fused kernel vs forward + tensor + inverse
   if (c.logn <= 13) {
     const int n = std::max(8, polys / 2);

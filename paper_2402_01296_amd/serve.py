@@ -132,9 +132,13 @@ class Server:
                     for (t, i) in b["reqs"]:
                         latency[i] = fin - t
                     if keep_outputs:
+                        # copy on the batch's own stream: the output block returns to that
+                        # stream's allocator pool when the batch is dropped, so a copy on another
+                        # stream could race with the next batch reusing the block
                         n_out = self.sessions[name].n_outputs()
-                        for j, (t, i) in enumerate(b["reqs"]):
-                            outputs[i] = b["out"][j * n_out:(j + 1) * n_out].clone()
+                        with torch.cuda.stream(self.streams[name]):
+                            for j, (t, i) in enumerate(b["reqs"]):
+                                outputs[i] = b["out"][j * n_out:(j + 1) * n_out].clone()
                     used -= b["bytes"]
                     done += len(b["reqs"])
                     progressed = True
@@ -164,6 +168,7 @@ class Server:
             if not progressed:
                 time.sleep(0.0001)
         elapsed = time.perf_counter() - t0
+        torch.cuda.synchronize()
         lat = np.array([latency[i] for i in range(n_total)])
         sizes = collections.Counter(n for n, _ in batches)
         mean_batch = {k: float(np.mean([r for n, r in batches if n == k])) for k in sizes}

@@ -243,18 +243,21 @@ def test_errors_are_reported(env_t1k):
         ctx.import_(bad)
 
 
-@pytest.mark.parametrize("pname", ["t1k", "cfg2"])
-def test_transform_shapes_agree(pname, monkeypatch):
-    """Every transform shape the autotuner may pick computes the same exact transform."""
+@pytest.mark.parametrize("pname", ["t1k", "cfg2", "cfg3"])
+@pytest.mark.parametrize("persist", ["0", "1"])
+def test_transform_shapes_agree(pname, persist, monkeypatch):
+    """Every transform shape (registers per thread, per-limb or persistent prefetching kernel)
+    the autotuner may pick computes the same exact transform."""
     torch = torch_cuda()
     from oracle import params
     from paper_2402_01296_amd import bcn
     spec = params.get(pname)
+    monkeypatch.setenv("BCN_NTT_PERSIST", persist)
     outs = []
     for loge in (3, 4, 5):
         monkeypatch.setenv("BCN_NTT_LOGE", str(loge))
         ctx = bcn.Context(spec.n, spec.q[0].bit_length(), spec.L, spec.K, spec.alpha, spec.t)
-        x = np.stack([synthetic.test_poly(3, i, ctx.q, spec.n) for i in range(3)])
+        x = np.stack([synthetic.test_poly(3, i, ctx.q, spec.n) for i in range(700)])
         d = torch.from_numpy(x.astype(np.float64)).cuda()
         ctx.ntt(d, 0)
         f = d.cpu().numpy().copy()
