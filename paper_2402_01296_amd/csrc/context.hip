@@ -255,7 +255,13 @@ Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uin
   if (const char* env = std::getenv("BCN_NTT_LOGE")) {
     const int v = std::atoi(env);
     for (int o : c->ntt_loge_options())
-      if (o == v) c->ntt_loge = v;
+      if (o == v) c->ntt_loge = v, c->pinned_loge = true;
+  }
+  c->square_loge = c->ntt_loge;
+  if (const char* env = std::getenv("BCN_SQUARE_LOGE")) {
+    const int v = std::atoi(env);
+    for (int o : c->ntt_loge_options())
+      if (o == v) c->square_loge = v, c->pinned_square_loge = true;
   }
   // the fused square keeps three register sets live; above N = 8192 it would spill
   c->fuse_square = logn <= 13;
@@ -263,6 +269,7 @@ Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uin
   c->fuse_ks = logn <= 13 && alpha <= 2;
   if (const char* env = std::getenv("BCN_FUSE_KS")) c->fuse_ks = logn <= 13 && alpha <= 2 && std::atoi(env) != 0;
   if (const char* env = std::getenv("BCN_NTT_PERSIST")) c->ntt_persist = std::atoi(env) != 0;
+  if (const char* env = std::getenv("BCN_NTT_PREFETCH")) c->ntt_prefetch = std::atoi(env) != 0, c->pinned_prefetch = true;
   {
     hipDeviceProp_t prop;
     BCN_HIP(hipGetDeviceProperties(&prop, device));

@@ -92,8 +92,11 @@ struct Context {
   std::unique_ptr<Arena> arena;
 
   int ntt_loge = 0;                      // registers per thread = 2^ntt_loge in the transform
+  int square_loge = 0;                   // the same for the fused square's transforms
+  bool pinned_loge = false, pinned_square_loge = false, pinned_prefetch = false;   // fixed by the environment
   bool fuse_square = true;               // square's transforms and tensor in one kernel
   bool ntt_persist = false;              // persistent, prefetching transform kernel
+  bool ntt_prefetch = false;             // transform loads the next pass's twiddles before each exchange
   int persist_blocks = 512;              // its grid: workgroups resident at once
   bool fuse_ks = true;                   // key switching's digits, transforms and products in one kernel
   std::vector<int> ntt_loge_options() const;

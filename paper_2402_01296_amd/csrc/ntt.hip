@@ -44,28 +44,134 @@ struct Sched {
   static constexpr int s0(int p) { return INV ? p * LOGE : (p == 0 ? 0 : S::C0 + (p - 1) * LOGE); }
 };
 
-// One pass of the transform.  FROM_REGS: the first pass starts from the
-// registers (already in this pass's layout) instead of reading HBM.  TO_REGS:
-// the last pass leaves its results in the registers (lazy form, no final
-// reduction or untwist) instead of writing HBM.
-template <int LOGN, int LOGE, bool INV, int P, bool FROM_REGS = false, bool TO_REGS = false>
-__device__ __forceinline__ void run_pass(double (&x)[1 << LOGE], double* lds, const double* __restrict__ src,
-                                         double* __restrict__ a, const double* __restrict__ tw,
-                                         const double* __restrict__ post, const Mod m, const int tid) {
+// Twiddles one thread uses in pass P, in the order the butterfly loops consume them:
+// forward stages take one per block of butterflies that share it, inverse stages
+// one per position inside a block.
+template <int LOGN, int LOGE, bool INV, int P>
+struct PassTw {
+  using S = Shape<LOGN, LOGE>;
+  static constexpr int C = Sched<LOGN, LOGE, INV>::c(P);
+  static constexpr int NT = (S::E >> C) * ((1 << C) - 1);
+};
+
+// Index of element j of group g in pass P (transform order).
+template <int LOGN, int LOGE, bool INV, int P>
+__device__ __forceinline__ int pass_base(int g, int tid) {
   using S = Shape<LOGN, LOGE>;
   constexpr int N = S::N, T = S::T;
   constexpr int C = Sched<LOGN, LOGE, INV>::c(P);
   constexpr int S0 = Sched<LOGN, LOGE, INV>::s0(P);
+  constexpr int SMIN = INV ? (1 << S0) : (N >> (S0 + C));
+  const int sid = g * T + tid;
+  const int b = sid / SMIN, r = sid % SMIN;
+  return INV ? b * (SMIN << C) + r : b * (N >> S0) + r;
+}
+
+template <int LOGN, int LOGE, bool INV, int P, int NT>
+__device__ __forceinline__ void load_tw(double (&wt)[NT], const double* __restrict__ tw, const int tid) {
+  using S = Shape<LOGN, LOGE>;
+  constexpr unsigned N = S::N;
+  constexpr int C = Sched<LOGN, LOGE, INV>::c(P);
+  constexpr int S0 = Sched<LOGN, LOGE, INV>::s0(P);
   constexpr int SZ = 1 << C;
   constexpr int G = S::E >> C;
-  constexpr int SMIN = INV ? (1 << S0) : (N >> (S0 + C));
+  constexpr unsigned SMIN = INV ? (1u << S0) : (N >> (S0 + C));
+  // unsigned 32-bit indices: lets the compiler address the table with a scalar base
+  // and one 32-bit lane offset
+  unsigned base[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) base[g] = (unsigned)pass_base<LOGN, LOGE, INV, P>(g, tid);
+  int k = 0;
+#pragma unroll
+  for (int l = 0; l < C; ++l) {
+    const int s = S0 + l;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if (!INV) {
+        const int sh = C - 1 - l;
+#pragma unroll
+        for (int kb = 0; kb < (SZ >> (sh + 1)); ++kb) {
+          const unsigned gi = base[g] + ((unsigned)kb << (sh + 1)) * SMIN;
+          wt[k++] = tw[(1u << s) + (gi >> (LOGN - s))];
+        }
+      } else {
+        const unsigned r = base[g] & (SMIN - 1);
+#pragma unroll
+        for (int jl = 0; jl < (1 << l); ++jl) wt[k++] = tw[(r + jl * SMIN) * (N >> (s + 1))];
+      }
+    }
+  }
+}
 
+// Wave (64 lanes) that holds transform index e in pass P.
+template <int LOGN, int LOGE, bool INV, int P>
+constexpr int pass_wave(int e) {
+  using S = Shape<LOGN, LOGE>;
+  constexpr int N = S::N, T = S::T;
+  constexpr int C = Sched<LOGN, LOGE, INV>::c(P);
+  constexpr int S0 = Sched<LOGN, LOGE, INV>::s0(P);
+  constexpr int SMIN = INV ? (1 << S0) : (N >> (S0 + C));
+  const int r = e % SMIN;
+  const int b = INV ? e / (SMIN << C) : e / (N >> S0);
+  return ((b * SMIN + r) % T) / 64;
+}
+
+// True when every wave holds the same indices in passes P and P + 1: the exchange
+// between them then stays inside each wave's own LDS words and needs no workgroup
+// barrier.
+template <int LOGN, int LOGE, bool INV, int P>
+constexpr bool exchange_is_wave_local() {
+  for (int e = 0; e < (1 << LOGN); ++e)
+    if (pass_wave<LOGN, LOGE, INV, P>(e) != pass_wave<LOGN, LOGE, INV, P + 1>(e)) return false;
+  return true;
+}
+
+// Orders one wave's LDS writes before its later reads.  A wave's LDS operations
+// execute in issue order, so only the compiler has to be kept from moving them.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One pass of the transform.  FROM_REGS: the first pass starts from the
+// registers (already in this pass's layout) instead of reading HBM.  TO_REGS:
+// the last pass leaves its results in the registers (lazy form, no final
+// reduction or untwist) instead of writing HBM.  PF: every pass loads the next
+// pass's twiddles before the exchange barriers, so their latency overlaps the
+// exchange (costs registers for one more pass's twiddles).
+template <int LOGN, int LOGE, bool INV, int P, bool FROM_REGS = false, bool TO_REGS = false, bool PF = false>
+__device__ __forceinline__ void run_pass(double (&x)[1 << LOGE], double* lds, const double* __restrict__ src,
+                                         double* __restrict__ a, const double* __restrict__ tw,
+                                         const double* __restrict__ post, const Mod m, const int tid_in,
+                                         const double* wpre = nullptr) {
+  using S = Shape<LOGN, LOGE>;
+  constexpr int N = S::N;
+  constexpr int C = Sched<LOGN, LOGE, INV>::c(P);
+  constexpr int SZ = 1 << C;
+  constexpr int G = S::E >> C;
+  constexpr int S0 = Sched<LOGN, LOGE, INV>::s0(P);
+  constexpr int SMIN = INV ? (1 << S0) : (N >> (S0 + C));
+  constexpr int NT = PassTw<LOGN, LOGE, INV, P>::NT;
+
+  // The thread index is hidden from the optimiser at the start of every transform (an
+  // empty asm that claims to change it): otherwise the address arithmetic of passes
+  // with the same layout in different transforms (the forward transform's last pass and
+  // the inverse transform's first, or two transforms in one kernel) is computed once and
+  // kept live across the whole kernel, which more than doubles the register use of the
+  // fused kernels.
+  int tid = tid_in;
+  if constexpr (P == 0) asm volatile("" : "+v"(tid));
   int base[G];
 #pragma unroll
-  for (int g = 0; g < G; ++g) {
-    const int sid = g * T + tid;
-    const int b = sid / SMIN, r = sid % SMIN;
-    base[g] = INV ? b * (SMIN << C) + r : b * (N >> S0) + r;
+  for (int g = 0; g < G; ++g) base[g] = pass_base<LOGN, LOGE, INV, P>(g, tid);
+
+  double wt[NT];
+  if constexpr (PF && P > 0) {
+#pragma unroll
+    for (int k = 0; k < NT; ++k) wt[k] = wpre[k];
+  } else {
+    load_tw<LOGN, LOGE, INV, P>(wt, tw, tid);
   }
 
   // gather
@@ -83,10 +189,10 @@ __device__ __forceinline__ void run_pass(double (&x)[1 << LOGE], double* lds, co
       for (int j = 0; j < SZ; ++j) x[g * SZ + j] = lds[lds_sw<LOGE>(base[g] + j * SMIN)];
   }
 
-  // butterflies: one twiddle load per group of butterflies that share it
+  // butterflies
+  int k = 0;
 #pragma unroll
   for (int l = 0; l < C; ++l) {
-    const int s = S0 + l;
     if (!INV) {
       // forward stage: local blocks of 2*half elements, one twiddle per block
       const int sh = C - 1 - l;
@@ -96,8 +202,7 @@ __device__ __forceinline__ void run_pass(double (&x)[1 << LOGE], double* lds, co
 #pragma unroll
         for (int kb = 0; kb < (SZ >> (sh + 1)); ++kb) {
           const int j0 = kb << (sh + 1);
-          const int gi = base[g] + j0 * SMIN;
-          const double w = tw[(1 << s) + (gi >> (LOGN - s))];
+          const double w = wt[k++];
 #pragma unroll
           for (int jj = 0; jj < half; ++jj) {
             const int j = g * SZ + j0 + jj;
@@ -113,10 +218,9 @@ __device__ __forceinline__ void run_pass(double (&x)[1 << LOGE], double* lds, co
       const int half = 1 << l;
 #pragma unroll
       for (int g = 0; g < G; ++g) {
-        const int r = base[g] & (SMIN - 1);
 #pragma unroll
         for (int jl = 0; jl < half; ++jl) {
-          const double w = tw[(r + jl * SMIN) * (N >> (s + 1))];
+          const double w = wt[k++];
 #pragma unroll
           for (int kb = 0; kb < (SZ >> (l + 1)); ++kb) {
             const int j = g * SZ + (kb << (l + 1)) + jl;
@@ -144,29 +248,56 @@ __device__ __forceinline__ void run_pass(double (&x)[1 << LOGE], double* lds, co
         }
     }
   } else {
-    if constexpr (P > 0 || FROM_REGS) __syncthreads();   // previous LDS readers are done
+    constexpr int NT1 = PassTw<LOGN, LOGE, INV, P + 1>::NT;
+    double wn[PF ? NT1 : 1];
+    if constexpr (PF) load_tw<LOGN, LOGE, INV, P + 1>(wn, tw, tid);
+    // A wave-local exchange inside one transform (P > 0) overwrites only words the same
+    // wave read in this pass; the first exchange may overwrite words other waves read in
+    // the caller's previous transform, so it keeps the workgroup barrier.
+    constexpr bool LOCAL = exchange_is_wave_local<LOGN, LOGE, INV, P>();
+    if constexpr (LOCAL && P > 0) {
+      wave_sync();
+    } else if constexpr (P > 0 || FROM_REGS) {
+      __syncthreads();   // previous LDS readers are done
+    }
 #pragma unroll
     for (int g = 0; g < G; ++g)
 #pragma unroll
       for (int j = 0; j < SZ; ++j) lds[lds_sw<LOGE>(base[g] + j * SMIN)] = x[g * SZ + j];
-    __syncthreads();
-    run_pass<LOGN, LOGE, INV, P + 1, FROM_REGS, TO_REGS>(x, lds, src, a, tw, post, m, tid);
+    if constexpr (LOCAL) {
+      wave_sync();
+    } else {
+      __syncthreads();
+    }
+    run_pass<LOGN, LOGE, INV, P + 1, FROM_REGS, TO_REGS, PF>(x, lds, src, a, tw, post, m, tid, wn);
   }
 }
 
-template <int LOGN, int LOGE, bool INV>
+// Workgroups of a launch go to the eight XCDs in turn (workgroup i to XCD i mod 8) and every
+// XCD has an L2 of its own.  xcd_order renumbers the workgroups so that each XCD walks one
+// contiguous stretch of a limb-major work list: all workgroups of one limb then run on one or
+// two XCDs, whose L2 keeps that limb's twiddle (and key) tables resident.
+__device__ __forceinline__ int xcd_order(int bid, int total) {
+  constexpr int X = 8;
+  const int per = total / X, rem = total % X, x = bid % X;
+  return x * per + min(x, rem) + bid / X;
+}
+
+template <int LOGN, int LOGE, bool INV, bool PF>
 __global__ void __launch_bounds__(1 << (LOGN - LOGE))
 k_ntt(double* __restrict__ data, Basis basis, Tables tb) {
   constexpr int N = 1 << LOGN;
   extern __shared__ double lds[];
-  const int limb = blockIdx.x % basis.n;
+  const int nb = basis.n, npoly = gridDim.x / nb;
+  const int w = xcd_order(blockIdx.x, gridDim.x);
+  const int limb = w / npoly, poly = w - limb * npoly;
   const int pid = basis.id[limb];
   const Mod m = tb.mods[pid];
-  double* a = data + (size_t)blockIdx.x * N;
+  double* a = data + ((size_t)poly * nb + limb) * N;
   const double* tw = INV ? tb.inv + (size_t)pid * (N / 2) : tb.fwd + (size_t)pid * N;
   const double* post = tb.post + (size_t)pid * N;
   double x[1 << LOGE];
-  run_pass<LOGN, LOGE, INV, 0>(x, lds, a, a, tw, post, m, threadIdx.x);
+  run_pass<LOGN, LOGE, INV, 0, false, false, PF>(x, lds, a, a, tw, post, m, threadIdx.x);
 }
 
 // Register positions of the first pass: element (g, j) of a thread sits at
@@ -220,20 +351,23 @@ k_ntt_persist(double* __restrict__ data, int total, Basis basis, Tables tb, int 
 }
 
 // Square in the transform domain, fused: for one limb of one ciphertext
-// (a0, a1 in coefficient form over Q then the auxiliary primes) computes the
-// forward transforms of a0 and a1, the products d0 = a0^2, d1 = 2 a0 a1,
-// d2 = a1^2 and their inverse transforms, writing d0, d1, d2 in coefficient
-// form.  The forward transform ends in the register layout the inverse
-// transform starts from, so nothing between the two loads and three stores
-// goes through HBM.
+// (a0, a1 in coefficient form over Q then the auxiliary primes) writes, in
+// coefficient form, d0 = a0^2, d1 = 2 a0 a1 and d2 = a1^2 (products in the
+// transform domain).  The forward transform ends in the register layout the
+// inverse transform starts from, so the products and inverse transforms work on
+// registers.  At most two register sets are live: A0 = NTT(a0) and A1 = NTT(a1)
+// give d1 and d0 in place, then a1 is transformed a second time for d2.  That is
+// six transforms instead of five, but it halves the registers a thread needs, so
+// two workgroups share a CU instead of one.
 template <int LOGN, int LOGE>
-__global__ void __launch_bounds__(1 << (LOGN - LOGE))
-k_square_fused(const double* __restrict__ in, double* __restrict__ out, Basis basis, Tables tb, int zero) {
+__global__ void __launch_bounds__(1 << (LOGN - LOGE)) __attribute__((amdgpu_waves_per_eu(LOGE <= 4 ? 4 : 1)))
+k_square_fused(const double* __restrict__ in, double* __restrict__ out, Basis basis, Tables tb) {
   constexpr int N = 1 << LOGN;
   constexpr int E = 1 << LOGE;
   extern __shared__ double lds[];
-  const int nb = basis.n;
-  const int ct = blockIdx.x / nb, limb = blockIdx.x % nb;
+  const int nb = basis.n, nct = gridDim.x / nb;
+  const int w = xcd_order(blockIdx.x, gridDim.x);
+  const int limb = w / nct, ct = w - limb * nct;
   const int pid = basis.id[limb];
   const Mod m = tb.mods[pid];
   const double* fw = tb.fwd + (size_t)pid * N;
@@ -241,32 +375,31 @@ k_square_fused(const double* __restrict__ in, double* __restrict__ out, Basis ba
   const double* post = tb.post + (size_t)pid * N;
   const double* a0 = in + ((size_t)(ct * 2) * nb + limb) * N;
   const double* a1 = in + ((size_t)(ct * 2 + 1) * nb + limb) * N;
-  double x0[E], x1[E], x[E];
-  run_pass<LOGN, LOGE, false, 0, false, true>(x0, lds, a0, nullptr, fw, post, m, threadIdx.x);
+  double* d0 = out + ((size_t)(ct * 3) * nb + limb) * N;
+  double* d1 = d0 + (size_t)nb * N;
+  double* d2 = d1 + (size_t)nb * N;
+  const int tid = threadIdx.x;
+  double x0[E], x1[E];
+  run_pass<LOGN, LOGE, false, 0, false, true>(x0, lds, a0, nullptr, fw, post, m, tid);
   __syncthreads();
-  run_pass<LOGN, LOGE, false, 0, false, true>(x1, lds, a1, nullptr, fw, post, m, threadIdx.x);
+  run_pass<LOGN, LOGE, false, 0, false, true>(x1, lds, a1, nullptr, fw, post, m, tid);
 #pragma unroll
   for (int i = 0; i < E; ++i) {
-    x0[i] = reduce(x0[i], m);
-    x1[i] = reduce(x1[i], m);
+    const double r0 = reduce(x0[i], m);
+    const double p = mul_mod(r0, reduce(x1[i], m), m);
+    x1[i] = add_mod(p, p, m);
+    x0[i] = mul_mod(r0, r0, m);
   }
-#pragma unroll 1
-  for (int k = 0; k < 3; ++k) {
+  run_pass<LOGN, LOGE, true, 0, true, false>(x1, lds, nullptr, d1, iw, post, m, tid);
+  run_pass<LOGN, LOGE, true, 0, true, false>(x0, lds, nullptr, d0, iw, post, m, tid);
+  __syncthreads();
+  run_pass<LOGN, LOGE, false, 0, false, true>(x1, lds, a1, nullptr, fw, post, m, tid);
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
-      if (k == 0) {
-        x[i] = mul_mod(x0[i], x0[i], m);
-      } else if (k == 1) {
-        const double p = mul_mod(x0[i], x1[i], m);
-        x[i] = add_mod(p, p, m);
-      } else {
-        x[i] = mul_mod(x1[i], x1[i], m);
-      }
-    }
-    double* dst = out + ((size_t)(ct * 3 + k) * nb + limb) * N;
-    // `zero` is 0 at run time: keeps the transform's address arithmetic inside the loop
-    run_pass<LOGN, LOGE, true, 0, true, false>(x, lds + (k & zero), nullptr, dst, iw, post, m, threadIdx.x + (k & zero));
+  for (int i = 0; i < E; ++i) {
+    const double r = reduce(x1[i], m);
+    x1[i] = mul_mod(r, r, m);
   }
+  run_pass<LOGN, LOGE, true, 0, true, false>(x1, lds, nullptr, d2, iw, post, m, tid);
 }
 
 template <int LOGN, int LOGE, bool INV>
@@ -275,7 +408,10 @@ void launch(const Context& c, double* data, int n_polys, const Basis& b, hipStre
   const size_t lds = (size_t)N * sizeof(double);
   const unsigned blocks = (unsigned)n_polys * b.n;
   if (blocks == 0) return;
-  hipLaunchKernelGGL((k_ntt<LOGN, LOGE, INV>), dim3(blocks), dim3(N >> LOGE), lds, s, data, b, c.tab);
+  if (c.ntt_prefetch)
+    hipLaunchKernelGGL((k_ntt<LOGN, LOGE, INV, true>), dim3(blocks), dim3(N >> LOGE), lds, s, data, b, c.tab);
+  else
+    hipLaunchKernelGGL((k_ntt<LOGN, LOGE, INV, false>), dim3(blocks), dim3(N >> LOGE), lds, s, data, b, c.tab);
   BCN_HIP(hipGetLastError());
 }
 
@@ -301,8 +437,9 @@ k_ks_fused(const double* __restrict__ src, size_t src_stride, int level, int L, 
   constexpr int C0 = S::C0;
   constexpr int SMIN0 = N >> C0, SZ0 = 1 << C0, G0 = E >> C0;
   extern __shared__ double lds[];
-  const int nb = qp.n;
-  const int ct = blockIdx.x / nb, limb = blockIdx.x % nb;
+  const int nb = qp.n, nct = gridDim.x / nb;
+  const int w = xcd_order(blockIdx.x, gridDim.x);
+  const int limb = w / nct, ct = w - limb * nct;
   const int pid = qp.id[limb];
   const Mod m = tb.mods[pid];
   const double* fw = tb.fwd + (size_t)pid * N;
@@ -389,8 +526,10 @@ void set_attr() {
                               lds));
   BCN_HIP(hipFuncSetAttribute((const void*)k_ntt_persist<LOGN, LOGE, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               lds));
-  BCN_HIP(hipFuncSetAttribute((const void*)k_ntt<LOGN, LOGE, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-  BCN_HIP(hipFuncSetAttribute((const void*)k_ntt<LOGN, LOGE, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+  BCN_HIP(hipFuncSetAttribute((const void*)k_ntt<LOGN, LOGE, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+  BCN_HIP(hipFuncSetAttribute((const void*)k_ntt<LOGN, LOGE, true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+  BCN_HIP(hipFuncSetAttribute((const void*)k_ntt<LOGN, LOGE, false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+  BCN_HIP(hipFuncSetAttribute((const void*)k_ntt<LOGN, LOGE, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
   BCN_HIP(hipFuncSetAttribute((const void*)k_square_fused<LOGN, LOGE>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               lds));
   BCN_HIP(hipFuncSetAttribute((const void*)k_ks_fused<LOGN, LOGE, 1, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -427,7 +566,7 @@ void launch_square(const Context& c, const double* in, double* out, int n, const
   const unsigned blocks = (unsigned)n * b.n;
   if (blocks == 0) return;
   hipLaunchKernelGGL((k_square_fused<LOGN, LOGE>), dim3(blocks), dim3(N >> LOGE), (size_t)N * sizeof(double), s, in,
-                     out, b, c.tab, 0);
+                     out, b, c.tab);
   BCN_HIP(hipGetLastError());
 }
 
@@ -495,7 +634,7 @@ void square_transform_fused(const Context& c, const double* in, double* out, int
   const double units = (double)n * b.n;
   ProfScope ps(c, "square_fused", s, 8.0 * c.n * units * 5,
                units * (5.0 * (8.0 * (c.n / 2) * c.logn + 4.0 * c.n) + 3.0 * 8.0 * c.n + 2.0 * 4.0 * c.n));
-  const int key = c.logn * 16 + c.ntt_loge;
+  const int key = c.logn * 16 + c.square_loge;
   switch (key) {
 #define BCN_SQ_CASE(LN, LE) \
   case LN * 16 + LE: launch_square<LN, LE>(c, in, out, n, b, s); break;

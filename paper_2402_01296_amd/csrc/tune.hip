@@ -33,25 +33,48 @@ std::string autotune_ntt(Context& c, hipStream_t s) {
   double* buf = c.arena->take((size_t)polys * b.n * c.n);
   BCN_HIP(hipMemsetAsync(buf, 0, (size_t)polys * b.n * c.n * sizeof(double), s));
   std::string report;
-  int best = c.ntt_loge;
-  float best_ms = 1e30f;
-  for (int loge : c.ntt_loge_options()) {
-    c.ntt_loge = loge;
-    const float ms = time_ms(s, 5, [&] {
-      ntt_forward(c, buf, polys, b, s);
-      ntt_inverse(c, buf, polys, b, s);
-    });
-    char line[128];
-    std::snprintf(line, sizeof line, "ntt logn=%d loge=%d: %.3f ms for %d limbs fwd+inv\n", c.logn, loge, ms,
-                  polys * b.n);
-    report += line;
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = loge;
+  // a candidate replaces the current (default) choice only when it is clearly faster, so that
+  // near-ties do not flip the shape from one process to the next
+  constexpr float kMargin = 0.97f;
+  if (!c.pinned_loge) {
+    const int dflt = c.ntt_loge;
+    int best = dflt;
+    float best_ms = 1e30f, dflt_ms = 1e30f;
+    for (int loge : c.ntt_loge_options()) {
+      c.ntt_loge = loge;
+      const float ms = time_ms(s, 5, [&] {
+        ntt_forward(c, buf, polys, b, s);
+        ntt_inverse(c, buf, polys, b, s);
+      });
+      char line[128];
+      std::snprintf(line, sizeof line, "ntt logn=%d loge=%d: %.3f ms for %d limbs fwd+inv\n", c.logn, loge, ms,
+                    polys * b.n);
+      report += line;
+      if (loge == dflt) dflt_ms = ms;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = loge;
+      }
     }
+    c.ntt_loge = best_ms < kMargin * dflt_ms ? best : dflt;
   }
-  c.ntt_loge = best;
-  report += "ntt chosen loge=" + std::to_string(best) + "\n";
+  report += "ntt chosen loge=" + std::to_string(c.ntt_loge) + "\n";
+  if (!c.pinned_prefetch) {
+    float t[2];
+    for (int pf = 0; pf < 2; ++pf) {
+      c.ntt_prefetch = pf != 0;
+      t[pf] = time_ms(s, 5, [&] {
+        ntt_forward(c, buf, polys, b, s);
+        ntt_inverse(c, buf, polys, b, s);
+      });
+    }
+    c.ntt_prefetch = t[1] < kMargin * t[0];
+    char line[160];
+    std::snprintf(line, sizeof line, "ntt twiddles per pass %.3f ms, prefetched across the exchange %.3f ms\n", t[0],
+                  t[1]);
+    report += line;
+  }
+  report += std::string("ntt chosen prefetch=") + (c.ntt_prefetch ? "1" : "0") + "\n";
   {
     float t[2];
     for (int pers = 0; pers < 2; ++pers) {
@@ -61,13 +84,13 @@ std::string autotune_ntt(Context& c, hipStream_t s) {
         ntt_inverse(c, buf, polys, b, s);
       });
     }
-    c.ntt_persist = t[1] < t[0];
+    c.ntt_persist = t[1] < kMargin * t[0];
     char line[160];
     std::snprintf(line, sizeof line, "ntt per-limb %.3f ms, persistent prefetching %.3f ms\n", t[0], t[1]);
     report += line;
     report += std::string("ntt chosen persistent=") + (c.ntt_persist ? "1" : "0") + "\n";
   }
-  // square's transform segment: fused kernel vs forward + tensor + inverse
+  // square's transform segment: fused kernel (each transform shape) vs forward + tensor + inverse
   if (c.logn <= 13) {
     const int n = std::max(8, polys / 2);
     double* in = buf;
@@ -82,12 +105,30 @@ std::string autotune_ntt(Context& c, hipStream_t s) {
     const float copy = time_ms(s, 5, [&] {
       BCN_HIP(hipMemcpyAsync(tmp, in, (size_t)n * 2 * b.n * c.n * sizeof(double), hipMemcpyDeviceToDevice, s));
     });
-    const float fused = time_ms(s, 5, [&] { square_transform_fused(c, in, out, n, b, s); });
+    const int dflt = c.square_loge;
+    int best = dflt;
+    float best_ms = 1e30f, dflt_ms = 1e30f;
+    for (int loge : c.ntt_loge_options()) {
+      if (c.pinned_square_loge && loge != dflt) continue;
+      c.square_loge = loge;
+      const float ms = time_ms(s, 5, [&] { square_transform_fused(c, in, out, n, b, s); });
+      char line[160];
+      std::snprintf(line, sizeof line, "square transforms (%d ciphertexts, %d limbs): fused loge=%d %.3f ms\n", n,
+                    b.n, loge, ms);
+      report += line;
+      if (loge == dflt) dflt_ms = ms;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = loge;
+      }
+    }
+    c.square_loge = best_ms < kMargin * dflt_ms ? best : dflt;
+    const float fused = c.square_loge == best ? best_ms : dflt_ms;
     char line[160];
-    std::snprintf(line, sizeof line, "square transforms (%d ciphertexts, %d limbs): fused %.3f ms, unfused %.3f ms\n",
-                  n, b.n, fused, unfused - copy);
+    std::snprintf(line, sizeof line, "square transforms unfused %.3f ms\n", unfused - copy);
     report += line;
     c.fuse_square = fused < unfused - copy;
+    report += "square chosen loge=" + std::to_string(c.square_loge) + "\n";
   } else {
     c.fuse_square = false;
   }

@@ -268,15 +268,23 @@ def test_transform_shapes_agree(pname, persist, monkeypatch):
     assert all((o == outs[0]).all() for o in outs)
 
 
-@pytest.mark.parametrize("fuse_sq,fuse_ks", [("0", "0"), ("1", "0"), ("0", "1"), ("1", "1")])
-@pytest.mark.parametrize("pname", ["t1k", "t2k"])
-def test_square_paths_agree(pname, fuse_sq, fuse_ks, monkeypatch):
-    """Fused and unfused square / key-switching paths give the oracle's exact ciphertexts."""
+_SQUARE_PATHS = [(p, fs, fk, lg) for p in ("t1k", "t2k")
+                 for fs, fk, lg in (("0", "0", ""), ("1", "0", "3"), ("1", "0", "4"), ("0", "1", ""),
+                                    ("1", "1", "3"), ("1", "1", "4"))]
+_SQUARE_PATHS += [("cfg2", "0", "0", ""), ("cfg2", "1", "1", "4"), ("cfg2", "1", "1", "5")]
+
+
+@pytest.mark.parametrize("pname,fuse_sq,fuse_ks,sq_loge", _SQUARE_PATHS)
+def test_square_paths_agree(pname, fuse_sq, fuse_ks, sq_loge, monkeypatch):
+    """Fused (each transform shape) and unfused square / key-switching paths give the oracle's
+    exact ciphertexts."""
     torch_cuda()
     from oracle import params
     from paper_2402_01296_amd import bcn
     monkeypatch.setenv("BCN_FUSE_SQUARE", fuse_sq)
     monkeypatch.setenv("BCN_FUSE_KS", fuse_ks)
+    if sq_loge:
+        monkeypatch.setenv("BCN_SQUARE_LOGE", sq_loge)
     prm, ctx = context(pname)
     s = synthetic.ternary_secret(31, prm.n)
     sk = ctx.secret_key(s)
