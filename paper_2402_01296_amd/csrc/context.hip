@@ -207,11 +207,11 @@ Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uin
 
   // per-prime tables
   const size_t N = n;
-  const size_t per = N + N / 2 + N;
+  const size_t per = N + N + N;
   std::vector<double> h((size_t)np * per);
   double* fwd = h.data();
   double* inv = fwd + (size_t)np * N;
-  double* post = inv + (size_t)np * (N / 2);
+  double* post = inv + (size_t)np * N;
   for (int id = 0; id < np; ++id) {
     const uint64_t q = c->primes[id];
     const uint64_t psi = host::negacyclic_root(q, N);
@@ -222,8 +222,15 @@ Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uin
     uint64_t x = 1;
     for (size_t i = 0; i < N; ++i) { pw[i] = x; x = host::mulmod(x, psi, q); }
     for (size_t i = 0; i < N; ++i) fwd[id * N + i] = (double)pw[host::bitrev((uint32_t)i, logn)];
+    // inverse twiddles, stage-major: stage s (2^s butterflies per block) uses
+    // omega^-(p N / 2^(s+1)) for positions p < 2^s, stored at [2^s + p], so the lanes of
+    // one wave (consecutive p) read consecutive words
+    std::vector<uint64_t> om(N / 2);
     x = 1;
-    for (size_t k = 0; k < N / 2; ++k) { inv[id * (N / 2) + k] = (double)x; x = host::mulmod(x, omega_inv, q); }
+    for (size_t k = 0; k < N / 2; ++k) { om[k] = x; x = host::mulmod(x, omega_inv, q); }
+    inv[id * N] = 0.0;
+    for (int st = 0; st < logn; ++st)
+      for (size_t p = 0; p < ((size_t)1 << st); ++p) inv[id * N + ((size_t)1 << st) + p] = (double)om[p * (N >> (st + 1))];
     x = ninv;
     for (size_t k = 0; k < N; ++k) { post[id * N + k] = (double)x; x = host::mulmod(x, psi_inv, q); }
   }
@@ -233,7 +240,7 @@ Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uin
   BCN_HIP(hipMemcpy(dm, c->hmods.data(), np * sizeof(Mod), hipMemcpyHostToDevice));
   c->tab.fwd = c->d_tables;
   c->tab.inv = c->d_tables + (size_t)np * N;
-  c->tab.post = c->d_tables + (size_t)np * N + (size_t)np * (N / 2);
+  c->tab.post = c->d_tables + (size_t)np * 2 * N;
   c->tab.mods = dm;
   c->tab.logn = logn;
 

@@ -26,7 +26,7 @@ struct Basis {
 // Device-resident per-prime tables (all binary64 integers).
 struct Tables {
   const double* fwd;   // [np][N]   psi^bitrev(i): twiddles of the forward transform
-  const double* inv;   // [np][N/2] omega^-k, omega = psi^2
+  const double* inv;   // [np][N]   stage-major: [2^s + p] = omega^-(p N / 2^(s+1)), omega = psi^2
   const double* post;  // [np][N]   N^-1 psi^-k: untwist of the inverse transform
   const Mod* mods;     // [np]
   int logn;

@@ -97,7 +97,7 @@ __device__ __forceinline__ void load_tw(double (&wt)[NT], const double* __restri
       } else {
         const unsigned r = base[g] & (SMIN - 1);
 #pragma unroll
-        for (int jl = 0; jl < (1 << l); ++jl) wt[k++] = tw[(r + jl * SMIN) * (N >> (s + 1))];
+        for (int jl = 0; jl < (1 << l); ++jl) wt[k++] = tw[(1u << s) + r + jl * SMIN];
       }
     }
   }
@@ -294,7 +294,7 @@ k_ntt(double* __restrict__ data, Basis basis, Tables tb) {
   const int pid = basis.id[limb];
   const Mod m = tb.mods[pid];
   double* a = data + ((size_t)poly * nb + limb) * N;
-  const double* tw = INV ? tb.inv + (size_t)pid * (N / 2) : tb.fwd + (size_t)pid * N;
+  const double* tw = INV ? tb.inv + (size_t)pid * N : tb.fwd + (size_t)pid * N;
   const double* post = tb.post + (size_t)pid * N;
   double x[1 << LOGE];
   run_pass<LOGN, LOGE, INV, 0, false, false, PF>(x, lds, a, a, tw, post, m, threadIdx.x);
@@ -340,7 +340,7 @@ k_ntt_persist(double* __restrict__ data, int total, Basis basis, Tables tb, int 
     if (next < total) gather_pass0<LOGN, LOGE, INV>(xn, data + (size_t)next * N, tid + z);
     const int pid = basis.id[limb % basis.n];
     const Mod m = tb.mods[pid];
-    const double* tw = INV ? tb.inv + (size_t)pid * (N / 2) : tb.fwd + (size_t)pid * N;
+    const double* tw = INV ? tb.inv + (size_t)pid * N : tb.fwd + (size_t)pid * N;
     const double* post = tb.post + (size_t)pid * N;
     double* a = data + (size_t)limb * N;
     run_pass<LOGN, LOGE, INV, 0, true, false>(x, lds + z, nullptr, a, tw, post, m, tid + z);
@@ -371,7 +371,7 @@ k_square_fused(const double* __restrict__ in, double* __restrict__ out, Basis ba
   const int pid = basis.id[limb];
   const Mod m = tb.mods[pid];
   const double* fw = tb.fwd + (size_t)pid * N;
-  const double* iw = tb.inv + (size_t)pid * (N / 2);
+  const double* iw = tb.inv + (size_t)pid * N;
   const double* post = tb.post + (size_t)pid * N;
   const double* a0 = in + ((size_t)(ct * 2) * nb + limb) * N;
   const double* a1 = in + ((size_t)(ct * 2 + 1) * nb + limb) * N;
@@ -443,7 +443,7 @@ k_ks_fused(const double* __restrict__ src, size_t src_stride, int level, int L, 
   const int pid = qp.id[limb];
   const Mod m = tb.mods[pid];
   const double* fw = tb.fwd + (size_t)pid * N;
-  const double* iw = tb.inv + (size_t)pid * (N / 2);
+  const double* iw = tb.inv + (size_t)pid * N;
   const double* post = tb.post + (size_t)pid * N;
   const double* xs = src + (size_t)ct * src_stride;
   const int KL = L + (nb - level);
