@@ -117,9 +117,10 @@ int bcn_ct_import(bcn_context* ctx, const uint64_t* host_in, int n, int level, d
 
 /* Negacyclic NTT of raw limbs in place: data device [n_polys][n_limbs][N] doubles,
  * limb i uses prime id first_prime + i (ids as in bcn_context_primes; the plaintext
- * modulus t has id n_q + n_p + n_aux).  Forward output position p holds
- * a(psi^(2j+1)) with j = bitreverse(p), psi the smallest x >= 2 with x^N = -1.
- * inverse != 0 applies the exact inverse (bit-reversed input, natural output). */
+ * modulus t has id n_q + n_p + n_aux).  Forward output word p holds a(psi^(2j+1))
+ * with j = bitreverse(i), i = (p mod N/16) * 16 + floor(p / (N/16)) (index i is
+ * stored at word (i mod 16) * N/16 + floor(i / 16)), psi the smallest x >= 2 with
+ * x^N = -1.  inverse != 0 applies the exact inverse (that order in, natural out). */
 int bcn_ntt(bcn_context* ctx, double* data, int n_polys, int n_limbs, int first_prime, int inverse,
             bcn_stream stream);
 

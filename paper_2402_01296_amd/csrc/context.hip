@@ -250,8 +250,8 @@ Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uin
   uint64_t g = 1;
   for (size_t i = 0; i < N / 2; ++i) {
     const uint64_t e0 = g, e1 = (two_n - g) % two_n;
-    pos[i] = host::bitrev((uint32_t)((e0 - 1) / 2), logn);
-    pos[N / 2 + i] = host::bitrev((uint32_t)((e1 - 1) / 2), logn);
+    pos[i] = ntt_store((int)host::bitrev((uint32_t)((e0 - 1) / 2), logn), logn);
+    pos[N / 2 + i] = ntt_store((int)host::bitrev((uint32_t)((e1 - 1) / 2), logn), logn);
     g = g * 3 % two_n;
   }
   BCN_HIP(hipMalloc(&c->d_slot_pos, N * sizeof(uint32_t)));

@@ -32,6 +32,15 @@ struct Tables {
   int logn;
 };
 
+// Storage order of transform-domain limbs.  Transform index i (evaluation point
+// psi^(2 bitrev(i) + 1)) is stored at word (i mod 16) * N/16 + floor(i / 16): the
+// forward transform's last pass, in which every thread holds 2^LOGE consecutive
+// indices, then writes lane-consecutive words, and the inverse transform's first
+// pass reads them the same way (with i stored at word i, every lane of a wave
+// touched its own cache line).  Requires N >= 16.
+BCN_HD int ntt_store(int i, int logn) { return ((i & 15) << (logn - 4)) + (i >> 4); }
+BCN_HD int ntt_index(int p, int logn) { return ((p & ((1 << (logn - 4)) - 1)) << 4) + (p >> (logn - 4)); }
+
 struct Error : std::runtime_error {
   int code;
   Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}

@@ -285,7 +285,8 @@ k_ks_inner(const double* __restrict__ D, KeySel ka, int n, int d_div, int level,
   const Mod m = mods[b.id[limb]];
   const int sel = (int)(o % ka.nk);
   const int g = ka.keys ? ka.galois[sel] : ka.galois1;
-  const int src = g == 1 ? k : ntt_perm(k, g, logn);
+  // positions are in transform-domain storage order; the permutation acts on transform indices
+  const int src = g == 1 ? k : ntt_store(ntt_perm(ntt_index(k, logn), g, logn), logn);
   const double* dd = D + (o / d_div) * dnum * nb * N + (size_t)limb * N + src;
   const double* key = ka.keys ? ka.keys[sel] : ka.key1;
   const int klimb = limb < level ? limb : L + (limb - level);

@@ -180,7 +180,10 @@ __device__ __forceinline__ void run_pass(double (&x)[1 << LOGE], double* lds, co
 #pragma unroll
       for (int g = 0; g < G; ++g)
 #pragma unroll
-        for (int j = 0; j < SZ; ++j) x[g * SZ + j] = src[base[g] + j * SMIN];
+        for (int j = 0; j < SZ; ++j) {
+          const int gi = base[g] + j * SMIN;
+          x[g * SZ + j] = src[INV ? ntt_store(gi, LOGN) : gi];   // inverse input is transform-domain
+        }
     }
   } else {
 #pragma unroll
@@ -244,7 +247,7 @@ __device__ __forceinline__ void run_pass(double (&x)[1 << LOGE], double* lds, co
           const int gi = base[g] + j * SMIN;
           double v = x[g * SZ + j];
           v = INV ? norm(mul_lazy(post[gi], v, m), m) : reduce(v, m);
-          a[gi] = v;
+          a[INV ? gi : ntt_store(gi, LOGN)] = v;
         }
     }
   } else {
@@ -315,7 +318,10 @@ __device__ __forceinline__ void gather_pass0(double (&x)[1 << LOGE], const doubl
     const int sid = g * T + tid;
     const int base = INV ? sid * SZ : sid;     // pass 0: one block (forward) / contiguous sets (inverse)
 #pragma unroll
-    for (int j = 0; j < SZ; ++j) x[g * SZ + j] = src[base + j * SMIN];
+    for (int j = 0; j < SZ; ++j) {
+      const int gi = base + j * SMIN;
+      x[g * SZ + j] = src[INV ? ntt_store(gi, LOGN) : gi];
+    }
   }
 }
 
@@ -490,12 +496,15 @@ k_ks_fused(const double* __restrict__ src, size_t src_stride, int level, int L, 
     // `zero` is 0 at run time; indexing through it keeps the per-pass address
     // arithmetic inside the digit loop instead of hoisting it into registers
     run_pass<LOGN, LOGE, false, 0, true, true>(x, lds + (j & zero), nullptr, nullptr, fw, post, m, tid + (j & zero));
-    const double* k0 = key + ((size_t)(j * 2) * KL + klimb) * N + (size_t)tid * E;
-    const double* k1 = key + ((size_t)(j * 2 + 1) * KL + klimb) * N + (size_t)tid * E;
+    // the forward transform leaves indices tid * E + i in the registers; the keys are
+    // stored in transform-domain storage order
+    const double* k0 = key + ((size_t)(j * 2) * KL + klimb) * N;
+    const double* k1 = key + ((size_t)(j * 2 + 1) * KL + klimb) * N;
 #pragma unroll
     for (int i = 0; i < E; ++i) {
-      acc0[i] += mul_lazy(k0[i], x[i], m);
-      acc1[i] += mul_lazy(k1[i], x[i], m);
+      const int p = ntt_store(tid * E + i, LOGN);
+      acc0[i] += mul_lazy(k0[p], x[i], m);
+      acc1[i] += mul_lazy(k1[p], x[i], m);
     }
   }
   double* u0 = u + ((size_t)(ct * 2) * nb + limb) * N;

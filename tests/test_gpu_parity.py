@@ -16,6 +16,11 @@ def _bitrev(x, bits):
     return int(format(x, "0%db" % bits)[::-1], 2)
 
 
+def _ntt_word_index(p, bits):
+    """Transform index held at storage word p (index i is stored at (i mod 16) * N/16 + i // 16)."""
+    return (p % (1 << (bits - 4))) * 16 + p // (1 << (bits - 4))
+
+
 @pytest.mark.parametrize("pname", ["t1k", "t2k"])
 def test_ntt_forward_is_the_definition(pname):
     torch = torch_cuda()
@@ -27,7 +32,7 @@ def test_ntt_forward_is_the_definition(pname):
     d = torch.from_numpy(x.astype(np.float64))[None].cuda()
     ctx.ntt(d, 0)
     got = d.cpu().numpy()[0].astype(np.uint64)
-    perm = np.array([_bitrev(p, bits) for p in range(n)])
+    perm = np.array([_bitrev(_ntt_word_index(p, bits), bits) for p in range(n)])
     for i, q in enumerate(primes):
         ref = np.array(ring.ntt([int(v) for v in x[i]], q, nt.negacyclic_root(q, n)), dtype=np.uint64)
         assert (got[i] == ref[perm]).all(), "limb %d (q=%d)" % (i, q)
@@ -49,7 +54,7 @@ def test_ntt_full_size_sampled():
         psi = nt.negacyclic_root(q, n)
         xi = [int(v) for v in x[i]]
         for pos in rng.integers(0, n, 6):
-            assert int(got[i, pos]) == ring.ntt_at(xi, q, psi, _bitrev(int(pos), bits))
+            assert int(got[i, pos]) == ring.ntt_at(xi, q, psi, _bitrev(_ntt_word_index(int(pos), bits), bits))
     ctx.ntt(d, 0, inverse=True)
     assert (d.cpu().numpy()[0].astype(np.uint64) == x).all()
 
