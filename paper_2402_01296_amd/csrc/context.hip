@@ -221,7 +221,11 @@ Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uin
     std::vector<uint64_t> pw(N);
     uint64_t x = 1;
     for (size_t i = 0; i < N; ++i) { pw[i] = x; x = host::mulmod(x, psi, q); }
-    for (size_t i = 0; i < N; ++i) fwd[id * N + i] = (double)pw[host::bitrev((uint32_t)i, logn)];
+    fwd[id * N] = (double)pw[0];
+    for (int st = 0; st < logn; ++st)
+      for (int b = 0; b < (1 << st); ++b)
+        fwd[id * N + ((size_t)1 << st) + fwd_tw_word(b, st, logn)] =
+            (double)pw[host::bitrev((uint32_t)((1u << st) + b), logn)];
     // inverse twiddles, stage-major: stage s (2^s butterflies per block) uses
     // omega^-(p N / 2^(s+1)) for positions p < 2^s, stored at [2^s + p], so the lanes of
     // one wave (consecutive p) read consecutive words

@@ -25,7 +25,7 @@ struct Basis {
 
 // Device-resident per-prime tables (all binary64 integers).
 struct Tables {
-  const double* fwd;   // [np][N]   psi^bitrev(i): twiddles of the forward transform
+  const double* fwd;   // [np][N]   forward twiddles psi^bitrev(2^s + b) at [2^s + fwd_tw_word(b, s)]
   const double* inv;   // [np][N]   stage-major: [2^s + p] = omega^-(p N / 2^(s+1)), omega = psi^2
   const double* post;  // [np][N]   N^-1 psi^-k: untwist of the inverse transform
   const Mod* mods;     // [np]
@@ -40,6 +40,17 @@ struct Tables {
 // touched its own cache line).  Requires N >= 16.
 BCN_HD int ntt_store(int i, int logn) { return ((i & 15) << (logn - 4)) + (i >> 4); }
 BCN_HD int ntt_index(int p, int logn) { return ((p & ((1 << (logn - 4)) - 1)) << 4) + (p >> (logn - 4)); }
+
+// Forward twiddles: stage s (2^s blocks) keeps psi^bitrev(2^s + b) for block b at
+// word 2^s + fwd_tw_word(b, s, logn).  In the last four stages the blocks of one
+// thread are consecutive and the lanes of a wave step by 2^(s - logn + 4); within
+// those stages the words are stored transposed (b mod M, b / M with M = 2^(s - logn + 4))
+// so that a wave's loads are lane-consecutive.
+BCN_HD int fwd_tw_word(int b, int s, int logn) {
+  const int lm = s - (logn - 4);
+  if (lm <= 0) return b;
+  return ((b & ((1 << lm) - 1)) << (s - lm)) + (b >> lm);
+}
 
 struct Error : std::runtime_error {
   int code;

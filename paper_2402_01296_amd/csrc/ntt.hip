@@ -92,7 +92,7 @@ __device__ __forceinline__ void load_tw(double (&wt)[NT], const double* __restri
 #pragma unroll
         for (int kb = 0; kb < (SZ >> (sh + 1)); ++kb) {
           const unsigned gi = base[g] + ((unsigned)kb << (sh + 1)) * SMIN;
-          wt[k++] = tw[(1u << s) + (gi >> (LOGN - s))];
+          wt[k++] = tw[(1u << s) + fwd_tw_word((int)(gi >> (LOGN - s)), s, LOGN)];
         }
       } else {
         const unsigned r = base[g] & (SMIN - 1);
