@@ -67,6 +67,12 @@ __device__ __forceinline__ int pass_base(int g, int tid) {
   return INV ? b * (SMIN << C) + r : b * (N >> S0) + r;
 }
 
+// Read-only load through the constant address space: with a wave-uniform index the
+// compiler issues it as a scalar load.
+__device__ __forceinline__ double const_load(const double* p, unsigned i) {
+  return ((const __attribute__((address_space(4))) double*)p)[i];
+}
+
 template <int LOGN, int LOGE, bool INV, int P, int NT>
 __device__ __forceinline__ void load_tw(double (&wt)[NT], const double* __restrict__ tw, const int tid) {
   using S = Shape<LOGN, LOGE>;
@@ -76,11 +82,17 @@ __device__ __forceinline__ void load_tw(double (&wt)[NT], const double* __restri
   constexpr int SZ = 1 << C;
   constexpr int G = S::E >> C;
   constexpr unsigned SMIN = INV ? (1u << S0) : (N >> (S0 + C));
+  // A pass whose twiddles are the same for all lanes of a wave (forward passes whose
+  // blocks span at least 64 lanes, inverse passes whose blocks start at every index)
+  // computes the indices from the wave's first lane, so they become scalar loads
+  // through the scalar cache instead of vector loads competing with the data stream.
+  constexpr bool UNIFORM = INV ? SMIN == 1 : SMIN >= 64;
+  const int t = UNIFORM ? __builtin_amdgcn_readfirstlane(tid) : tid;
   // unsigned 32-bit indices: lets the compiler address the table with a scalar base
   // and one 32-bit lane offset
   unsigned base[G];
 #pragma unroll
-  for (int g = 0; g < G; ++g) base[g] = (unsigned)pass_base<LOGN, LOGE, INV, P>(g, tid);
+  for (int g = 0; g < G; ++g) base[g] = (unsigned)pass_base<LOGN, LOGE, INV, P>(g, t);
   int k = 0;
 #pragma unroll
   for (int l = 0; l < C; ++l) {
@@ -92,12 +104,16 @@ __device__ __forceinline__ void load_tw(double (&wt)[NT], const double* __restri
 #pragma unroll
         for (int kb = 0; kb < (SZ >> (sh + 1)); ++kb) {
           const unsigned gi = base[g] + ((unsigned)kb << (sh + 1)) * SMIN;
-          wt[k++] = tw[(1u << s) + fwd_tw_word((int)(gi >> (LOGN - s)), s, LOGN)];
+          const unsigned w = (1u << s) + fwd_tw_word((int)(gi >> (LOGN - s)), s, LOGN);
+          wt[k++] = UNIFORM ? const_load(tw, w) : tw[w];
         }
       } else {
         const unsigned r = base[g] & (SMIN - 1);
 #pragma unroll
-        for (int jl = 0; jl < (1 << l); ++jl) wt[k++] = tw[(1u << s) + r + jl * SMIN];
+        for (int jl = 0; jl < (1 << l); ++jl) {
+          const unsigned w = (1u << s) + r + jl * SMIN;
+          wt[k++] = UNIFORM ? const_load(tw, w) : tw[w];
+        }
       }
     }
   }
