@@ -277,8 +277,17 @@ Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uin
   // the fused square keeps three register sets live; above N = 8192 it would spill
   c->fuse_square = logn <= 13;
   if (const char* env = std::getenv("BCN_FUSE_SQUARE")) c->fuse_square = logn <= 13 && std::atoi(env) != 0;
-  c->fuse_ks = logn <= 13 && alpha <= 2;
-  if (const char* env = std::getenv("BCN_FUSE_KS")) c->fuse_ks = logn <= 13 && alpha <= 2 && std::atoi(env) != 0;
+  // the fused kernel keeps two accumulators and a working set in registers: N <= 8192, digits of <= 2 primes
+  const bool can_fuse_ks = logn <= 13 && alpha <= 2;
+  c->ks_mode = alpha <= 2 ? 2 : 0;
+  if (const char* env = std::getenv("BCN_FUSE_KS")) {
+    c->ks_mode = std::atoi(env) != 0 && can_fuse_ks ? 1 : 0;
+    c->pinned_ks = true;
+  }
+  if (const char* env = std::getenv("BCN_KS_MODE")) {
+    const int v = std::atoi(env);
+    if (v == 0 || (v == 1 && can_fuse_ks) || (v == 2 && alpha <= 2)) c->ks_mode = v, c->pinned_ks = true;
+  }
   if (const char* env = std::getenv("BCN_NTT_PERSIST")) c->ntt_persist = std::atoi(env) != 0;
   if (const char* env = std::getenv("BCN_NTT_PREFETCH")) c->ntt_prefetch = std::atoi(env) != 0, c->pinned_prefetch = true;
   {

@@ -52,6 +52,17 @@ BCN_HD int fwd_tw_word(int b, int s, int logn) {
   return ((b & ((1 << lm) - 1)) << (s - lm)) + (b >> lm);
 }
 
+__device__ __forceinline__ int bitrev_n(int x, int logn) { return (int)(__brev((unsigned)x) >> (32 - logn)); }
+
+// Transform-domain automorphism: sigma_k(a)^ at transform index i is a^ at the
+// returned transform index (evaluation point psi^(2 bitrev(i) + 1) maps to its k-th power).
+__device__ __forceinline__ int ntt_perm(int i, int galois, int logn) {
+  const int N = 1 << logn;
+  const int j = bitrev_n(i, logn);
+  const int e = (int)(((long long)(2 * j + 1) * galois) & (2 * N - 1));
+  return bitrev_n((e - 1) >> 1, logn);
+}
+
 struct Error : std::runtime_error {
   int code;
   Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
@@ -118,7 +129,9 @@ struct Context {
   bool ntt_persist = false;              // persistent, prefetching transform kernel
   bool ntt_prefetch = false;             // transform loads the next pass's twiddles before each exchange
   int persist_blocks = 512;              // its grid: workgroups resident at once
-  bool fuse_ks = true;                   // key switching's digits, transforms and products in one kernel
+  int ks_mode = 2;                       // key switching: 0 ModUp + NTT + inner product + INTT (four kernels),
+                                         // 1 one fused kernel, 2 digits+NTT and inner product+INTT (two kernels)
+  bool pinned_ks = false;
   std::vector<int> ntt_loge_options() const;
 
   int idQ(int i) const { return i; }
@@ -228,6 +241,12 @@ struct KeySel {
 };
 void ks_inner(const Context& c, const double* D, int d_div, const KeySel& ks, int n, int level, double* out,
               hipStream_t s);
+// Key switching in two kernels: digits of n_src sources formed and transformed into D
+// ([n_src][dnum][level + K][N], transform domain), then for each of n_out outputs the
+// inner product with its key (output o uses source o / d_div) and both inverse
+// transforms into u ([n_out][2][level + K][N], coefficient form).
+void ks_split(const Context& c, const double* src, size_t src_stride, int n_src, int level, const KeySel& ks,
+              int n_out, int d_div, double* D, double* u, hipStream_t s);
 // exact round(u/P) of u [n][2][level+K][N] (coeff) -> [n][2][level][N], plus an addend:
 // add_mode 0: none; 1: add [n][2][level][N]; 2: add sigma_k(add) to part 0 only (add [n][2][level][N]).
 // With modswitch the result is further rounded by q_level to level-1 limbs.

@@ -262,15 +262,6 @@ k_modup(const double* __restrict__ in, size_t in_stride, double* __restrict__ ou
   }
 }
 
-__device__ __forceinline__ int bitrev_n(int x, int logn) { return (int)(__brev((unsigned)x) >> (32 - logn)); }
-
-// NTT-domain automorphism: sigma_k(a)^ at position pos = a^ at the returned position
-__device__ __forceinline__ int ntt_perm(int pos, int galois, int logn) {
-  const int N = 1 << logn;
-  const int j = bitrev_n(pos, logn);
-  const int e = (int)(((long long)(2 * j + 1) * galois) & (2 * N - 1));
-  return bitrev_n((e - 1) >> 1, logn);
-}
 
 
 __global__ void __launch_bounds__(TPB)

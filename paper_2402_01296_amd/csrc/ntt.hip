@@ -544,6 +544,158 @@ void launch_persist(const Context& c, double* data, int n_polys, const Basis& b,
   BCN_HIP(hipGetLastError());
 }
 
+
+template <int LOGN, int LOGE>
+void launch_ks(const Context& c, const double* src, size_t stride, int n, int level, const KsDigits& dg,
+               const double* key, int kinv, double* u, const Basis& qp, hipStream_t s) {
+  constexpr int N = 1 << LOGN;
+  const unsigned blocks = (unsigned)n * qp.n;
+  if (blocks == 0) return;
+#define BCN_KSL(NA, GAL)                                                                                 \
+  hipLaunchKernelGGL((k_ks_fused<LOGN, LOGE, NA, GAL>), dim3(blocks), dim3(N >> LOGE), (size_t)N * sizeof(double), s, \
+                     src, stride, level, c.L, c.dnum(level), dg, key, kinv, u, qp, c.tab, 0)
+  if (c.alpha == 1) {
+    if (kinv == 1) BCN_KSL(1, false); else BCN_KSL(1, true);
+  } else {
+    if (kinv == 1) BCN_KSL(2, false); else BCN_KSL(2, true);
+  }
+#undef BCN_KSL
+  BCN_HIP(hipGetLastError());
+}
+
+// Key-switching digits straight into the transform domain.  Block (poly, digit j,
+// target limb) forms D_j = lift_c([x]_{Q_j}) mod the target prime while gathering
+// the forward transform's first pass from the source residues, transforms it and
+// stores it in transform-domain order at D[poly][j][limb] (the layout the four-kernel
+// path builds with ModUp and a forward transform).
+template <int LOGN, int LOGE, int NA>
+__global__ void __launch_bounds__(1 << (LOGN - LOGE))
+k_ntt_digits(const double* __restrict__ src, size_t src_stride, int dnum, KsDigits dg, double* __restrict__ D,
+             Basis qp, Tables tb) {
+  using S = Shape<LOGN, LOGE>;
+  constexpr int N = S::N, E = S::E, T = S::T;
+  constexpr int C0 = S::C0;
+  constexpr int SMIN0 = N >> C0, SZ0 = 1 << C0, G0 = E >> C0;
+  extern __shared__ double lds[];
+  const int nb = qp.n;
+  // consecutive blocks (one XCD) take the target limbs of one (poly, digit): the
+  // digit's source residues are read once from HBM and then hit that XCD's L2
+  const int w = xcd_order(blockIdx.x, gridDim.x);
+  const int limb = w % nb, pj = w / nb;
+  const int j = pj % dnum, poly = pj / dnum;
+  const int pid = qp.id[limb];
+  const Mod m = tb.mods[pid];
+  const double* xs = src + (size_t)poly * src_stride;
+  const int lo = dg.lo[j], na = dg.na[j];
+  const bool inside = limb >= lo && limb < lo + na;
+  const Mod mq = tb.mods[lo];                      // Q prime ids equal their limb index
+  const int tid = threadIdx.x;
+  double x[E];
+#pragma unroll
+  for (int g = 0; g < G0; ++g)
+#pragma unroll
+    for (int jj = 0; jj < SZ0; ++jj) {
+      const int sp = g * T + tid + jj * SMIN0;
+      double v;
+      if (inside) {
+        v = xs[(size_t)limb * N + sp];
+      } else if (NA == 1 || na == 1) {
+        const double xv = xs[(size_t)lo * N + sp];
+        const double c = xv > (mq.q - 1.0) * 0.5 ? xv - mq.q : xv;   // |c| < q_j / 2 < p
+        v = c < 0.0 ? c + m.q : c;
+      } else {
+        const Conv& cv = *dg.cv[j];
+        const double xa[2] = {xs[(size_t)lo * N + sp], xs[(size_t)(lo + 1) * N + sp]};
+        double va[2];
+        garner<2>(xa, va, cv, tb.mods);
+        double a = mul_lazy(va[1], cv.pm[limb][0], m) + va[0];
+        if (above_half<2>(va, 2, cv, tb.mods)) a -= cv.Mmod[limb];
+        v = reduce(a, m);
+      }
+      x[g * SZ0 + jj] = v;
+    }
+  run_pass<LOGN, LOGE, false, 0, true, false>(x, lds, nullptr, D + ((size_t)pj * nb + limb) * N,
+                                              tb.fwd + (size_t)pid * N, tb.post, m, tid);
+}
+
+// Key-switching inner product fused into the inverse transforms.  Block (output o,
+// target limb) accumulates u_k = sum_j sigma(D_j^) * key_j[k] (k = 0, 1; sigma the
+// transform-domain Galois permutation of output o's key, none for
+// relinearisation) while gathering the inverse transform's first pass, then
+// inverse-transforms both accumulators into u[o][k][limb] (coefficient form).
+// Output o reads the digits of source o / d_div.
+template <int LOGN, int LOGE>
+__global__ void __launch_bounds__(1 << (LOGN - LOGE))
+k_ks_intt(const double* __restrict__ D, int d_div, KeySel ka, int level, int dnum, int L, Basis qp, Tables tb,
+          double* __restrict__ u) {
+  using S = Shape<LOGN, LOGE>;
+  constexpr int N = S::N, E = S::E, T = S::T;
+  constexpr int C0 = Sched<LOGN, LOGE, true>::c(0);
+  constexpr int SZ0 = 1 << C0, G0 = E >> C0;
+  extern __shared__ double lds[];
+  const int nb = qp.n;
+  const int w = xcd_order(blockIdx.x, gridDim.x);
+  const int limb = w % nb, o = w / nb;
+  const int pid = qp.id[limb];
+  const Mod m = tb.mods[pid];
+  const int sel = o % ka.nk;
+  const int gal = ka.keys ? ka.galois[sel] : ka.galois1;
+  const double* key = ka.keys ? ka.keys[sel] : ka.key1;
+  const double* dd = D + (size_t)(o / d_div) * dnum * nb * N + (size_t)limb * N;
+  const int klimb = limb < level ? limb : L + (limb - level);
+  const int KL = nb - level + L;                   // limbs of a key part (L + K)
+  const int tid = threadIdx.x;
+  double x[E], acc1[E];
+#pragma unroll
+  for (int g = 0; g < G0; ++g)
+#pragma unroll
+    for (int jj = 0; jj < SZ0; ++jj) {
+      // the inverse transform's first pass holds indices sid * SZ0 + jj, sid = g * T + tid
+      const int gi = (g * T + tid) * SZ0 + jj;
+      const int p = ntt_store(gi, LOGN);
+      const int ps = gal == 1 ? p : ntt_store(ntt_perm(gi, gal, LOGN), LOGN);
+      double a0 = 0.0, a1 = 0.0;
+      for (int j = 0; j < dnum; ++j) {
+        const double dj = dd[(size_t)j * nb * N + ps];
+        a0 += mul_lazy(dj, key[((size_t)(j * 2) * KL + klimb) * N + p], m);
+        a1 += mul_lazy(dj, key[((size_t)(j * 2 + 1) * KL + klimb) * N + p], m);
+      }
+      x[g * SZ0 + jj] = reduce(a0, m);
+      acc1[g * SZ0 + jj] = reduce(a1, m);
+    }
+  const double* iw = tb.inv + (size_t)pid * N;
+  const double* post = tb.post + (size_t)pid * N;
+  run_pass<LOGN, LOGE, true, 0, true, false>(x, lds, nullptr, u + ((size_t)(o * 2) * nb + limb) * N, iw, post, m,
+                                             tid);
+  run_pass<LOGN, LOGE, true, 0, true, false>(acc1, lds, nullptr, u + ((size_t)(o * 2 + 1) * nb + limb) * N, iw, post,
+                                             m, tid);
+}
+
+template <int LOGN, int LOGE>
+void launch_ks_split(const Context& c, int part, const double* src, size_t stride, int n_src, int level,
+                     const KsDigits& dg, double* D, const KeySel& ks, int n_out, int d_div, double* u, const Basis& qp,
+                     hipStream_t s) {
+  constexpr int N = 1 << LOGN;
+  const size_t lds = (size_t)N * sizeof(double);
+  const int dnum = c.dnum(level);
+  const unsigned b1 = part == 1 ? (unsigned)n_src * dnum * qp.n : 0u;
+  if (b1 > 0) {
+    if (c.alpha == 1)
+      hipLaunchKernelGGL((k_ntt_digits<LOGN, LOGE, 1>), dim3(b1), dim3(N >> LOGE), lds, s, src, stride, dnum, dg, D, qp,
+                         c.tab);
+    else
+      hipLaunchKernelGGL((k_ntt_digits<LOGN, LOGE, 2>), dim3(b1), dim3(N >> LOGE), lds, s, src, stride, dnum, dg, D, qp,
+                         c.tab);
+    BCN_HIP(hipGetLastError());
+  }
+  const unsigned b2 = part == 2 ? (unsigned)n_out * qp.n : 0u;
+  if (b2 > 0) {
+    hipLaunchKernelGGL((k_ks_intt<LOGN, LOGE>), dim3(b2), dim3(N >> LOGE), lds, s, D, d_div, ks, level, dnum, c.L, qp,
+                       c.tab, u);
+    BCN_HIP(hipGetLastError());
+  }
+}
+
 template <int LOGN, int LOGE>
 void set_attr() {
   const int lds = (1 << LOGN) * (int)sizeof(double);
@@ -565,24 +717,9 @@ void set_attr() {
                               lds));
   BCN_HIP(hipFuncSetAttribute((const void*)k_ks_fused<LOGN, LOGE, 2, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               lds));
-}
-
-template <int LOGN, int LOGE>
-void launch_ks(const Context& c, const double* src, size_t stride, int n, int level, const KsDigits& dg,
-               const double* key, int kinv, double* u, const Basis& qp, hipStream_t s) {
-  constexpr int N = 1 << LOGN;
-  const unsigned blocks = (unsigned)n * qp.n;
-  if (blocks == 0) return;
-#define BCN_KSL(NA, GAL)                                                                                 \
-  hipLaunchKernelGGL((k_ks_fused<LOGN, LOGE, NA, GAL>), dim3(blocks), dim3(N >> LOGE), (size_t)N * sizeof(double), s, \
-                     src, stride, level, c.L, c.dnum(level), dg, key, kinv, u, qp, c.tab, 0)
-  if (c.alpha == 1) {
-    if (kinv == 1) BCN_KSL(1, false); else BCN_KSL(1, true);
-  } else {
-    if (kinv == 1) BCN_KSL(2, false); else BCN_KSL(2, true);
-  }
-#undef BCN_KSL
-  BCN_HIP(hipGetLastError());
+  BCN_HIP(hipFuncSetAttribute((const void*)k_ntt_digits<LOGN, LOGE, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+  BCN_HIP(hipFuncSetAttribute((const void*)k_ntt_digits<LOGN, LOGE, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+  BCN_HIP(hipFuncSetAttribute((const void*)k_ks_intt<LOGN, LOGE>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
 }
 
 template <int LOGN, int LOGE>
@@ -675,12 +812,11 @@ void square_transform_fused(const Context& c, const double* in, double* out, int
 
 const Conv* conv_device(const Context& c, const std::string& key, const Conv& cv);
 
-void ks_fused(const Context& c, const double* src, size_t src_stride, int n, int level, const double* key, int galois,
-              double* u, hipStream_t s) {
+namespace {
+KsDigits ks_digits(const Context& c, int level, const Basis& qp) {
   if (c.alpha > 2) throw Error(-1, "fused key switching supports digits of at most two primes");
   const int dnum = c.dnum(level);
   if (dnum > 8) throw Error(-1, "too many digits");
-  const Basis qp = c.basis_QP(level);
   KsDigits dg{};
   for (int j = 0; j < dnum; ++j) {
     const int lo = j * c.alpha, hi = std::min((j + 1) * c.alpha, level);
@@ -694,6 +830,44 @@ void ks_fused(const Context& c, const double* src, size_t src_stride, int n, int
       dg.cv[j] = conv_device(c, "ksd" + std::to_string(level) + "_" + std::to_string(j), make_conv(c, src_ids, dst));
     }
   }
+  return dg;
+}
+}  // namespace
+
+void ks_split(const Context& c, const double* src, size_t src_stride, int n_src, int level, const KeySel& ks,
+              int n_out, int d_div, double* D, double* u, hipStream_t s) {
+  const Basis qp = c.basis_QP(level);
+  const KsDigits dg = ks_digits(c, level, qp);
+  const int dnum = c.dnum(level);
+  const double tr = 8.0 * (c.n / 2) * c.logn + 4.0 * c.n;        // FP64 ops of one limb transform
+  const int key = c.logn * 16 + c.ntt_loge;
+  for (int part = 1; part <= 2; ++part) {
+    // digits: source limbs once, digits out, dnum * (level + K) forward transforms per source;
+    // inner product: digits and two key parts in, two parts out, two inverse transforms per output limb
+    const double u1 = (double)n_src * dnum * qp.n, u2 = (double)n_out * qp.n;
+    ProfScope ps(c, part == 1 ? "ntt_digits" : "ks_intt", s,
+                 part == 1 ? 8.0 * c.n * ((double)n_src * level + u1) : 8.0 * c.n * u2 * (dnum + 2.0),
+                 part == 1 ? u1 * tr : u2 * (2.0 * tr + dnum * 2.0 * 7.0 * c.n));
+    switch (key) {
+#define BCN_KSS_CASE(LN, LE)                                                                                 \
+  case LN * 16 + LE:                                                                                         \
+    launch_ks_split<LN, LE>(c, part, src, src_stride, n_src, level, dg, D, ks, n_out, d_div, u, qp, s); break;
+      BCN_KSS_CASE(10, 3) BCN_KSS_CASE(10, 4)
+      BCN_KSS_CASE(11, 3) BCN_KSS_CASE(11, 4)
+      BCN_KSS_CASE(12, 4) BCN_KSS_CASE(12, 5)
+      BCN_KSS_CASE(13, 4) BCN_KSS_CASE(13, 5)
+      BCN_KSS_CASE(14, 4) BCN_KSS_CASE(14, 5)
+#undef BCN_KSS_CASE
+      default: throw Error(-1, "unsupported ring degree / transform shape");
+    }
+  }
+}
+
+void ks_fused(const Context& c, const double* src, size_t src_stride, int n, int level, const double* key, int galois,
+              double* u, hipStream_t s) {
+  const Basis qp = c.basis_QP(level);
+  const KsDigits dg = ks_digits(c, level, qp);
+  const int dnum = c.dnum(level);
   const int kinv = galois == 1 ? 1 : (int)host::inv_pow2((uint64_t)galois, c.logn + 1);
   // algorithmic traffic: digit sources (level limbs per target limb), two key limbs per digit, two outputs
   const double units = (double)n * qp.n;

@@ -252,8 +252,11 @@ void square_relin(Context& c, const EvalKeys& ek, const double* in, double* out,
   double* U = ar.take((size_t)n * 2 * nbp * N);
   KeySel ks;
   ks.key1 = ek.relin;
-  if (c.fuse_ks) {
+  if (c.ks_mode == 1) {
     ks_fused(c, Z + 2 * level * N, (size_t)3 * level * N, n, level, ek.relin, 1, U, s);
+  } else if (c.ks_mode == 2) {
+    double* D = ar.take((size_t)n * dn * nbp * N);
+    ks_split(c, Z + 2 * level * N, (size_t)3 * level * N, n, level, ks, n, 1, D, U, s);
   } else {
     double* D = ar.take((size_t)n * dn * nbp * N);
     decompose_modup(c, Z + 2 * level * N, (size_t)3 * level * N, D, n, level, s);
@@ -274,16 +277,20 @@ void rotate_hoisted(Context& c, EvalKeys& ek, const double* in, int n_in, int le
   const int nbp = qp.n, dn = c.dnum(level);
   const KeyTable& tb = ek.table(steps);
   double* D = ar.take((size_t)n_in * dn * nbp * N);
-  decompose_modup(c, in + level * N, (size_t)2 * level * N, D, n_in, level, s);
-  ntt_forward(c, D, n_in * dn, qp, s);
   double* U = ar.take((size_t)n_in * ns * 2 * nbp * N);
   KeySel ks;
   ks.keys = tb.keys;
   ks.galois = tb.galois;
   ks.kinv = tb.kinv;
   ks.nk = tb.nk;
-  ks_inner(c, D, ns, ks, n_in * ns, level, U, s);
-  ntt_inverse(c, U, 2 * n_in * ns, qp, s);
+  if (c.ks_mode == 2) {
+    ks_split(c, in + level * N, (size_t)2 * level * N, n_in, level, ks, n_in * ns, ns, D, U, s);
+  } else {
+    decompose_modup(c, in + level * N, (size_t)2 * level * N, D, n_in, level, s);
+    ntt_forward(c, D, n_in * dn, qp, s);
+    ks_inner(c, D, ns, ks, n_in * ns, level, U, s);
+    ntt_inverse(c, U, 2 * n_in * ns, qp, s);
+  }
   moddown(c, U, n_in * ns, level, in, ns, (size_t)2 * level * N, 2, ks, false, out, s, out_div, out_outer);
 }
 
@@ -302,8 +309,10 @@ void rotate_sum(Context& c, const EvalKeys& ek, double* ct, int n, int level, in
     ks.key1 = ek.rot_key(r);
     ks.galois1 = galois_element(c, r);
     ks.kinv1 = galois_inverse(c, ks.galois1);
-    if (c.fuse_ks) {
+    if (c.ks_mode == 1) {
       ks_fused(c, ct + level * N, (size_t)2 * level * N, n, level, ks.key1, ks.galois1, U, s);
+    } else if (c.ks_mode == 2) {
+      ks_split(c, ct + level * N, (size_t)2 * level * N, n, level, ks, n, 1, D, U, s);
     } else {
       decompose_modup(c, ct + level * N, (size_t)2 * level * N, D, n, level, s);
       ntt_forward(c, D, n * dn, qp, s);

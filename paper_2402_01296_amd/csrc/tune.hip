@@ -133,12 +133,14 @@ std::string autotune_ntt(Context& c, hipStream_t s) {
     c.fuse_square = false;
   }
   report += std::string("square chosen fused=") + (c.fuse_square ? "1" : "0") + "\n";
-  // key switching: fused digits/transforms/products vs modup + transforms + inner product
-  if (c.logn <= 13 && c.alpha <= 2) {
+  // key switching: four kernels (ModUp, forward transforms, inner product, inverse
+  // transforms), one fused kernel, or two kernels (digits + forward transform, inner
+  // product + inverse transforms), on a batch shaped like the first relinearisation
+  if (!c.pinned_ks) {
     const int level = c.L;
     const Basis qp = c.basis_QP(level);
     const int dn = c.dnum(level);
-    const int n = std::max(8, 2048 / (qp.n * (dn + 2)));
+    const int n = std::max(8, 8192 / (qp.n * (dn + 2)));
     double* src = c.arena->take((size_t)n * level * c.n);
     double* key = c.arena->take((size_t)dn * 2 * (c.L + c.K) * c.n);
     double* D = c.arena->take((size_t)n * dn * qp.n * c.n);
@@ -147,22 +149,28 @@ std::string autotune_ntt(Context& c, hipStream_t s) {
     BCN_HIP(hipMemsetAsync(key, 0, (size_t)dn * 2 * (c.L + c.K) * c.n * sizeof(double), s));
     KeySel ks;
     ks.key1 = key;
-    const float unfused = time_ms(s, 5, [&] {
+    float t[3] = {1e30f, 1e30f, 1e30f};
+    t[0] = time_ms(s, 5, [&] {
       decompose_modup(c, src, (size_t)level * c.n, D, n, level, s);
       ntt_forward(c, D, n * dn, qp, s);
       ks_inner(c, D, 1, ks, n, level, U, s);
       ntt_inverse(c, U, 2 * n, qp, s);
     });
-    const float fused = time_ms(s, 5, [&] { ks_fused(c, src, (size_t)level * c.n, n, level, key, 1, U, s); });
-    char line[160];
-    std::snprintf(line, sizeof line, "key switch (%d polynomials, %d digits): fused %.3f ms, unfused %.3f ms\n", n, dn,
-                  fused, unfused);
+    if (c.logn <= 13 && c.alpha <= 2)
+      t[1] = time_ms(s, 5, [&] { ks_fused(c, src, (size_t)level * c.n, n, level, key, 1, U, s); });
+    if (c.alpha <= 2) t[2] = time_ms(s, 5, [&] { ks_split(c, src, (size_t)level * c.n, n, level, ks, n, 1, D, U, s); });
+    char line[200];
+    std::snprintf(line, sizeof line,
+                  "key switch (%d polynomials, %d digits): four kernels %.3f ms, fused %.3f ms, two kernels %.3f ms\n", n,
+                  dn, t[0], t[1] < 1e29f ? t[1] : -1.0f, t[2] < 1e29f ? t[2] : -1.0f);
     report += line;
-    c.fuse_ks = fused < unfused;
-  } else {
-    c.fuse_ks = false;
+    const int dflt = c.ks_mode;
+    int best = dflt;
+    for (int k = 0; k < 3; ++k)
+      if (t[k] < t[best]) best = k;
+    c.ks_mode = t[best] < kMargin * t[dflt] ? best : dflt;
   }
-  report += std::string("key switch chosen fused=") + (c.fuse_ks ? "1" : "0") + "\n";
+  report += "key switch chosen mode=" + std::to_string(c.ks_mode) + "\n";
   return report;
 }
 

@@ -273,21 +273,25 @@ def test_transform_shapes_agree(pname, persist, monkeypatch):
     assert all((o == outs[0]).all() for o in outs)
 
 
-_SQUARE_PATHS = [(p, fs, fk, lg) for p in ("t1k", "t2k")
-                 for fs, fk, lg in (("0", "0", ""), ("1", "0", "3"), ("1", "0", "4"), ("0", "1", ""),
-                                    ("1", "1", "3"), ("1", "1", "4"))]
-_SQUARE_PATHS += [("cfg2", "0", "0", ""), ("cfg2", "1", "1", "4"), ("cfg2", "1", "1", "5")]
+# (parameter set, fused square, key-switch mode, square transform shape); key-switch modes:
+# 0 four kernels, 1 one fused kernel, 2 digits+NTT and inner product+INTT
+_SQUARE_PATHS = [(p, fs, km, lg) for p in ("t1k", "t2k")
+                 for fs, km, lg in (("0", "0", ""), ("1", "0", "3"), ("1", "0", "4"), ("0", "1", ""),
+                                    ("1", "1", "3"), ("1", "1", "4"), ("0", "2", ""), ("1", "2", "3"),
+                                    ("1", "2", "4"))]
+_SQUARE_PATHS += [("cfg2", "0", "0", ""), ("cfg2", "1", "1", "4"), ("cfg2", "1", "1", "5"), ("cfg2", "1", "2", "4"),
+                  ("cfg2", "1", "2", "5")]
 
 
-@pytest.mark.parametrize("pname,fuse_sq,fuse_ks,sq_loge", _SQUARE_PATHS)
-def test_square_paths_agree(pname, fuse_sq, fuse_ks, sq_loge, monkeypatch):
-    """Fused (each transform shape) and unfused square / key-switching paths give the oracle's
-    exact ciphertexts."""
+@pytest.mark.parametrize("pname,fuse_sq,ks_mode,sq_loge", _SQUARE_PATHS)
+def test_square_paths_agree(pname, fuse_sq, ks_mode, sq_loge, monkeypatch):
+    """Fused (each transform shape) and unfused square, and every key-switching path, give the
+    oracle's exact ciphertexts."""
     torch_cuda()
     from oracle import params
     from paper_2402_01296_amd import bcn
     monkeypatch.setenv("BCN_FUSE_SQUARE", fuse_sq)
-    monkeypatch.setenv("BCN_FUSE_KS", fuse_ks)
+    monkeypatch.setenv("BCN_KS_MODE", ks_mode)
     if sq_loge:
         monkeypatch.setenv("BCN_SQUARE_LOGE", sq_loge)
     prm, ctx = context(pname)
@@ -304,12 +308,13 @@ def test_square_paths_agree(pname, fuse_sq, fuse_ks, sq_loge, monkeypatch):
         assert (got[i] == bfv.ct_to_rns(prm, ref)).all()
 
 
-@pytest.mark.parametrize("fuse_ks", ["0", "1"])
-def test_rotate_sum_paths_agree(fuse_ks, monkeypatch):
-    """Rotate-and-sum through the fused key switch (automorphism folded into the digit gather)."""
+@pytest.mark.parametrize("ks_mode", ["0", "1", "2"])
+def test_rotate_sum_paths_agree(ks_mode, monkeypatch):
+    """Rotate-and-sum through every key-switching path (fused: automorphism folded into the
+    digit gather; two kernels: transform-domain permutation in the inner product)."""
     torch_cuda()
     from paper_2402_01296_amd import bcn
-    monkeypatch.setenv("BCN_FUSE_KS", fuse_ks)
+    monkeypatch.setenv("BCN_KS_MODE", ks_mode)
     prm, ctx = context("t2k")
     s = synthetic.ternary_secret(33, prm.n)
     sk = ctx.secret_key(s)
@@ -329,3 +334,31 @@ def test_rotate_sum_paths_agree(fuse_ks, monkeypatch):
             for r in (4, 2, 1):
                 c = bfv.add(prm, c, bfv.rotate(prm, c, r, gk[r]))
             assert (got[i] == bfv.ct_to_rns(prm, c)).all(), "ct %d level %d" % (i, level)
+
+
+@pytest.mark.parametrize("ks_mode", ["0", "2"])
+@pytest.mark.parametrize("pname", ["t1k", "t2k"])
+def test_rotation_hoisted_paths_agree(pname, ks_mode, monkeypatch):
+    """Hoisted rotations (one digit decomposition per source, several Galois keys) through the
+    four-kernel and two-kernel key-switching paths, against the oracle."""
+    torch_cuda()
+    from paper_2402_01296_amd import bcn
+    monkeypatch.setenv("BCN_KS_MODE", ks_mode)
+    prm, ctx = context(pname)
+    s = synthetic.ternary_secret(35, prm.n)
+    sk = ctx.secret_key(s)
+    ek = ctx.eval_keys()
+    steps = [1, 5, 64]
+    gk = {}
+    for r in steps:
+        a, e = key_randomness(prm, 35, 1000 + r)
+        ctx.keygen(sk, ek, bcn.BCN_KEY_ROTATION, r, np.stack(a), np.stack(e))
+        gk[r] = bfv.galois_key(prm, [int(v) for v in s], r, a, e)
+    level = prm.L
+    res = random_ct_residues(prm, level, 3, 95)
+    got = ctx.export(ctx.rotate(ek, ctx.import_(res), steps).reshape(-1, 2, level, prm.n))
+    for i in range(3):
+        c = oracle_ct(prm, res[i])
+        for si, r in enumerate(steps):
+            ref = bfv.rotate(prm, c, r, gk[r])
+            assert (got[i * len(steps) + si] == bfv.ct_to_rns(prm, ref)).all(), "ct %d step %d" % (i, r)
