@@ -131,6 +131,7 @@ struct Context {
   int persist_blocks = 512;              // its grid: workgroups resident at once
   int ks_mode = 2;                       // key switching: 0 ModUp + NTT + inner product + INTT (four kernels),
                                          // 1 one fused kernel, 2 digits+NTT and inner product+INTT (two kernels)
+  int ks_mode_rot = 2;                   // the same for hoisted rotations (0 or 2)
   bool pinned_ks = false;
   std::vector<int> ntt_loge_options() const;
 

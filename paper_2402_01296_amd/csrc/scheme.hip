@@ -283,7 +283,7 @@ void rotate_hoisted(Context& c, EvalKeys& ek, const double* in, int n_in, int le
   ks.galois = tb.galois;
   ks.kinv = tb.kinv;
   ks.nk = tb.nk;
-  if (c.ks_mode == 2) {
+  if (c.ks_mode_rot == 2) {
     ks_split(c, in + level * N, (size_t)2 * level * N, n_in, level, ks, n_in * ns, ns, D, U, s);
   } else {
     decompose_modup(c, in + level * N, (size_t)2 * level * N, D, n_in, level, s);

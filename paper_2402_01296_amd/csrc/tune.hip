@@ -169,8 +169,30 @@ std::string autotune_ntt(Context& c, hipStream_t s) {
     for (int k = 0; k < 3; ++k)
       if (t[k] < t[best]) best = k;
     c.ks_mode = t[best] < kMargin * t[dflt] ? best : dflt;
+    // hoisted rotations: each source's digits serve several Galois keys, and the
+    // transform-domain permutation scatters the inner product's digit reads
+    if (c.alpha <= 2) {
+      const int ns = 8, nsrc = std::max(2, n / ns);
+      double* U2 = c.arena->take((size_t)nsrc * ns * 2 * qp.n * c.n);
+      KeySel kr;
+      kr.key1 = key;
+      kr.galois1 = 3;
+      const float r0 = time_ms(s, 3, [&] {
+        decompose_modup(c, src, (size_t)level * c.n, D, nsrc, level, s);
+        ntt_forward(c, D, nsrc * dn, qp, s);
+        ks_inner(c, D, ns, kr, nsrc * ns, level, U2, s);
+        ntt_inverse(c, U2, 2 * nsrc * ns, qp, s);
+      });
+      const float r2 = time_ms(s, 3, [&] { ks_split(c, src, (size_t)level * c.n, nsrc, level, kr, nsrc * ns, ns, D, U2, s); });
+      std::snprintf(line, sizeof line, "hoisted rotations (%d sources x %d keys): four kernels %.3f ms, two kernels %.3f ms\n",
+                    nsrc, ns, r0, r2);
+      report += line;
+      const int d = c.ks_mode_rot;
+      const float td = d == 2 ? r2 : r0, tb = std::min(r0, r2);
+      c.ks_mode_rot = tb < kMargin * td ? (r2 < r0 ? 2 : 0) : d;
+    }
   }
-  report += "key switch chosen mode=" + std::to_string(c.ks_mode) + "\n";
+  report += "key switch chosen mode=" + std::to_string(c.ks_mode) + " rotations=" + std::to_string(c.ks_mode_rot) + "\n";
   return report;
 }
 
