@@ -270,6 +270,10 @@ void automorphism_coeff(const Context& c, const double* in, double* out, int n, 
 void lift_plain(const Context& c, const double* m, double* out, int n, int level, hipStream_t s);
 // slot values (int64, any representative) -> transform-domain vector mod t at the slot positions
 void slots_to_tdomain(const Context& c, const int64_t* slots, double* out, int n, hipStream_t s);
+// slot-batched FP32 features [requests][batch][stride_b] -> quantised plaintexts in the
+// transform domain of R_t [n_pt][N] (n_pt = requests * stride_b)
+void features_to_tdomain(const Context& c, const float* f, int n_pt, int batch, int stride_b, float scale, int clampv,
+                         double* out, hipStream_t s);
 void tdomain_to_slots(const Context& c, const double* in, int64_t* slots, int n, hipStream_t s);
 // decryption rounding: x [n][level][N] (coeff) -> m [n][N] = round(t x / Q) mod t
 void dec_round(const Context& c, const double* x, double* m, int n, int level, hipStream_t s);

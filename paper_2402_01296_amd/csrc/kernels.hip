@@ -534,6 +534,28 @@ __global__ void k_quantise(const float* __restrict__ f, int n_pt, int mode, int 
   }
 }
 
+// Slot-batched features straight to the transform domain of R_t: plaintext p =
+// r * stride_b + j (request r, feature j) takes, at slot b < batch, the quantised
+// feature f[r][b][j] (zero at the other slots), reduced mod t and written at the
+// transform position of slot b.  Every position is written, so no clearing pass.
+__global__ void k_features_to_t(const float* __restrict__ f, int n_pt, int batch, int stride_b, float scale,
+                                int clampv, long long t, double* __restrict__ out, int logn,
+                                const uint32_t* __restrict__ pos) {
+  const size_t N = (size_t)1 << logn;
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx >= (size_t)n_pt * N) return;
+  const size_t p = idx >> logn, b = idx & (N - 1);
+  long long v = 0;
+  if (b < (size_t)batch) {
+    const size_t r = p / stride_b, j = p % stride_b;
+    float q = rintf(scale * f[(r * batch + b) * (size_t)stride_b + j]);
+    q = fminf(fmaxf(q, (float)-clampv), (float)clampv);
+    v = (long long)q % t;
+    if (v < 0) v += t;
+  }
+  out[p * N + pos[b]] = (double)v;
+}
+
 #define BCN_DISPATCH_NS(ns, MACRO)                                                                  \
   switch (ns) {                                                                                     \
     case 1: MACRO(1); break; case 2: MACRO(2); break; case 3: MACRO(3); break; case 4: MACRO(4); break; \
@@ -755,6 +777,14 @@ void slots_to_tdomain(const Context& c, const int64_t* slots, double* out, int n
   if (n == 0) return;
   hipLaunchKernelGGL(k_slots_to_t, dim3(nblocks((size_t)n * c.n)), dim3(TPB), 0, s, slots, out, n, c.logn,
                      (long long)c.t, c.d_slot_pos);
+  BCN_HIP(hipGetLastError());
+}
+
+void features_to_tdomain(const Context& c, const float* f, int n_pt, int batch, int stride_b, float scale, int clampv,
+                         double* out, hipStream_t s) {
+  if (n_pt == 0) return;
+  hipLaunchKernelGGL(k_features_to_t, dim3(nblocks((size_t)n_pt * c.n)), dim3(TPB), 0, s, f, n_pt, batch, stride_b,
+                     scale, clampv, (long long)c.t, out, c.logn, c.d_slot_pos);
   BCN_HIP(hipGetLastError());
 }
 

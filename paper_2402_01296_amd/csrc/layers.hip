@@ -194,14 +194,20 @@ void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, doub
     ntt_inverse(c, A, 2 * nout, c.basis_Q(level), s);
   }
   if (L.features) {
-    int64_t* sl = reinterpret_cast<int64_t*>(ar.take((size_t)nout * N));
-    fill(reinterpret_cast<double*>(sl), (size_t)nout * N, 0.0, s);   // all-zero bits = int64 zeros
-    if (L.packing == BCN_PACK_BATCH)
-      quantise_features(c, features, nout, 0, L.batch, L.stride_b, nullptr, 0, L.fscale, L.fclamp, sl, s);
-    else
-      quantise_features(c, features, nout, 1, 0, 0, L.slot_of, L.per, L.fscale, L.fclamp, sl, s);
     double* m = ar.take((size_t)nout * N);
-    encode_device(c, sl, m, nout, s);
+    if (L.packing == BCN_PACK_BATCH) {
+      // quantise straight into the transform domain of R_t, then m = encode(slots)
+      features_to_tdomain(c, features, nout, L.batch, L.stride_b, L.fscale, L.fclamp, m, s);
+      Basis bt{};
+      bt.n = 1;
+      bt.id[0] = c.id_t;
+      ntt_inverse(c, m, nout, bt, s);
+    } else {
+      int64_t* sl = reinterpret_cast<int64_t*>(ar.take((size_t)nout * N));
+      fill(reinterpret_cast<double*>(sl), (size_t)nout * N, 0.0, s);   // all-zero bits = int64 zeros
+      quantise_features(c, features, nout, 1, 0, 0, L.slot_of, L.per, L.fscale, L.fclamp, sl, s);
+      encode_device(c, sl, m, nout, s);
+    }
     add_delta(c, A, nout, level, m, s);
   }
   if (direct) return;

@@ -633,9 +633,11 @@ k_ks_intt(const double* __restrict__ D, int d_div, KeySel ka, int level, int dnu
   constexpr int C0 = Sched<LOGN, LOGE, true>::c(0);
   constexpr int SZ0 = 1 << C0, G0 = E >> C0;
   extern __shared__ double lds[];
-  const int nb = qp.n;
+  const int nb = qp.n, nout = gridDim.x / nb;
+  // limb-major: the blocks of one XCD share one or two target limbs, so that limb's key
+  // parts (2 dnum limbs, read by every output) stay in that XCD's L2
   const int w = xcd_order(blockIdx.x, gridDim.x);
-  const int limb = w % nb, o = w / nb;
+  const int limb = w / nout, o = w - limb * nout;
   const int pid = qp.id[limb];
   const Mod m = tb.mods[pid];
   const int sel = o % ka.nk;

@@ -62,3 +62,21 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
     # the binding wraps every declared entry point, with nothing undeclared
     assert sorted(bcn.exported_symbols()) == declared
+
+
+def test_library_has_no_unresolved_internal_symbols():
+    """Every bcn:: function the library calls is defined in it (an internal function left
+    in an anonymous namespace of another source file would only fail when loaded)."""
+    import shutil
+    import subprocess
+    from paper_2402_01296_amd import bcn
+    if not os.path.exists(bcn.LIB_PATH):
+        from paper_2402_01296_amd import build
+        build.build()
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm not available")
+    out = subprocess.run([nm, "-D", "-C", "--undefined-only", bcn.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    unresolved = [ln for ln in out.splitlines() if "bcn::" in ln]
+    assert not unresolved, unresolved
