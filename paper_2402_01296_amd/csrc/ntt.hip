@@ -647,24 +647,47 @@ k_ks_intt(const double* __restrict__ D, int d_div, KeySel ka, int level, int dnu
   const int klimb = limb < level ? limb : L + (limb - level);
   const int KL = nb - level + L;                   // limbs of a key part (L + K)
   const int tid = threadIdx.x;
+  // The inverse transform's first pass holds transform indices (g * T + tid) * SZ0 + jj.
+  // Elements are gathered in chunks of CH: all loads of a chunk (CH digit words and 2 CH
+  // key words per digit) are issued before any is consumed, so a chunk costs one memory
+  // round trip per digit instead of one per element and digit.
+  constexpr int CH = 4;
   double x[E], acc1[E];
 #pragma unroll
-  for (int g = 0; g < G0; ++g)
+  for (int c0 = 0; c0 < E; c0 += CH) {
+    int pos[CH], srcw[CH];
 #pragma unroll
-    for (int jj = 0; jj < SZ0; ++jj) {
-      // the inverse transform's first pass holds indices sid * SZ0 + jj, sid = g * T + tid
-      const int gi = (g * T + tid) * SZ0 + jj;
-      const int p = ntt_store(gi, LOGN);
-      const int ps = gal == 1 ? p : ntt_store(ntt_perm(gi, gal, LOGN), LOGN);
-      double a0 = 0.0, a1 = 0.0;
-      for (int j = 0; j < dnum; ++j) {
-        const double dj = dd[(size_t)j * nb * N + ps];
-        a0 += mul_lazy(dj, key[((size_t)(j * 2) * KL + klimb) * N + p], m);
-        a1 += mul_lazy(dj, key[((size_t)(j * 2 + 1) * KL + klimb) * N + p], m);
-      }
-      x[g * SZ0 + jj] = reduce(a0, m);
-      acc1[g * SZ0 + jj] = reduce(a1, m);
+    for (int e = 0; e < CH; ++e) {
+      const int gi = ((c0 + e) / SZ0 * T + tid) * SZ0 + (c0 + e) % SZ0;
+      pos[e] = ntt_store(gi, LOGN);
+      srcw[e] = gal == 1 ? pos[e] : ntt_store(ntt_perm(gi, gal, LOGN), LOGN);
     }
+    double a0[CH], a1[CH];
+#pragma unroll
+    for (int e = 0; e < CH; ++e) a0[e] = a1[e] = 0.0;
+    for (int j = 0; j < dnum; ++j) {
+      const double* dj = dd + (size_t)j * nb * N;
+      const double* k0 = key + ((size_t)(j * 2) * KL + klimb) * N;
+      const double* k1 = key + ((size_t)(j * 2 + 1) * KL + klimb) * N;
+      double dv[CH], kv0[CH], kv1[CH];
+#pragma unroll
+      for (int e = 0; e < CH; ++e) {
+        dv[e] = dj[srcw[e]];
+        kv0[e] = k0[pos[e]];
+        kv1[e] = k1[pos[e]];
+      }
+#pragma unroll
+      for (int e = 0; e < CH; ++e) {
+        a0[e] += mul_lazy(dv[e], kv0[e], m);
+        a1[e] += mul_lazy(dv[e], kv1[e], m);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < CH; ++e) {
+      x[c0 + e] = reduce(a0[e], m);
+      acc1[c0 + e] = reduce(a1[e], m);
+    }
+  }
   const double* iw = tb.inv + (size_t)pid * N;
   const double* post = tb.post + (size_t)pid * N;
   run_pass<LOGN, LOGE, true, 0, true, false>(x, lds, nullptr, u + ((size_t)(o * 2) * nb + limb) * N, iw, post, m,
