@@ -249,7 +249,8 @@ void ks_inner(const Context& c, const double* D, int d_div, const KeySel& ks, in
 void ks_split(const Context& c, const double* src, size_t src_stride, int n_src, int level, const KeySel& ks,
               int n_out, int d_div, double* D, double* u, hipStream_t s);
 // exact round(u/P) of u [n][2][level+K][N] (coeff) -> [n][2][level][N], plus an addend:
-// add_mode 0: none; 1: add [n][2][level][N]; 2: add sigma_k(add) to part 0 only (add [n][2][level][N]).
+// add_mode 0: none; 1: add [n][2][level][N]; 2: add sigma_k(add) to part 0 only (add [n][2][level][N]);
+// 3: add add itself and sigma_k of its part 0 (rotate-and-add; out must not alias add).
 // With modswitch the result is further rounded by q_level to level-1 limbs.
 // The addend of output o is add + (o / add_div) * add_stride; mode 2 gathers it through the
 // inverse Galois element kinv[o].

@@ -337,6 +337,15 @@ k_moddown(const double* __restrict__ u, int n, int logn, const double* __restric
     } else if (add_mode == 2 && part == 0) {
       const int kinv = ks.kinv ? ks.kinv[ci % ks.nk] : ks.kinv1;
       r = add_mod(r, auto_gather(add + (ci / add_div) * add_stride + (size_t)d * N, k, kinv, logn, md), md);
+    } else if (add_mode == 3) {
+      // rotate-and-add: the result is add + Rot(add) (add itself, plus sigma_k of its part 0)
+      const double* ab = add + (ci / add_div) * add_stride;
+      double a = ab[(size_t)(part * NQ + d) * N + k];
+      if (part == 0) {
+        const int kinv = ks.kinv ? ks.kinv[ci % ks.nk] : ks.kinv1;
+        a = add_mod(a, auto_gather(ab + (size_t)d * N, k, kinv, logn, md), md);
+      }
+      r = add_mod(r, a, md);
     }
     res[d] = r;
   }

@@ -304,24 +304,29 @@ void rotate_sum(Context& c, const EvalKeys& ek, double* ct, int n, int level, in
   double* D = ar.take((size_t)n * dn * nbp * N);
   double* U = ar.take((size_t)n * 2 * nbp * N);
   double* R = ar.take((size_t)n * 2 * level * N);
+  // S <- S + Rot(S, r) for r = span/2 .. 1; the sum is formed inside ModDown (add mode 3),
+  // alternating between ct and R as source and destination
+  double* cur = ct;
+  double* nxt = R;
   for (int r = span / 2; r >= 1; r /= 2) {
     KeySel ks;
     ks.key1 = ek.rot_key(r);
     ks.galois1 = galois_element(c, r);
     ks.kinv1 = galois_inverse(c, ks.galois1);
     if (c.ks_mode == 1) {
-      ks_fused(c, ct + level * N, (size_t)2 * level * N, n, level, ks.key1, ks.galois1, U, s);
-    } else if (c.ks_mode == 2) {
-      ks_split(c, ct + level * N, (size_t)2 * level * N, n, level, ks, n, 1, D, U, s);
+      ks_fused(c, cur + level * N, (size_t)2 * level * N, n, level, ks.key1, ks.galois1, U, s);
+    } else if (c.ks_mode_rot == 2) {
+      ks_split(c, cur + level * N, (size_t)2 * level * N, n, level, ks, n, 1, D, U, s);
     } else {
-      decompose_modup(c, ct + level * N, (size_t)2 * level * N, D, n, level, s);
+      decompose_modup(c, cur + level * N, (size_t)2 * level * N, D, n, level, s);
       ntt_forward(c, D, n * dn, qp, s);
       ks_inner(c, D, 1, ks, n, level, U, s);
       ntt_inverse(c, U, 2 * n, qp, s);
     }
-    moddown(c, U, n, level, ct, 1, (size_t)2 * level * N, 2, ks, false, R, s);
-    add_inplace(c, ct, R, 2 * n, level, s);
+    moddown(c, U, n, level, cur, 1, (size_t)2 * level * N, 3, ks, false, nxt, s);
+    std::swap(cur, nxt);
   }
+  if (cur != ct) copy_rows(cur, 0, ct, 0, (size_t)n * 2 * level * N, 1, s);
 }
 
 MacPlan make_mac_plan(const Context& c, const std::vector<int32_t>& w, int n_out, int n_in,
