@@ -208,6 +208,7 @@ std::string autotune_layer_mac(Context& c, Layer& L, hipStream_t s) {
   int best_tile = L.mac.tile;
   for (int tile : {1, 2, 4, 8, 16, 32, 64}) {
     if (tile / 2 >= L.mac.n_out && tile > 8) break;
+    if (tile < 8 && L.mac.n_out > 64) continue;   // narrow tiles only pay off for narrow layers
     MacPlan p = make_mac_plan(c, L.mac_weights, L.mac.n_out, n_in_mac, L.mac_order, tile);
     float ms = 0;
     try {
