@@ -377,15 +377,15 @@ k_ntt_persist(double* __restrict__ data, int total, Basis basis, Tables tb, int 
 // coefficient form, d0 = a0^2, d1 = 2 a0 a1 and d2 = a1^2 (products in the
 // transform domain).  The forward transform ends in the register layout the
 // inverse transform starts from, so the products and inverse transforms work on
-// registers.  At most two register sets are live: A0 = NTT(a0) and A1 = NTT(a1)
-// give d1 and d0 in place, then a1 is transformed a second time for d2.  That is
-// six transforms instead of five, but it halves the registers a thread needs, so
-// two workgroups share a CU instead of one.
+// registers.  At most two register sets are live (so two workgroups share a CU):
+// A1^2 is parked in d2's own output words (each thread re-reads only what it wrote)
+// while A0^2 and 2 A0 A1 are inverse-transformed, then transformed into d2.
 template <int LOGN, int LOGE>
 __global__ void __launch_bounds__(1 << (LOGN - LOGE)) __attribute__((amdgpu_waves_per_eu(LOGE <= 4 ? 4 : 1)))
 k_square_fused(const double* __restrict__ in, double* __restrict__ out, Basis basis, Tables tb) {
   constexpr int N = 1 << LOGN;
   constexpr int E = 1 << LOGE;
+  constexpr int T = N / E;
   extern __shared__ double lds[];
   const int nb = basis.n, nct = gridDim.x / nb;
   const int w = xcd_order(blockIdx.x, gridDim.x);
@@ -408,19 +408,19 @@ k_square_fused(const double* __restrict__ in, double* __restrict__ out, Basis ba
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const double r0 = reduce(x0[i], m);
-    const double p = mul_mod(r0, reduce(x1[i], m), m);
+    const double r1 = reduce(x1[i], m);
+    d2[i * T + tid] = mul_mod(r1, r1, m);     // parked: lane-consecutive, read back by this thread
+    const double p = mul_mod(r0, r1, m);
     x1[i] = add_mod(p, p, m);
     x0[i] = mul_mod(r0, r0, m);
   }
   run_pass<LOGN, LOGE, true, 0, true, false>(x1, lds, nullptr, d1, iw, post, m, tid);
   run_pass<LOGN, LOGE, true, 0, true, false>(x0, lds, nullptr, d0, iw, post, m, tid);
-  __syncthreads();
-  run_pass<LOGN, LOGE, false, 0, false, true>(x1, lds, a1, nullptr, fw, post, m, tid);
 #pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const double r = reduce(x1[i], m);
-    x1[i] = mul_mod(r, r, m);
-  }
+  for (int i = 0; i < E; ++i) x1[i] = d2[i * T + tid];
+  // the inverse transform's first exchange is a workgroup barrier that every thread reaches
+  // only after consuming its parked words, so its final stores into d2 cannot overtake a
+  // slower thread's reads
   run_pass<LOGN, LOGE, true, 0, true, false>(x1, lds, nullptr, d2, iw, post, m, tid);
 }
 
