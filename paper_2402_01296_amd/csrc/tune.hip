@@ -91,7 +91,8 @@ std::string autotune_ntt(Context& c, hipStream_t s) {
     report += std::string("ntt chosen persistent=") + (c.ntt_persist ? "1" : "0") + "\n";
   }
   // square's transform segment: fused kernel (each transform shape) vs forward + tensor + inverse
-  if (c.logn <= 13) {
+  // (at N = 16384 the fused kernel needs all of a CU's LDS and spills a little; measured anyway)
+  if (c.logn <= 14) {
     const int n = std::max(8, polys / 2);
     double* in = buf;
     double* out = c.arena->take((size_t)n * 3 * b.n * c.n);
