@@ -246,8 +246,10 @@ void ks_inner(const Context& c, const double* D, int d_div, const KeySel& ks, in
 // ([n_src][dnum][level + K][N], transform domain), then for each of n_out outputs the
 // inner product with its key (output o uses source o / d_div) and both inverse
 // transforms into u ([n_out][2][level + K][N], coefficient form).
+// src_galois != 1 switches sigma_k(source) (k = src_galois): the digits are stored through
+// the transform-domain permutation, and ks must then carry none (galois 1).
 void ks_split(const Context& c, const double* src, size_t src_stride, int n_src, int level, const KeySel& ks,
-              int n_out, int d_div, double* D, double* u, hipStream_t s);
+              int n_out, int d_div, double* D, double* u, hipStream_t s, int src_galois = 1);
 // exact round(u/P) of u [n][2][level+K][N] (coeff) -> [n][2][level][N], plus an addend:
 // add_mode 0: none; 1: add [n][2][level][N]; 2: add sigma_k(add) to part 0 only (add [n][2][level][N]);
 // 3: add add itself and sigma_k of its part 0 (rotate-and-add; out must not alias add).

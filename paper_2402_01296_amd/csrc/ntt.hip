@@ -160,7 +160,7 @@ template <int LOGN, int LOGE, bool INV, int P, bool FROM_REGS = false, bool TO_R
 __device__ __forceinline__ void run_pass(double (&x)[1 << LOGE], double* lds, const double* __restrict__ src,
                                          double* __restrict__ a, const double* __restrict__ tw,
                                          const double* __restrict__ post, const Mod m, const int tid_in,
-                                         const double* wpre = nullptr) {
+                                         const double* wpre = nullptr, int store_gal = 1) {
   using S = Shape<LOGN, LOGE>;
   constexpr int N = S::N;
   constexpr int C = Sched<LOGN, LOGE, INV>::c(P);
@@ -263,7 +263,9 @@ __device__ __forceinline__ void run_pass(double (&x)[1 << LOGE], double* lds, co
           const int gi = base[g] + j * SMIN;
           double v = x[g * SZ + j];
           v = INV ? norm(mul_lazy(post[gi], v, m), m) : reduce(v, m);
-          a[INV ? gi : ntt_store(gi, LOGN)] = v;
+          // store_gal != 1 (forward only): write sigma(a)^ instead, where sigma(a)^ at index
+          // i is a^ at ntt_perm(i, k), i.e. the value of index gi goes to ntt_perm(gi, k^-1)
+          a[INV ? gi : ntt_store(store_gal == 1 ? gi : ntt_perm(gi, store_gal, LOGN), LOGN)] = v;
         }
     }
   } else {
@@ -288,7 +290,7 @@ __device__ __forceinline__ void run_pass(double (&x)[1 << LOGE], double* lds, co
     } else {
       __syncthreads();
     }
-    run_pass<LOGN, LOGE, INV, P + 1, FROM_REGS, TO_REGS, PF>(x, lds, src, a, tw, post, m, tid, wn);
+    run_pass<LOGN, LOGE, INV, P + 1, FROM_REGS, TO_REGS, PF>(x, lds, src, a, tw, post, m, tid, wn, store_gal);
   }
 }
 
@@ -567,11 +569,12 @@ void launch_ks(const Context& c, const double* src, size_t stride, int n, int le
 // target limb) forms D_j = lift_c([x]_{Q_j}) mod the target prime while gathering
 // the forward transform's first pass from the source residues, transforms it and
 // stores it in transform-domain order at D[poly][j][limb] (the layout the four-kernel
-// path builds with ModUp and a forward transform).
+// path builds with ModUp and a forward transform).  store_gal = k^-1 != 1 stores the
+// digits of sigma_k(x) (the transform-domain permutation applied on the store).
 template <int LOGN, int LOGE, int NA>
 __global__ void __launch_bounds__(1 << (LOGN - LOGE))
 k_ntt_digits(const double* __restrict__ src, size_t src_stride, int dnum, KsDigits dg, double* __restrict__ D,
-             Basis qp, Tables tb) {
+             Basis qp, Tables tb, int store_gal) {
   using S = Shape<LOGN, LOGE>;
   constexpr int N = S::N, E = S::E, T = S::T;
   constexpr int C0 = S::C0;
@@ -615,7 +618,7 @@ k_ntt_digits(const double* __restrict__ src, size_t src_stride, int dnum, KsDigi
       x[g * SZ0 + jj] = v;
     }
   run_pass<LOGN, LOGE, false, 0, true, false>(x, lds, nullptr, D + ((size_t)pj * nb + limb) * N,
-                                              tb.fwd + (size_t)pid * N, tb.post, m, tid);
+                                              tb.fwd + (size_t)pid * N, tb.post, m, tid, nullptr, store_gal);
 }
 
 // Key-switching inner product fused into the inverse transforms.  Block (output o,
@@ -699,7 +702,7 @@ k_ks_intt(const double* __restrict__ D, int d_div, KeySel ka, int level, int dnu
 template <int LOGN, int LOGE>
 void launch_ks_split(const Context& c, int part, const double* src, size_t stride, int n_src, int level,
                      const KsDigits& dg, double* D, const KeySel& ks, int n_out, int d_div, double* u, const Basis& qp,
-                     hipStream_t s) {
+                     int store_gal, hipStream_t s) {
   constexpr int N = 1 << LOGN;
   const size_t lds = (size_t)N * sizeof(double);
   const int dnum = c.dnum(level);
@@ -707,10 +710,10 @@ void launch_ks_split(const Context& c, int part, const double* src, size_t strid
   if (b1 > 0) {
     if (c.alpha == 1)
       hipLaunchKernelGGL((k_ntt_digits<LOGN, LOGE, 1>), dim3(b1), dim3(N >> LOGE), lds, s, src, stride, dnum, dg, D, qp,
-                         c.tab);
+                         c.tab, store_gal);
     else
       hipLaunchKernelGGL((k_ntt_digits<LOGN, LOGE, 2>), dim3(b1), dim3(N >> LOGE), lds, s, src, stride, dnum, dg, D, qp,
-                         c.tab);
+                         c.tab, store_gal);
     BCN_HIP(hipGetLastError());
   }
   const unsigned b2 = part == 2 ? (unsigned)n_out * qp.n : 0u;
@@ -860,12 +863,13 @@ KsDigits ks_digits(const Context& c, int level, const Basis& qp) {
 }  // namespace
 
 void ks_split(const Context& c, const double* src, size_t src_stride, int n_src, int level, const KeySel& ks,
-              int n_out, int d_div, double* D, double* u, hipStream_t s) {
+              int n_out, int d_div, double* D, double* u, hipStream_t s, int src_galois) {
   const Basis qp = c.basis_QP(level);
   const KsDigits dg = ks_digits(c, level, qp);
   const int dnum = c.dnum(level);
   const double tr = 8.0 * (c.n / 2) * c.logn + 4.0 * c.n;        // FP64 ops of one limb transform
   const int key = c.logn * 16 + c.ntt_loge;
+  const int store_gal = src_galois == 1 ? 1 : (int)host::inv_pow2((uint64_t)src_galois, c.logn + 1);
   for (int part = 1; part <= 2; ++part) {
     // digits: source limbs once, digits out, dnum * (level + K) forward transforms per source;
     // inner product: digits and two key parts in, two parts out, two inverse transforms per output limb
@@ -876,7 +880,7 @@ void ks_split(const Context& c, const double* src, size_t src_stride, int n_src,
     switch (key) {
 #define BCN_KSS_CASE(LN, LE)                                                                                 \
   case LN * 16 + LE:                                                                                         \
-    launch_ks_split<LN, LE>(c, part, src, src_stride, n_src, level, dg, D, ks, n_out, d_div, u, qp, s); break;
+    launch_ks_split<LN, LE>(c, part, src, src_stride, n_src, level, dg, D, ks, n_out, d_div, u, qp, store_gal, s); break;
       BCN_KSS_CASE(10, 3) BCN_KSS_CASE(10, 4)
       BCN_KSS_CASE(11, 3) BCN_KSS_CASE(11, 4)
       BCN_KSS_CASE(12, 4) BCN_KSS_CASE(12, 5)

@@ -316,7 +316,11 @@ void rotate_sum(Context& c, const EvalKeys& ek, double* ct, int n, int level, in
     if (c.ks_mode == 1) {
       ks_fused(c, cur + level * N, (size_t)2 * level * N, n, level, ks.key1, ks.galois1, U, s);
     } else if (c.ks_mode_rot == 2) {
-      ks_split(c, cur + level * N, (size_t)2 * level * N, n, level, ks, n, 1, D, U, s);
+      // one Galois element per call: permute the digits as they are stored (scattered
+      // stores) instead of on the inner product's digit reads (scattered loads)
+      KeySel kd = ks;
+      kd.galois1 = 1;
+      ks_split(c, cur + level * N, (size_t)2 * level * N, n, level, kd, n, 1, D, U, s, ks.galois1);
     } else {
       decompose_modup(c, cur + level * N, (size_t)2 * level * N, D, n, level, s);
       ntt_forward(c, D, n * dn, qp, s);
