@@ -289,6 +289,11 @@ Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uin
     if (v == 0 || (v == 1 && can_fuse_ks) || (v == 2 && alpha <= 2)) c->ks_mode = v, c->pinned_ks = true;
   }
   c->ks_mode_rot = c->ks_mode == 2 ? 2 : 0;
+  if (const char* env = std::getenv("BCN_KS_LOGE")) {
+    const int v = std::atoi(env);
+    for (int o : c->ntt_loge_options())
+      if (o == v) c->ks_loge = v, c->pinned_ks = true;
+  }
   if (const char* env = std::getenv("BCN_NTT_PERSIST")) c->ntt_persist = std::atoi(env) != 0;
   if (const char* env = std::getenv("BCN_NTT_PREFETCH")) c->ntt_prefetch = std::atoi(env) != 0, c->pinned_prefetch = true;
   {

@@ -132,6 +132,7 @@ struct Context {
   int ks_mode = 2;                       // key switching: 0 ModUp + NTT + inner product + INTT (four kernels),
                                          // 1 one fused kernel, 2 digits+NTT and inner product+INTT (two kernels)
   int ks_mode_rot = 2;                   // the same for hoisted rotations (0 or 2)
+  int ks_loge = 4;                       // transform shape of the two-kernel key switch
   bool pinned_ks = false;
   std::vector<int> ntt_loge_options() const;
 
@@ -207,7 +208,7 @@ struct MacPlan {
 };
 // requests > 1: independent requests at in + r*in_req, out + r*out_req (doubles)
 void mac(const Context& c, const MacPlan& p, const double* in, double* out, int level, hipStream_t s, int requests = 1,
-         size_t in_req = 0, size_t out_req = 0);
+         size_t in_req = 0, size_t out_req = 0, const double* delta_msg = nullptr);
 
 // c0 of each ciphertext += Delta(m_i), m_i in [0, t) coefficient form, [n][N]
 void add_delta(const Context& c, double* ct, int n, int level, const double* m, hipStream_t s);

@@ -20,12 +20,23 @@ inline unsigned nblocks(size_t work) { return (unsigned)((work + TPB - 1) / TPB)
 // uniform weights of one column arrive as a few wide scalar loads.  Inputs are
 // centred (|x| <= (q-1)/2) so every partial sum is an exact FP64 integer;
 // `chunk` bounds the inputs between two partial reductions.
+// Optional plaintext add folded into the MAC's stores (the unidirectional feature
+// connection): part 0 of output row r gains round(Q_level m_r / t) for the encoded
+// plaintext m_r (msg[r][N], values mod t), exactly as the separate Add(c, u) kernel.
+struct DeltaAdd {
+  const double* msg = nullptr;  // [requests][rows][N]; null: no add
+  size_t msg_req = 0;           // words between requests
+  double qmodt = 0.0;           // Q_level mod t
+  Mod mt{};                     // t
+  double negtinv[kMaxBasis];    // -t^-1 mod q_i
+};
+
 template <int TO>
 __global__ void __launch_bounds__(TPB)
 k_mac(const double* __restrict__ in, double* __restrict__ out, int words, int logn, int level,
       const double* __restrict__ Wp, const int* __restrict__ rows, const int* __restrict__ tptr,
       const int* __restrict__ tcols, int chunk, Basis b, const Mod* __restrict__ mods, size_t in_req,
-      size_t out_req) {
+      size_t out_req, DeltaAdd da) {
   const int w = blockIdx.x * TPB + threadIdx.x;
   if (w >= words) return;
   in += blockIdx.z * in_req;     // request blockIdx.z of a batch of independent requests
@@ -71,10 +82,22 @@ k_mac(const double* __restrict__ in, double* __restrict__ out, int words, int lo
     for (int o = 0; o < TO; ++o) acc[o] = fma(wr[o], x, acc[o]);
     ++cnt;
   }
+  const bool add = da.msg != nullptr && w < (words >> 1);            // part 0 words
+  const int limb = (w >> logn) % level;
+  const size_t k = (size_t)w & (((size_t)1 << logn) - 1);
 #pragma unroll
   for (int o = 0; o < TO; ++o) {
     const int row = rows[tile * TO + o];
-    if (row >= 0) out[(size_t)row * words + w] = reduce(acc[o], m);
+    if (row < 0) continue;
+    double r = reduce(acc[o], m);
+    if (add) {
+      const double mv = da.msg[blockIdx.z * da.msg_req + ((size_t)row << logn) + k];
+      const double rt = mul_mod(da.qmodt, mv, da.mt);                 // [Q m]_t
+      double d = norm(mul_lazy(rt, da.negtinv[limb], m), m);         // floor(Q m / t) mod q
+      if (2.0 * rt > da.mt.q) d = add_mod(d, 1.0, m);                 // nearest, never a tie (t odd)
+      r = add_mod(r, d, m);
+    }
+    out[(size_t)row * words + w] = r;
   }
 }
 
@@ -579,10 +602,30 @@ __global__ void k_features_to_t(const float* __restrict__ f, int n_pt, int batch
 
 // ------------------------------------------------------------------ host wrappers
 
+namespace {
+// Q_level mod t and -t^-1 mod q_i: the constants of round(Q_level m / t) mod q_i
+void delta_consts(const Context& c, int level, double* qmodt_out, double* neg) {
+  uint64_t qmodt = 1;
+  for (int i = 0; i < level; ++i) {
+    qmodt = host::mulmod(qmodt, c.primes[i] % c.t, c.t);
+    const uint64_t q = c.primes[i];
+    neg[i] = (double)((q - host::invmod(c.t % q, q)) % q);
+  }
+  *qmodt_out = (double)qmodt;
+}
+}  // namespace
+
 void mac(const Context& c, const MacPlan& p, const double* in, double* out, int level, hipStream_t s, int requests,
-         size_t in_req, size_t out_req) {
+         size_t in_req, size_t out_req, const double* delta_msg) {
   const int words = 2 * level * c.n;
   if (p.n_out == 0 || requests == 0) return;
+  DeltaAdd da;
+  if (delta_msg) {
+    da.msg = delta_msg;
+    da.msg_req = (size_t)p.n_out * c.n;
+    da.mt = c.mod(c.id_t);
+    delta_consts(c, level, &da.qmodt, da.negtinv);
+  }
   // algorithmic work: one FMA per word for each nonzero (output, input) weight
   ProfScope ps(c, "mac", s, 8.0 * words * ((double)p.n_in + p.n_out) * requests, (double)words * p.nnz * requests);
   dim3 grid(nblocks(words), p.n_tiles, requests);
@@ -590,7 +633,7 @@ void mac(const Context& c, const MacPlan& p, const double* in, double* out, int 
   switch (p.tile) {
 #define BCN_MAC_CASE(TO) \
   case TO: hipLaunchKernelGGL(k_mac<TO>, grid, dim3(TPB), 0, s, in, out, words, c.logn, level, p.W, p.rows, \
-                              p.tile_ptr, p.tile_cols, p.chunk, b, c.tab.mods, in_req, out_req); break;
+                              p.tile_ptr, p.tile_cols, p.chunk, b, c.tab.mods, in_req, out_req, da); break;
     BCN_MAC_CASE(1) BCN_MAC_CASE(2) BCN_MAC_CASE(4) BCN_MAC_CASE(8) BCN_MAC_CASE(16) BCN_MAC_CASE(32)
     BCN_MAC_CASE(64)
 #undef BCN_MAC_CASE
@@ -602,16 +645,11 @@ void mac(const Context& c, const MacPlan& p, const double* in, double* out, int 
 void add_delta(const Context& c, double* ct, int n, int level, const double* m, hipStream_t s) {
   if (n == 0) return;
   const Mod mt = c.mod(c.id_t);
-  // Q_level mod t and -t^-1 mod q_i
-  uint64_t qmodt = 1;
+  double qmodt = 0.0;
   LimbConsts neg{};
-  for (int i = 0; i < level; ++i) {
-    qmodt = host::mulmod(qmodt, c.primes[i] % c.t, c.t);
-    const uint64_t q = c.primes[i];
-    neg.v[i] = (double)((q - host::invmod(c.t % q, q)) % q);
-  }
+  delta_consts(c, level, &qmodt, neg.v);
   hipLaunchKernelGGL(k_add_delta, dim3(nblocks((size_t)n * level * c.n)), dim3(TPB), 0, s, ct, n, level, c.logn, m,
-                     (double)qmodt, mt, c.basis_Q(level), c.tab.mods, neg);
+                     qmodt, mt, c.basis_Q(level), c.tab.mods, neg);
   BCN_HIP(hipGetLastError());
 }
 

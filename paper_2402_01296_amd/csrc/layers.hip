@@ -176,7 +176,18 @@ void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, doub
   const bool direct = !L.square && !L.features && L.span == 0 && L.packing == BCN_PACK_BATCH;
   double* A = direct ? out : ar.take((size_t)nout * ctw);
   if (L.packing == BCN_PACK_BATCH) {
-    mac(c, L.mac, in, A, level, s, R, (size_t)L.n_in * ctw, (size_t)L.n_out * ctw);
+    // slot batching: the features are quantised straight into the transform domain of R_t,
+    // encoded (inverse transform mod t) and added by the MAC's own stores
+    double* fm = nullptr;
+    if (L.features) {
+      fm = ar.take((size_t)nout * N);
+      features_to_tdomain(c, features, nout, L.batch, L.stride_b, L.fscale, L.fclamp, fm, s);
+      Basis bt{};
+      bt.n = 1;
+      bt.id[0] = c.id_t;
+      ntt_inverse(c, fm, nout, bt, s);
+    }
+    mac(c, L.mac, in, A, level, s, R, (size_t)L.n_in * ctw, (size_t)L.n_out * ctw, fm);
   } else if (L.kind == BCN_CONV2D) {
     // taps [R*n_in][k2]: tap 0 = the input, taps 1.. = hoisted rotations
     double* taps = ar.take((size_t)nin * L.k2 * ctw);
@@ -193,21 +204,13 @@ void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, doub
     ptvec_mac_ntt(c, H, L.n_in, A, L.n_out, level, L.ptv_hat, s, R);
     ntt_inverse(c, A, 2 * nout, c.basis_Q(level), s);
   }
-  if (L.features) {
+  if (L.features && L.packing != BCN_PACK_BATCH) {
+    // HW packing: features enter after the conv's mask
     double* m = ar.take((size_t)nout * N);
-    if (L.packing == BCN_PACK_BATCH) {
-      // quantise straight into the transform domain of R_t, then m = encode(slots)
-      features_to_tdomain(c, features, nout, L.batch, L.stride_b, L.fscale, L.fclamp, m, s);
-      Basis bt{};
-      bt.n = 1;
-      bt.id[0] = c.id_t;
-      ntt_inverse(c, m, nout, bt, s);
-    } else {
-      int64_t* sl = reinterpret_cast<int64_t*>(ar.take((size_t)nout * N));
-      fill(reinterpret_cast<double*>(sl), (size_t)nout * N, 0.0, s);   // all-zero bits = int64 zeros
-      quantise_features(c, features, nout, 1, 0, 0, L.slot_of, L.per, L.fscale, L.fclamp, sl, s);
-      encode_device(c, sl, m, nout, s);
-    }
+    int64_t* sl = reinterpret_cast<int64_t*>(ar.take((size_t)nout * N));
+    fill(reinterpret_cast<double*>(sl), (size_t)nout * N, 0.0, s);   // all-zero bits = int64 zeros
+    quantise_features(c, features, nout, 1, 0, 0, L.slot_of, L.per, L.fscale, L.fclamp, sl, s);
+    encode_device(c, sl, m, nout, s);
     add_delta(c, A, nout, level, m, s);
   }
   if (direct) return;

@@ -383,7 +383,7 @@ k_ntt_persist(double* __restrict__ data, int total, Basis basis, Tables tb, int 
 // A1^2 is parked in d2's own output words (each thread re-reads only what it wrote)
 // while A0^2 and 2 A0 A1 are inverse-transformed, then transformed into d2.
 template <int LOGN, int LOGE>
-__global__ void __launch_bounds__(1 << (LOGN - LOGE)) __attribute__((amdgpu_waves_per_eu(LOGE <= 4 ? 4 : 1)))
+__global__ void __launch_bounds__(1 << (LOGN - LOGE)) __attribute__((amdgpu_waves_per_eu(LOGE <= 4 ? 4 : 2)))
 k_square_fused(const double* __restrict__ in, double* __restrict__ out, Basis basis, Tables tb) {
   constexpr int N = 1 << LOGN;
   constexpr int E = 1 << LOGE;
@@ -868,7 +868,7 @@ void ks_split(const Context& c, const double* src, size_t src_stride, int n_src,
   const KsDigits dg = ks_digits(c, level, qp);
   const int dnum = c.dnum(level);
   const double tr = 8.0 * (c.n / 2) * c.logn + 4.0 * c.n;        // FP64 ops of one limb transform
-  const int key = c.logn * 16 + c.ntt_loge;
+  const int key = c.logn * 16 + c.ks_loge;
   const int store_gal = src_galois == 1 ? 1 : (int)host::inv_pow2((uint64_t)src_galois, c.logn + 1);
   for (int part = 1; part <= 2; ++part) {
     // digits: source limbs once, digits out, dnum * (level + K) forward transforms per source;

@@ -159,7 +159,21 @@ std::string autotune_ntt(Context& c, hipStream_t s) {
     });
     if (c.logn <= 13 && c.alpha <= 2)
       t[1] = time_ms(s, 5, [&] { ks_fused(c, src, (size_t)level * c.n, n, level, key, 1, U, s); });
-    if (c.alpha <= 2) t[2] = time_ms(s, 5, [&] { ks_split(c, src, (size_t)level * c.n, n, level, ks, n, 1, D, U, s); });
+    if (c.alpha <= 2) {
+      // the two-kernel path's own transform shape (its kernels hold more registers than a
+      // plain transform, so the best shape can differ)
+      const int dflt_loge = c.ks_loge;
+      float best_l = 1e30f, dflt_l = 1e30f;
+      int best_loge = dflt_loge;
+      for (int loge : c.ntt_loge_options()) {
+        c.ks_loge = loge;
+        const float ms = time_ms(s, 5, [&] { ks_split(c, src, (size_t)level * c.n, n, level, ks, n, 1, D, U, s); });
+        if (loge == dflt_loge) dflt_l = ms;
+        if (ms < best_l) best_l = ms, best_loge = loge;
+      }
+      c.ks_loge = best_l < kMargin * dflt_l ? best_loge : dflt_loge;
+      t[2] = c.ks_loge == best_loge ? best_l : dflt_l;
+    }
     char line[200];
     std::snprintf(line, sizeof line,
                   "key switch (%d polynomials, %d digits): four kernels %.3f ms, fused %.3f ms, two kernels %.3f ms\n", n,
@@ -193,7 +207,8 @@ std::string autotune_ntt(Context& c, hipStream_t s) {
       c.ks_mode_rot = tb < kMargin * td ? (r2 < r0 ? 2 : 0) : d;
     }
   }
-  report += "key switch chosen mode=" + std::to_string(c.ks_mode) + " rotations=" + std::to_string(c.ks_mode_rot) + "\n";
+  report += "key switch chosen mode=" + std::to_string(c.ks_mode) + " rotations=" + std::to_string(c.ks_mode_rot) +
+            " loge=" + std::to_string(c.ks_loge) + "\n";
   return report;
 }
 

@@ -362,3 +362,35 @@ def test_rotation_hoisted_paths_agree(pname, ks_mode, monkeypatch):
         for si, r in enumerate(steps):
             ref = bfv.rotate(prm, c, r, gk[r])
             assert (got[i * len(steps) + si] == bfv.ct_to_rns(prm, ref)).all(), "ct %d step %d" % (i, r)
+
+
+@pytest.mark.parametrize("pname,loge", [("t1k", "3"), ("t1k", "4"), ("t2k", "3"), ("t2k", "4"), ("cfg2", "5")])
+def test_two_kernel_key_switch_shapes_agree(pname, loge, monkeypatch):
+    """The two-kernel key switch at every transform shape the autotuner may pick for it:
+    relinearisation (square) and hoisted rotations against the oracle."""
+    torch_cuda()
+    from paper_2402_01296_amd import bcn
+    monkeypatch.setenv("BCN_KS_MODE", "2")
+    monkeypatch.setenv("BCN_KS_LOGE", loge)
+    prm, ctx = context(pname)
+    s = synthetic.ternary_secret(37, prm.n)
+    sk = ctx.secret_key(s)
+    ek = ctx.eval_keys()
+    a, e = key_randomness(prm, 37, 0)
+    ctx.keygen(sk, ek, bcn.BCN_KEY_RELIN, 0, np.stack(a), np.stack(e))
+    rk = bfv.relin_key(prm, [int(v) for v in s], a, e)
+    res = random_ct_residues(prm, prm.L, 2, 97)
+    got = ctx.export(ctx.square_relin(ek, ctx.import_(res), modswitch=False))
+    for i in range(2):
+        assert (got[i] == bfv.ct_to_rns(prm, bfv.square(prm, oracle_ct(prm, res[i]), rk))).all()
+    steps = [1, 7]
+    gk = {}
+    for r in steps:
+        a, e = key_randomness(prm, 37, 1000 + r)
+        ctx.keygen(sk, ek, bcn.BCN_KEY_ROTATION, r, np.stack(a), np.stack(e))
+        gk[r] = bfv.galois_key(prm, [int(v) for v in s], r, a, e)
+    got = ctx.export(ctx.rotate(ek, ctx.import_(res), steps).reshape(-1, 2, prm.L, prm.n))
+    for i in range(2):
+        c = oracle_ct(prm, res[i])
+        for si, r in enumerate(steps):
+            assert (got[i * len(steps) + si] == bfv.ct_to_rns(prm, bfv.rotate(prm, c, r, gk[r]))).all()
