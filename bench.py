@@ -324,8 +324,7 @@ def main():
     g = GpuSession(args.workload)
     tuning = None if args.no_autotune else g.autotune()
     for ln in (tuning or "").splitlines():
-        if "chosen" in ln:
-            print("bench: autotune %s" % ln, file=sys.stderr, flush=True)
+        print("bench: autotune %s" % ln, file=sys.stderr, flush=True)
     ct_in = g.encrypt_inputs()
     torch.cuda.synchronize()
     print("bench: %s keys+encryption ready, %d input ciphertexts" % (args.workload, ct_in.shape[0]),

@@ -260,6 +260,12 @@ Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uin
   }
   BCN_HIP(hipMalloc(&c->d_slot_pos, N * sizeof(uint32_t)));
   BCN_HIP(hipMemcpy(c->d_slot_pos, pos.data(), N * sizeof(uint32_t), hipMemcpyHostToDevice));
+  std::vector<uint32_t> slot_of(N, 0xffffffffu);
+  for (size_t i = 0; i < N; ++i) slot_of[pos[i]] = (uint32_t)i;
+  for (size_t i = 0; i < N; ++i)
+    if (slot_of[i] == 0xffffffffu) throw Error(-1, "slot map is not a permutation");
+  BCN_HIP(hipMalloc(&c->d_slot_of_word, N * sizeof(uint32_t)));
+  BCN_HIP(hipMemcpy(c->d_slot_of_word, slot_of.data(), N * sizeof(uint32_t), hipMemcpyHostToDevice));
   c->arena = std::make_unique<Arena>();
   // default transform shape (bcn_autotune may replace it by a measured choice)
   c->ntt_loge = logn >= 14 ? 5 : 4;
@@ -320,6 +326,7 @@ void destroy_context(Context* c) {
   release_convs(*c);
   if (c->d_tables) (void)hipFree(c->d_tables);
   if (c->d_slot_pos) (void)hipFree(c->d_slot_pos);
+  if (c->d_slot_of_word) (void)hipFree(c->d_slot_of_word);
   delete c;
 }
 

@@ -120,6 +120,7 @@ struct Context {
   double* d_tables = nullptr;            // one allocation for all tables
   Tables tab{};
   uint32_t* d_slot_pos = nullptr;        // [N] position of slot s in the transform of R_t
+  uint32_t* d_slot_of_word = nullptr;    // [N] inverse of d_slot_pos: the slot held at each word
   std::unique_ptr<Arena> arena;
 
   int ntt_loge = 0;                      // registers per thread = 2^ntt_loge in the transform
@@ -205,6 +206,11 @@ struct MacPlan {
   int* tile_cols = nullptr;     // device: columns with a nonzero weight in the tile
   int chunk = 0;                // inputs between two partial reductions
   long nnz = 0;                 // nonzero weights
+  // matrix-core variant (mfma_mtw > 0): int8 weights in the MFMA operand layout; workgroups of four
+  // waves, mfma_wm of them along the 16-row output tiles (mfma_mtw tiles each), the rest along the words
+  int mfma_mtw = 0, mfma_wm = 0, mfma_digits = 0, ksteps = 0, mtiles = 0;
+  void* A8 = nullptr;           // device [mtiles][ksteps][64 lanes][16 bytes]
+  double* corr = nullptr;       // device [n_out][L]: 128 * sum_c 256^c * row sum of the weights, mod each q
 };
 // requests > 1: independent requests at in + r*in_req, out + r*out_req (doubles)
 void mac(const Context& c, const MacPlan& p, const double* in, double* out, int level, hipStream_t s, int requests = 1,
