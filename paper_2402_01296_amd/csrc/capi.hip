@@ -263,7 +263,7 @@ int bcn_mac(bcn_context* ctx, const double* in, int n_in, double* out, int n_out
     check_ptr(out, "out");
     check_ptr(w, "w");
     std::vector<int32_t> W(w, w + (size_t)n_in * n_out);
-    bcn::MacPlan p = bcn::make_mac_plan_auto(c, W, n_out, n_in);
+    bcn::MacPlan p = bcn::make_mac_plan(c, W, n_out, n_in);
     try {
       bcn::mac(c, p, in, out, level, (hipStream_t)stream);
       BCN_HIP(hipStreamSynchronize((hipStream_t)stream));

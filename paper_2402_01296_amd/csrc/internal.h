@@ -206,11 +206,7 @@ struct MacPlan {
   int* tile_cols = nullptr;     // device: columns with a nonzero weight in the tile
   int chunk = 0;                // inputs between two partial reductions
   long nnz = 0;                 // nonzero weights
-  // matrix-core variant (mfma_mtw > 0): int8 weights in the MFMA operand layout; workgroups of four
-  // waves, mfma_wm of them along the 16-row output tiles (mfma_mtw tiles each), the rest along the words
-  int mfma_mtw = 0, mfma_wm = 0, mfma_digits = 0, ksteps = 0, mtiles = 0;
-  void* A8 = nullptr;           // device [mtiles][ksteps][64 lanes][16 bytes]
-  double* corr = nullptr;       // device [n_out][L]: 128 * sum_c 256^c * row sum of the weights, mod each q
+  bool centre = true;           // false: every tile's sum of |w| * (q-1) fits 2^53 uncentred
 };
 // requests > 1: independent requests at in + r*in_req, out + r*out_req (doubles)
 void mac(const Context& c, const MacPlan& p, const double* in, double* out, int level, hipStream_t s, int requests = 1,

@@ -17,9 +17,11 @@ inline unsigned nblocks(size_t work) { return (unsigned)((work + TPB - 1) / TPB)
 
 // out[rows[tile*TO + o]] = sum over the tile's column entries e of Wp[e][o] * in[cols[e]].
 // Wp holds, per column entry, the TO weights of the tile contiguously, so the
-// uniform weights of one column arrive as a few wide scalar loads.  Inputs are
-// centred (|x| <= (q-1)/2) so every partial sum is an exact FP64 integer;
-// `chunk` bounds the inputs between two partial reductions.
+// uniform weights of one column arrive as a few wide scalar loads.  Every partial
+// sum is an exact FP64 integer: with CENTRE, inputs are centred (|x| <= (q-1)/2)
+// and `chunk` bounds the inputs between two partial reductions; without it (the
+// plan has checked that a whole tile's sum of |w| * (q-1) stays below 2^53) the
+// residues in [0, q) are accumulated as they are, with no reduction until the end.
 // Optional plaintext add folded into the MAC's stores (the unidirectional feature
 // connection): part 0 of output row r gains round(Q_level m_r / t) for the encoded
 // plaintext m_r (msg[r][N], values mod t), exactly as the separate Add(c, u) kernel.
@@ -31,7 +33,7 @@ struct DeltaAdd {
   double negtinv[kMaxBasis];    // -t^-1 mod q_i
 };
 
-template <int TO>
+template <int TO, bool CENTRE>
 __global__ void __launch_bounds__(TPB)
 k_mac(const double* __restrict__ in, double* __restrict__ out, int words, int logn, int level,
       const double* __restrict__ Wp, const int* __restrict__ rows, const int* __restrict__ tptr,
@@ -52,7 +54,7 @@ k_mac(const double* __restrict__ in, double* __restrict__ out, int words, int lo
   int cnt = 0;
   int e = beg;
   for (; e + 4 <= end; e += 4) {
-    if (cnt > chunk - 4) {
+    if (CENTRE && cnt > chunk - 4) {
 #pragma unroll
       for (int o = 0; o < TO; ++o) acc[o] = reduce_lazy(acc[o], m);
       cnt = 0;
@@ -62,7 +64,7 @@ k_mac(const double* __restrict__ in, double* __restrict__ out, int words, int lo
     for (int u = 0; u < 4; ++u) x[u] = xin[(size_t)tcols[e + u] * words];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const double xv = x[u] > halfq ? x[u] - m.q : x[u];
+      const double xv = CENTRE && x[u] > halfq ? x[u] - m.q : x[u];
       const double* __restrict__ wr = Wp + (size_t)(e + u) * TO;
 #pragma unroll
       for (int o = 0; o < TO; ++o) acc[o] = fma(wr[o], xv, acc[o]);
@@ -70,13 +72,13 @@ k_mac(const double* __restrict__ in, double* __restrict__ out, int words, int lo
     cnt += 4;
   }
   for (; e < end; ++e) {
-    if (cnt >= chunk) {
+    if (CENTRE && cnt >= chunk) {
 #pragma unroll
       for (int o = 0; o < TO; ++o) acc[o] = reduce_lazy(acc[o], m);
       cnt = 0;
     }
     double x = xin[(size_t)tcols[e] * words];
-    x = x > halfq ? x - m.q : x;
+    if (CENTRE) x = x > halfq ? x - m.q : x;
     const double* __restrict__ wr = Wp + (size_t)e * TO;
 #pragma unroll
     for (int o = 0; o < TO; ++o) acc[o] = fma(wr[o], x, acc[o]);
@@ -98,157 +100,6 @@ k_mac(const double* __restrict__ in, double* __restrict__ out, int words, int lo
       r = add_mod(r, d, m);
     }
     out[(size_t)row * words + w] = r;
-  }
-}
-
-// The same product on the int8 matrix cores, for a dense weight matrix (every
-// input feeds every output tile).  Residues x in [0, 2^(8D)) are split into D
-// bytes u_c and offset to signed digits s_c = u_c - 128, so x = sum_c 256^c s_c
-// + 128 S with S = sum_c 256^c.  One v_mfma_i32_16x16x64_i8 multiplies a
-// 16-row weight tile (A, int8) by 64 inputs x 16 words of one digit plane (B);
-// per digit the int32 accumulator holds sum_k W[row][k] s_c[k].  The epilogue
-// forms y = sum_{c<D-1} 256^c acc_c exactly in FP64, adds 256^(D-1) acc_(D-1)
-// as an exact modular product and corr[row][limb] = 128 S * (row sum) mod q,
-// and reduces.  The host admits a layer when every |W| <= 127 and every row's
-// sum of |W| is at most 2^20, which keeps acc_c within int32 and y below 2^52.
-//
-// Operand layout (16x16x64): lane l = 16 g + i holds A[i][16 g + j] and
-// B[16 g + j][i] as bytes j = 0..15 of its four dwords; D[4 g + r][i] is its
-// accumulator element r.  A is packed on the host per (tile, k-step) in exactly
-// that order; B is formed here through LDS.
-//
-// A workgroup has four waves: WM along the output tiles (MTW tiles each) and
-// 4/WM along the words (16 words each).  Per k-step of 64 inputs all threads
-// load the 64 x SPAN input block (coalesced along the words), split it into
-// digit planes in LDS, and each wave runs MTW x D matrix products.  Workgroups
-// of the output-tile groups that read one word block are adjacent in the grid.
-typedef int v4i __attribute__((ext_vector_type(4)));
-
-template <int D, int MTW, int WM>
-__global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(MTW == 4 ? 3 : 1)))
-k_mac_mfma(const double* __restrict__ in, double* __restrict__ out, int words, int logn, int level, int n_in,
-           int n_out, int ksteps, int mtiles, int mgroups, const v4i* __restrict__ A8, const double* __restrict__ corr,
-           int corr_stride, Basis b,
-           const Mod* __restrict__ mods, size_t in_req, size_t out_req, DeltaAdd da) {
-  static_assert(D == 4 || D == 5, "four or five byte digits");
-  constexpr int WN = 4 / WM;          // word tiles per workgroup
-  constexpr int SPAN = 16 * WN;       // words per workgroup
-  constexpr int PITCH = 20;           // dwords per (digit, word) row: 16 data + 4 pad, rows stay 16-B aligned
-  __shared__ __align__(16) uint32_t stage[D * SPAN * PITCH];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int g = lane >> 4, li = lane & 15;
-  const int wm = wave % WM, wn = wave / WM;
-  // blockIdx.x = word block * mgroups + output-tile group: the groups reading one word block are
-  // dispatched together and share its inputs in L2
-  const int mg = blockIdx.x % mgroups;
-  const int mt0 = (mg * WM + wm) * MTW;
-  const int w0 = (blockIdx.x / mgroups) * SPAN;
-  in += blockIdx.z * in_req;
-  out += blockIdx.z * out_req;
-  v4i acc[MTW][D];
-#pragma unroll
-  for (int t = 0; t < MTW; ++t)
-#pragma unroll
-    for (int c = 0; c < D; ++c) acc[t][c] = v4i{0, 0, 0, 0};
-
-  // Inputs of a k-step: each thread handles WN (k-quad, word) pairs of its 16 x SPAN.  The
-  // loads of PD = 4/WN consecutive k-steps are issued together (16 doubles per thread in
-  // flight), then the steps are split into digits and multiplied one after the other.
-  constexpr int PD = 4 / WN;
-  double xv[PD][WN][4];
-  for (int kb = 0; kb < ksteps; kb += PD) {
-#pragma unroll
-    for (int s2 = 0; s2 < PD; ++s2) {
-      const int ks = kb + s2;
-#pragma unroll
-      for (int qq = 0; qq < WN; ++qq) {
-        const int idx = tid + TPB * qq;
-        const int n = idx % SPAN, kq = idx / SPAN;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int k = ks * 64 + kq * 4 + j;
-          xv[s2][qq][j] = (ks < ksteps && k < n_in) ? in[(size_t)k * words + w0 + n] : 0.0;
-        }
-      }
-    }
-#pragma unroll
-    for (int s2 = 0; s2 < PD; ++s2) {
-      const int ks = kb + s2;
-      if (ks >= ksteps) break;   // uniform over the workgroup
-#pragma unroll
-      for (int qq = 0; qq < WN; ++qq) {
-        const int idx = tid + TPB * qq;
-        const int n = idx % SPAN, kq = idx / SPAN;
-        uint32_t lo[4], hi[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const double x = xv[s2][qq][j];
-          if constexpr (D == 5) {
-            const double h = floor(x * 0x1p-32);
-            lo[j] = (uint32_t)fma(h, -0x1p32, x);
-            hi[j] = (uint32_t)h;
-          } else {
-            lo[j] = (uint32_t)x;
-            hi[j] = 0u;
-          }
-        }
-        uint32_t* row = stage + (size_t)n * PITCH + kq;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int sh = 8 * c;
-          const uint32_t d = ((lo[0] >> sh) & 0xffu) | (((lo[1] >> sh) & 0xffu) << 8) |
-                             (((lo[2] >> sh) & 0xffu) << 16) | (((lo[3] >> sh) & 0xffu) << 24);
-          row[(size_t)c * SPAN * PITCH] = d ^ 0x80808080u;
-        }
-        if constexpr (D == 5) {
-          const uint32_t d = hi[0] | (hi[1] << 8) | (hi[2] << 16) | (hi[3] << 24);
-          row[(size_t)4 * SPAN * PITCH] = d ^ 0x80808080u;
-        }
-      }
-      __syncthreads();
-      v4i bop[D];
-#pragma unroll
-      for (int c = 0; c < D; ++c)
-        bop[c] = *reinterpret_cast<const v4i*>(stage + ((size_t)c * SPAN + wn * 16 + li) * PITCH + 4 * g);
-#pragma unroll
-      for (int t = 0; t < MTW; ++t) {
-        if (mt0 + t < mtiles) {   // uniform over the wave
-          const v4i a = A8[((size_t)(mt0 + t) * ksteps + ks) * 64 + lane];
-#pragma unroll
-          for (int c = 0; c < D; ++c)
-            acc[t][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, bop[c], acc[t][c], 0, 0, 0);
-        }
-      }
-      __syncthreads();
-    }
-  }
-
-  const int w = w0 + wn * 16 + li;
-  const int limb = (w >> logn) % level;
-  const Mod m = mods[b.id[limb]];
-  const bool add = da.msg != nullptr && w < (words >> 1);
-  const size_t kc = (size_t)w & (((size_t)1 << logn) - 1);
-  constexpr double kTop = D == 5 ? 0x1p32 : 0x1p24;   // 256^(D-1) <= q, as mul_lazy needs
-#pragma unroll
-  for (int t = 0; t < MTW; ++t) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = (mt0 + t) * 16 + 4 * g + r;
-      if (row >= n_out) continue;
-      double y = (double)acc[t][D - 2][r];
-#pragma unroll
-      for (int c = D - 3; c >= 0; --c) y = fma(y, 256.0, (double)acc[t][c][r]);
-      y += mul_lazy(kTop, (double)acc[t][D - 1][r], m) + corr[(size_t)row * corr_stride + limb];
-      double v = reduce(y, m);
-      if (add) {
-        const double mv = da.msg[blockIdx.z * da.msg_req + ((size_t)row << logn) + kc];
-        const double rt = mul_mod(da.qmodt, mv, da.mt);
-        double d = norm(mul_lazy(rt, da.negtinv[limb], m), m);
-        if (2.0 * rt > da.mt.q) d = add_mod(d, 1.0, m);
-        v = add_mod(v, d, m);
-      }
-      out[(size_t)row * words + w] = v;
-    }
   }
 }
 
@@ -721,11 +572,10 @@ __global__ void k_quantise(const float* __restrict__ f, int n_pt, int mode, int 
 // r * stride_b + j (request r, feature j) takes, at slot b < batch, the quantised
 // feature f[r][b][j] (zero at the other slots), reduced mod t and written at the
 // transform position of slot b.  Every position is written, so no clearing pass.
-// Features of slot b for plaintext p sit at f[(r * batch + b) * stride_b + j] with
-// p = r * stride_b + j: consecutive plaintexts are consecutive floats of one image.
-// A block takes 64 consecutive transform-domain words (their slots from the inverse
-// slot map) x 32 plaintexts: it reads each slot's 32 features as one run, quantises,
-// and transposes through LDS so that every plaintext row is written as one run.
+// Consecutive plaintexts are consecutive floats of one image, so a block takes 64
+// consecutive transform-domain words (their slots from the inverse slot map) x 32
+// plaintexts: it reads each slot's 32 features as one run, quantises, and
+// transposes through LDS so that every plaintext row is written as one run.
 // Quantised values lie in [-clampv, clampv] with clampv < t, so q mod t is q or q + t.
 __global__ void __launch_bounds__(TPB)
 k_features_to_t(const float* __restrict__ f, int n_pt, int batch, int stride_b, float scale, int clampv, double t,
@@ -801,37 +651,18 @@ void mac(const Context& c, const MacPlan& p, const double* in, double* out, int 
   }
   // algorithmic work: one FMA per word for each nonzero (output, input) weight
   ProfScope ps(c, "mac", s, 8.0 * words * ((double)p.n_in + p.n_out) * requests, (double)words * p.nnz * requests);
-  const Basis b = c.basis_Q(level);
-  if (p.mfma_mtw > 0) {
-    const int span = 64 / p.mfma_wm;
-    if (words % span != 0) throw Error(-1, "matrix-core MAC needs whole word tiles");
-    const int tiles_per_wg = p.mfma_wm * p.mfma_mtw;
-    const int mgroups = (p.mtiles + tiles_per_wg - 1) / tiles_per_wg;
-    dim3 g((words / span) * mgroups, 1, requests);
-    const int key = p.mfma_digits * 100 + p.mfma_mtw * 10 + p.mfma_wm;
-    switch (key) {
-#define BCN_MFMA_CASE(D, MTW, WM)                                                                               \
-  case D * 100 + MTW * 10 + WM:                                                                                 \
-    hipLaunchKernelGGL((k_mac_mfma<D, MTW, WM>), g, dim3(TPB), 0, s, in, out, words, c.logn, level, p.n_in,     \
-                       p.n_out, p.ksteps, p.mtiles, mgroups, static_cast<const v4i*>(p.A8), p.corr, c.L, b, c.tab.mods, \
-                       in_req,                                                                                 \
-                       out_req, da);                                                                           \
-    break;
-      BCN_MFMA_CASE(4, 1, 1) BCN_MFMA_CASE(4, 1, 2) BCN_MFMA_CASE(4, 1, 4) BCN_MFMA_CASE(4, 2, 4)
-      BCN_MFMA_CASE(4, 4, 4) BCN_MFMA_CASE(4, 2, 2)
-      BCN_MFMA_CASE(5, 1, 1) BCN_MFMA_CASE(5, 1, 2) BCN_MFMA_CASE(5, 1, 4) BCN_MFMA_CASE(5, 2, 4)
-      BCN_MFMA_CASE(5, 4, 4) BCN_MFMA_CASE(5, 2, 2)
-#undef BCN_MFMA_CASE
-      default: throw Error(-1, "unsupported matrix-core MAC shape");
-    }
-    BCN_HIP(hipGetLastError());
-    return;
-  }
   dim3 grid(nblocks(words), p.n_tiles, requests);
+  const Basis b = c.basis_Q(level);
   switch (p.tile) {
-#define BCN_MAC_CASE(TO) \
-  case TO: hipLaunchKernelGGL(k_mac<TO>, grid, dim3(TPB), 0, s, in, out, words, c.logn, level, p.W, p.rows, \
-                              p.tile_ptr, p.tile_cols, p.chunk, b, c.tab.mods, in_req, out_req, da); break;
+#define BCN_MAC_CASE(TO)                                                                                  \
+  case TO:                                                                                                \
+    if (p.centre)                                                                                         \
+      hipLaunchKernelGGL((k_mac<TO, true>), grid, dim3(TPB), 0, s, in, out, words, c.logn, level, p.W, p.rows, \
+                         p.tile_ptr, p.tile_cols, p.chunk, b, c.tab.mods, in_req, out_req, da);             \
+    else                                                                                                  \
+      hipLaunchKernelGGL((k_mac<TO, false>), grid, dim3(TPB), 0, s, in, out, words, c.logn, level, p.W,    \
+                         p.rows, p.tile_ptr, p.tile_cols, p.chunk, b, c.tab.mods, in_req, out_req, da);     \
+    break;
     BCN_MAC_CASE(1) BCN_MAC_CASE(2) BCN_MAC_CASE(4) BCN_MAC_CASE(8) BCN_MAC_CASE(16) BCN_MAC_CASE(32)
     BCN_MAC_CASE(64)
 #undef BCN_MAC_CASE

@@ -71,14 +71,14 @@ Layer* layer_create(Context& c, const bcn_layer_desc& d, int level) {
       for (int i = 0; i < L->oh; ++i)
         for (int j = 0; j < L->ow; ++j)
           for (int o = 0; o < d.out_c; ++o) order.push_back((o * L->oh + i) * L->ow + j);
-      L->mac = make_mac_plan_auto(c, W, L->n_out, L->n_in, order, 16);
+      L->mac = make_mac_plan(c, W, L->n_out, L->n_in, order, 16);
       L->mac_weights = W;
       L->mac_order = order;
     } else {
       L->n_in = d.in_c * d.in_h * d.in_w;
       L->n_out = d.out_c;
       std::vector<int32_t> W(d.weights, d.weights + (size_t)L->n_out * L->n_in);
-      L->mac = make_mac_plan_auto(c, W, L->n_out, L->n_in);
+      L->mac = make_mac_plan(c, W, L->n_out, L->n_in);
       L->mac_weights = W;
     }
     L->stride_b = L->n_out;
@@ -114,7 +114,7 @@ Layer* layer_create(Context& c, const bcn_layer_desc& d, int level) {
       for (int ci = 0; ci < d.in_c; ++ci)
         for (int t = 0; t < k2; ++t)
           W[(size_t)o * d.in_c * k2 + ci * k2 + tap_of[t]] = d.weights[(o * d.in_c + ci) * k2 + t];
-    L->mac = make_mac_plan_auto(c, W, d.out_c, d.in_c * k2);
+    L->mac = make_mac_plan(c, W, d.out_c, d.in_c * k2);
     L->mac_weights = W;
     // valid output slots and their mask
     const int ops = d.pos_stride * d.stride;

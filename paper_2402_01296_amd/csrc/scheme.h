@@ -56,17 +56,6 @@ void rotate_sum(Context& c, const EvalKeys& ek, double* ct, int n, int level, in
 // tile (power of two <= 64, 0 = automatic)
 MacPlan make_mac_plan(const Context& c, const std::vector<int32_t>& w, int n_out, int n_in,
                       const std::vector<int>& order = {}, int tile = 0);
-// Matrix-core MAC plan; throws unless every |weight| <= 127, every row's sum of |weights| is at
-// most 2^20, and all Q primes need the same number of byte digits (4 or 5).
-MacPlan make_mac_plan_mfma(const Context& c, const std::vector<int32_t>& w, int n_out, int n_in, int mtw, int wm);
-bool mac_mfma_eligible(const Context& c, const std::vector<int32_t>& w, int n_out, int n_in);
-bool mac_mfma_shape_ok(int mtw, int wm);
-// default matrix-core shape for n_out outputs: enough 16-row tiles per workgroup to cover them once
-void mac_mfma_default_shape(int n_out, int* mtw, int* wm);
-// the matrix-core plan (default shape, or BCN_MAC_MFMA=MTWxWM) when the weights admit it, else the
-// VALU plan; BCN_MAC_MFMA=0 always takes the VALU plan
-MacPlan make_mac_plan_auto(const Context& c, const std::vector<int32_t>& w, int n_out, int n_in,
-                           const std::vector<int>& order = {}, int tile = 0);
 void free_mac_plan(MacPlan& p);
 
 }  // namespace bcn

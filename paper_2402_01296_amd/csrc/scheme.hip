@@ -1,7 +1,6 @@
 // Scheme operations: keys, E / D, square + relinearisation, rotations.
 #include <algorithm>
-#include <cstdio>
-#include <cstdlib>
+#include <cmath>
 #include <cstring>
 
 #include "scheme.h"
@@ -386,6 +385,15 @@ MacPlan make_mac_plan(const Context& c, const std::vector<int32_t>& w, int n_out
   const double room = 9007199254740992.0 - qmax;
   p.chunk = std::max(4, (int)std::min(1e6, std::floor(room / ((double)wmax * qmax * 0.5))));
   if ((double)p.chunk * wmax * qmax * 0.5 >= room) throw Error(-1, "weights too large for exact accumulation");
+  // residues in [0, q) need no centring when each tile's sum of |w| times q - 1 stays below 2^53
+  double tile_abs_max = 0;
+  for (int t = 0; t < p.n_tiles; ++t)
+    for (int o = 0; o < tile; ++o) {
+      double a = 0;
+      for (int e = ptr[t]; e < ptr[t + 1]; ++e) a += std::fabs(W[(size_t)e * tile + o]);
+      tile_abs_max = std::max(tile_abs_max, a);
+    }
+  p.centre = !(tile_abs_max * qmax < room);
   BCN_HIP(hipMalloc(&p.W, std::max<size_t>(1, W.size()) * sizeof(double)));
   BCN_HIP(hipMalloc(&p.rows, rows.size() * sizeof(int)));
   BCN_HIP(hipMalloc(&p.tile_ptr, ptr.size() * sizeof(int)));
@@ -397,124 +405,12 @@ MacPlan make_mac_plan(const Context& c, const std::vector<int32_t>& w, int n_out
   return p;
 }
 
-namespace {
-// byte digits of the matrix-core MAC for the context's primes: D with 256^(D-1) <= q < 256^D for
-// every q (4 or 5), else 0
-int mfma_digits(const Context& c) {
-  uint64_t qmin = ~0ull, qmax = 0;
-  for (int i = 0; i < c.L; ++i) {
-    qmin = std::min<uint64_t>(qmin, c.primes[i]);
-    qmax = std::max<uint64_t>(qmax, c.primes[i]);
-  }
-  if (qmin >= (1ull << 24) && qmax < (1ull << 32)) return 4;
-  if (qmin >= (1ull << 32) && qmax < (1ull << 40)) return 5;
-  return 0;
-}
-}  // namespace
-
-bool mac_mfma_shape_ok(int mtw, int wm) {
-  return (mtw == 1 && (wm == 1 || wm == 2 || wm == 4)) || (mtw == 2 && (wm == 2 || wm == 4)) || (mtw == 4 && wm == 4);
-}
-
-void mac_mfma_default_shape(int n_out, int* mtw, int* wm) {
-  const int mt = (n_out + 15) / 16;
-  if (mt >= 9) { *mtw = 4; *wm = 4; }
-  else if (mt >= 5) { *mtw = 2; *wm = 4; }
-  else if (mt >= 3) { *mtw = 1; *wm = 4; }
-  else if (mt == 2) { *mtw = 1; *wm = 2; }
-  else { *mtw = 1; *wm = 1; }
-}
-
-MacPlan make_mac_plan_auto(const Context& c, const std::vector<int32_t>& w, int n_out, int n_in,
-                           const std::vector<int>& order, int tile) {
-  const char* e = std::getenv("BCN_MAC_MFMA");
-  if (e && std::strcmp(e, "0") == 0) return make_mac_plan(c, w, n_out, n_in, order, tile);
-  int mtw = 0, wm = 0;
-  if (e && *e) {
-    if (std::sscanf(e, "%dx%d", &mtw, &wm) != 2 || !mac_mfma_shape_ok(mtw, wm))
-      throw Error(-1, "BCN_MAC_MFMA must be 0 or MTWxWM (1x1, 1x2, 1x4, 2x2, 2x4, 4x4)");
-    // a pinned shape is honoured or refused, never silently replaced
-    if (!mac_mfma_eligible(c, w, n_out, n_in)) throw Error(-1, "weights not admissible for the matrix-core MAC");
-  } else {
-    mac_mfma_default_shape(n_out, &mtw, &wm);
-    if (!mac_mfma_eligible(c, w, n_out, n_in)) return make_mac_plan(c, w, n_out, n_in, order, tile);
-  }
-  return make_mac_plan_mfma(c, w, n_out, n_in, mtw, wm);
-}
-
-bool mac_mfma_eligible(const Context& c, const std::vector<int32_t>& w, int n_out, int n_in) {
-  const int D = mfma_digits(c);
-  if (D == 0 || n_out < 1 || n_in < 1 || w.size() != (size_t)n_out * n_in) return false;
-  double rowabs = 0;
-  for (int o = 0; o < n_out; ++o) {
-    double a = 0;
-    for (int k = 0; k < n_in; ++k) {
-      const int32_t v = w[(size_t)o * n_in + k];
-      if (v < -127 || v > 127) return false;
-      a += v < 0 ? -v : v;
-    }
-    rowabs = std::max(rowabs, a);
-  }
-  // |acc_c| <= 128 rowabs < 2^31, and the low digits' sum (< 2^31 rowabs) plus two residues
-  // stays below 2^52 for the final reduction
-  return rowabs <= 1048576.0;
-}
-
-MacPlan make_mac_plan_mfma(const Context& c, const std::vector<int32_t>& w, int n_out, int n_in, int mtw, int wm) {
-  if (!mac_mfma_shape_ok(mtw, wm)) throw Error(-1, "bad matrix-core MAC shape");
-  if (!mac_mfma_eligible(c, w, n_out, n_in)) throw Error(-1, "weights not admissible for the matrix-core MAC");
-  MacPlan p;
-  p.n_in = n_in;
-  p.n_out = n_out;
-  p.mfma_mtw = mtw;
-  p.mfma_wm = wm;
-  p.mfma_digits = mfma_digits(c);
-  p.mtiles = (n_out + 15) / 16;
-  p.ksteps = (n_in + 63) / 64;
-  // 128 S with S = sum_{c<D} 256^c
-  uint64_t S128 = 0;
-  for (int d = 0; d < p.mfma_digits; ++d) S128 = S128 * 256 + 1;
-  S128 *= 128;
-  // A operand of tile mt, k-step ks: lane 16 g + i holds W[16 mt + i][64 ks + 16 g + j], j = 0..15
-  std::vector<int8_t> A((size_t)p.mtiles * p.ksteps * 64 * 16, 0);
-  std::vector<double> corr((size_t)n_out * c.L, 0.0);   // [row][Q prime]
-  for (int mt = 0; mt < p.mtiles; ++mt)
-    for (int ks = 0; ks < p.ksteps; ++ks)
-      for (int lane = 0; lane < 64; ++lane)
-        for (int j = 0; j < 16; ++j) {
-          const int row = mt * 16 + (lane & 15), k = ks * 64 + 16 * (lane >> 4) + j;
-          if (row < n_out && k < n_in)
-            A[(((size_t)mt * p.ksteps + ks) * 64 + lane) * 16 + j] = (int8_t)w[(size_t)row * n_in + k];
-        }
-  for (int o = 0; o < n_out; ++o) {
-    int64_t sum = 0;
-    for (int k = 0; k < n_in; ++k) {
-      sum += w[(size_t)o * n_in + k];
-      p.nnz += w[(size_t)o * n_in + k] != 0;
-    }
-    for (int i = 0; i < c.L; ++i) {
-      const uint64_t q = c.primes[i];
-      const uint64_t sm = (uint64_t)(((sum % (int64_t)q) + (int64_t)q) % (int64_t)q);
-      corr[(size_t)o * c.L + i] = (double)host::mulmod(S128 % q, sm, q);
-    }
-  }
-  BCN_HIP(hipMalloc(&p.A8, A.size()));
-  BCN_HIP(hipMalloc(&p.corr, corr.size() * sizeof(double)));
-  BCN_HIP(hipMemcpy(p.A8, A.data(), A.size(), hipMemcpyHostToDevice));
-  BCN_HIP(hipMemcpy(p.corr, corr.data(), corr.size() * sizeof(double), hipMemcpyHostToDevice));
-  return p;
-}
-
 void free_mac_plan(MacPlan& p) {
   if (p.W) (void)hipFree(p.W);
   if (p.rows) (void)hipFree(p.rows);
   if (p.tile_ptr) (void)hipFree(p.tile_ptr);
   if (p.tile_cols) (void)hipFree(p.tile_cols);
-  if (p.A8) (void)hipFree(p.A8);
-  if (p.corr) (void)hipFree(p.corr);
   p.W = nullptr;
   p.rows = p.tile_ptr = p.tile_cols = nullptr;
-  p.A8 = nullptr;
-  p.corr = nullptr;
 }
 }  // namespace bcn

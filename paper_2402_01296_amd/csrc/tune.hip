@@ -2,8 +2,6 @@
 // device with hipEvents and keeps the fastest.
 #include <algorithm>
 #include <cstdio>
-#include <cstdlib>
-#include <cstring>
 #include <string>
 
 #include "layers.h"
@@ -218,17 +216,16 @@ std::string autotune_layer_mac(Context& c, Layer& L, hipStream_t s) {
   if (L.mac_weights.empty()) return "";
   const size_t ctw = (size_t)2 * L.level * c.n;
   const int n_in_mac = L.mac.n_in;
-  const char* pin = std::getenv("BCN_MAC_MFMA");
-  if (pin && *pin && std::strcmp(pin, "0") != 0) return "mac pinned mfma=" + std::string(pin) + "\n";
-  const bool try_mfma = !(pin && std::strcmp(pin, "0") == 0) &&
-                        mac_mfma_eligible(c, L.mac_weights, L.mac.n_out, n_in_mac);
   double* in = c.arena->take((size_t)n_in_mac * ctw);
   double* out = c.arena->take((size_t)L.mac.n_out * ctw);
   BCN_HIP(hipMemsetAsync(in, 0, (size_t)n_in_mac * ctw * sizeof(double), s));
   std::string report;
   float best_ms = 1e30f;
-  int best_tile = 0, best_mtw = 0, best_wm = 0;   // tile > 0: VALU plan; mtw > 0: matrix-core plan
-  auto consider = [&](MacPlan p, int tile, int mtw, int wm) {
+  int best_tile = L.mac.tile;
+  for (int tile : {1, 2, 4, 8, 16, 32, 64}) {
+    if (tile / 2 >= L.mac.n_out && tile > 8) break;
+    if (tile < 8 && L.mac.n_out > 64) continue;   // narrow tiles only pay off for narrow layers
+    MacPlan p = make_mac_plan(c, L.mac_weights, L.mac.n_out, n_in_mac, L.mac_order, tile);
     float ms = 0;
     try {
       ms = time_ms(s, 5, [&] { mac(c, p, in, out, L.level, s); });
@@ -238,40 +235,19 @@ std::string autotune_layer_mac(Context& c, Layer& L, hipStream_t s) {
     }
     free_mac_plan(p);
     char line[128];
-    if (mtw > 0)
-      std::snprintf(line, sizeof line, "mac %dx%d mfma=%dx%d: %.3f ms\n", L.mac.n_out, n_in_mac, mtw, wm, ms);
-    else
-      std::snprintf(line, sizeof line, "mac %dx%d tile=%d: %.3f ms\n", L.mac.n_out, n_in_mac, tile, ms);
+    std::snprintf(line, sizeof line, "mac %dx%d tile=%d: %.3f ms\n", L.mac.n_out, n_in_mac, tile, ms);
     report += line;
     if (ms < best_ms) {
       best_ms = ms;
       best_tile = tile;
-      best_mtw = mtw;
-      best_wm = wm;
-    }
-  };
-  for (int tile : {1, 2, 4, 8, 16, 32, 64}) {
-    if (tile / 2 >= L.mac.n_out && tile > 8) break;
-    if (tile < 8 && L.mac.n_out > 64) continue;   // narrow tiles only pay off for narrow layers
-    consider(make_mac_plan(c, L.mac_weights, L.mac.n_out, n_in_mac, L.mac_order, tile), tile, 0, 0);
-  }
-  if (try_mfma) {
-    const int mt = (L.mac.n_out + 15) / 16;
-    const int shapes[6][2] = {{1, 1}, {1, 2}, {1, 4}, {2, 2}, {2, 4}, {4, 4}};
-    for (const auto& sh : shapes) {
-      if (sh[0] * sh[1] > 2 * mt && sh[0] * sh[1] > 1) continue;   // more than half the tiles idle
-      consider(make_mac_plan_mfma(c, L.mac_weights, L.mac.n_out, n_in_mac, sh[0], sh[1]), 0, sh[0], sh[1]);
     }
   }
-  BCN_HIP(hipStreamSynchronize(s));
-  free_mac_plan(L.mac);
-  if (best_mtw > 0) {
-    L.mac = make_mac_plan_mfma(c, L.mac_weights, L.mac.n_out, n_in_mac, best_mtw, best_wm);
-    report += "mac chosen mfma=" + std::to_string(best_mtw) + "x" + std::to_string(best_wm) + "\n";
-  } else {
+  if (best_tile != L.mac.tile) {
+    BCN_HIP(hipStreamSynchronize(s));
+    free_mac_plan(L.mac);
     L.mac = make_mac_plan(c, L.mac_weights, L.mac.n_out, n_in_mac, L.mac_order, best_tile);
-    report += "mac chosen tile=" + std::to_string(best_tile) + "\n";
   }
+  report += "mac chosen tile=" + std::to_string(best_tile) + "\n";
   return report;
 }
 

@@ -153,44 +153,6 @@ def test_mac_parity(env_t1k, n_in, n_out, bound):
         assert (out[o] == ref).all(), "output %d" % o
 
 
-_MFMA_REF = {}
-
-
-@pytest.mark.parametrize("shape", ["1x1", "1x2", "1x4", "2x2", "2x4", "4x4"])
-@pytest.mark.parametrize("pname", ["t1k", "t1k5", "t2k"])
-def test_mac_matrix_core_shapes(pname, shape, monkeypatch):
-    # The int8 matrix-core MAC (four byte digits for 30-bit primes, five for 36- and 40-bit) in every
-    # workgroup shape against the VALU MAC on all outputs, and against the oracle on sampled rows.
-    # 150 inputs: two full 64-input steps and a ragged third; 37 outputs: two full 16-row tiles
-    # and a ragged one.  Rows 0/1 are all +127/-127 (the largest row sums), row 3 alternates the
-    # extremes, row 2 is all zero.
-    torch_cuda()
-    prm, ctx = context(pname)
-    level = prm.L
-    n_in, n_out = 150, 37
-    if pname not in _MFMA_REF:
-        res = random_ct_residues(prm, level, n_in, 21)
-        w = np.random.default_rng(8).integers(-6, 7, (n_out, n_in)).astype(np.int32)
-        w[0] = 127
-        w[1] = -127
-        w[2] = 0
-        w[3, ::2] = 127
-        w[3, 1::2] = -127
-        w[4, :20] = -127
-        monkeypatch.setenv("BCN_MAC_MFMA", "0")
-        valu = ctx.export(ctx.mac(ctx.import_(res), w))
-        cts = [oracle_ct(prm, r) for r in res]
-        for o in (0, 1, 2, 3, 4, 36):
-            ref = bfv.ct_to_rns(prm, bfv.mac(prm, cts, w[o]))
-            assert (valu[o] == ref).all(), "VALU output %d" % o
-        _MFMA_REF[pname] = (res, w, valu)
-    res, w, valu = _MFMA_REF[pname]
-    monkeypatch.setenv("BCN_MAC_MFMA", shape)
-    got = ctx.export(ctx.mac(ctx.import_(res), w))
-    for o in range(n_out):
-        assert (got[o] == valu[o]).all(), "output %d" % o
-
-
 def test_plain_ops_parity(env_t1k):
     ev = env_t1k
     prm, ctx, enc = ev["prm"], ev["ctx"], ev["enc"]
