@@ -283,6 +283,7 @@ Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uin
   // the fused square keeps three register sets live; above N = 8192 it would spill
   c->fuse_square = logn <= 13;
   if (const char* env = std::getenv("BCN_FUSE_SQUARE")) c->fuse_square = logn <= 13 && std::atoi(env) != 0;
+  if (const char* env = std::getenv("BCN_FUSE_MODDOWN")) c->fuse_moddown = std::atoi(env) != 0;
   // the fused kernel keeps two accumulators and a working set in registers: N <= 8192, digits of <= 2 primes
   const bool can_fuse_ks = logn <= 13 && alpha <= 2;
   c->ks_mode = alpha <= 2 ? 2 : 0;

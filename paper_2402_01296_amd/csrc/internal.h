@@ -127,6 +127,7 @@ struct Context {
   int square_loge = 0;                   // the same for the fused square's transforms
   bool pinned_loge = false, pinned_square_loge = false, pinned_prefetch = false;   // fixed by the environment
   bool fuse_square = true;               // square's transforms and tensor in one kernel
+  bool fuse_moddown = true;              // relinearisation's ModDown also scales and rounds d0, d1
   bool ntt_persist = false;              // persistent, prefetching transform kernel
   bool ntt_prefetch = false;             // transform loads the next pass's twiddles before each exchange
   int persist_blocks = 512;              // its grid: workgroups resident at once
@@ -224,8 +225,10 @@ void ptvec_mac_ntt(const Context& c, const double* in, int n_in, double* out, in
 void tensor_square(const Context& c, const double* in, double* out, int n, const Basis& b, hipStream_t s);
 // exact centred extension of [n][2][level][N] (coeff) into [n][2][level+m][N] over Q_level then B
 void extend_qb(const Context& c, const double* in, double* out, int n, int level, hipStream_t s);
-// round(t x / Q_level) for [n][3][level+m][N] (coeff, Q then B) -> [n][3][level][N]
-void scale_round(const Context& c, const double* in, double* out, int n, int level, hipStream_t s);
+// round(t x / Q_level) for [n][3][level+m][N] (coeff, Q then B) -> [n][3][level][N], or with
+// only_d2 just part 2 of each ciphertext -> [n][level][N]
+void scale_round(const Context& c, const double* in, double* out, int n, int level, hipStream_t s,
+                 bool only_d2 = false);
 // centred digits of x [n][level][N] (coeff) raised to Q_level+P: [n][dnum][level+K][N]
 void decompose_modup(const Context& c, const double* in, size_t in_stride, double* out, int n, int level,
                      hipStream_t s);
@@ -264,6 +267,13 @@ void ks_split(const Context& c, const double* src, size_t src_stride, int n_src,
 void moddown(const Context& c, const double* u, int n, int level, const double* add, int add_div, size_t add_stride,
              int add_mode, const KeySel& ks, bool modswitch, double* out, hipStream_t s, int out_div = 0,
              size_t out_outer = 0);
+// Relinearisation's ModDown with the addend scaled and rounded inline: out = round(u/P) +
+// round(t y_k / Q_level) for parts k = 0, 1 of the square's tensor y ([n][3][level+m][N], coeff,
+// Q_level then B), optionally modulus-switched.  Returns false (nothing launched) when the
+// shape (special, ciphertext and auxiliary prime counts) has no compiled variant.
+bool moddown_scale_round(const Context& c, const double* u, int n, int level, const double* y, bool modswitch,
+                         double* out, hipStream_t s);
+bool moddown_scale_round_ok(const Context& c, int level);
 // out = a + b over [count] words whose limb is (word >> logn) % nl
 // a += b over n polynomials of `level` limbs ([n][level][N], limb = row % level)
 void add_inplace(const Context& c, double* a, const double* b, int npoly, int level, hipStream_t s);

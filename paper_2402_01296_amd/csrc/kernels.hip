@@ -204,20 +204,14 @@ k_extend_qb(const double* __restrict__ in, double* __restrict__ out, int npoly, 
   }
 }
 
-// [n][3][level+m][N] (Q_level then B) -> [n][3][level][N]: round(t x / Q_level) mod q_i.
+// round(t x / Q_level) mod q_d, d < nq, for one coefficient x given by its NS residues
+// src[i * N] over Q_level then B (x centred, |x| < Q_level B / 2).
 // cv.src = Q_level + B, cv.dst = Q_level, cv.pm[d][k] = src_k mod q_d, cv.aux[d] = B mod q_d,
-// cv.aux2[0] = t, nq = level.
+// cv.aux2[0] = t.
 template <int NS>
-__global__ void __launch_bounds__(TPB)
-k_scale_round(const double* __restrict__ in, double* __restrict__ out, int npoly, int logn, int nq,
-              const Conv* __restrict__ cvp, const Mod* __restrict__ mods) {
-  const size_t N = (size_t)1 << logn;
-  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
-  if (idx >= (size_t)npoly * N) return;
-  const Conv& cv = *cvp;
-  const size_t poly = idx >> logn, k = idx & (N - 1);
+__device__ __forceinline__ void scale_round_coeff(const double* __restrict__ src, size_t N, int nq, const Conv& cv,
+                                                  const Mod* __restrict__ mods, double (&res)[NS]) {
   const double t = cv.aux2[0];
-  const double* src = in + poly * NS * N + k;
   double x[NS], v[NS];
 #pragma unroll
   for (int i = 0; i < NS; ++i) x[i] = src[i * N];
@@ -239,8 +233,9 @@ k_scale_round(const double* __restrict__ in, double* __restrict__ out, int npoly
   }
   const bool up = above_half<NS>(wdig, nq, cv, mods);
   const double R = c + (up ? 1.0 : 0.0);                          // round(t r / Q) in [0, t]
-  double* dst = out + poly * nq * N + k;
-  for (int d = 0; d < nq; ++d) {
+#pragma unroll
+  for (int d = 0; d < NS; ++d) {
+    if (d >= nq) break;
     const Mod md = mods[cv.dst[d]];
     // K = floor(x / Q) from the B digits, minus B when the centred value is negative
     double acc = v[NS - 1];
@@ -249,7 +244,27 @@ k_scale_round(const double* __restrict__ in, double* __restrict__ out, int npoly
       if (kk >= nq) acc = mul_lazy(acc, cv.pm[d][kk], md) + v[kk];
     if (neg) acc -= cv.aux[d];
     const double y = mul_lazy(t, reduce(acc, md), md) + R;
-    dst[d * N] = reduce(y, md);
+    res[d] = reduce(y, md);
+  }
+}
+
+// [n][3][level+m][N] (Q_level then B) -> [n*][level][N]: round(t x / Q_level) mod q_i for the
+// polynomials poly_mul * i + poly_add of the input (1, 0: all three parts; 3, 2: only part 2).
+template <int NS>
+__global__ void __launch_bounds__(TPB)
+k_scale_round(const double* __restrict__ in, double* __restrict__ out, int npoly, int logn, int nq, int poly_mul,
+              int poly_add, const Conv* __restrict__ cvp, const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << logn;
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx >= (size_t)npoly * N) return;
+  const size_t poly = idx >> logn, k = idx & (N - 1);
+  double res[NS];
+  scale_round_coeff<NS>(in + (poly * poly_mul + poly_add) * NS * N + k, N, nq, *cvp, mods, res);
+  double* dst = out + poly * nq * N + k;
+#pragma unroll
+  for (int d = 0; d < NS; ++d) {
+    if (d >= nq) break;
+    dst[d * N] = res[d];
   }
 }
 
@@ -329,11 +344,15 @@ __device__ __forceinline__ double auto_gather(const double* __restrict__ a, int 
 // exact round(u/P) mod q_i, optional addend, optional modulus switch.
 // cv.src = P primes (NK), cv.dst = Q_level; cv.pm/Mmod as for conversions;
 // cv.aux[d] = P^-1 mod q_d; cv.aux2[d] = q_{level-1}^-1 mod q_d.
-template <int NK, int NQ>
+// NS > 0 (relinearisation): the addend is parts 0 and 1 of the square's tensor y
+// ([n][3][NS][N] over Q_level then B), scaled and rounded here by the same per-coefficient
+// steps as k_scale_round, so those two parts never round-trip through HBM.
+template <int NK, int NQ, int NS = 0>
 __global__ void __launch_bounds__(TPB)
 k_moddown(const double* __restrict__ u, int n, int logn, const double* __restrict__ add, int add_div,
           size_t add_stride, int add_mode, KeySel ks, int modsw, const Conv* __restrict__ cvp,
-          const Mod* __restrict__ mods, double* __restrict__ out, int out_div, size_t out_outer) {
+          const Mod* __restrict__ mods, double* __restrict__ out, int out_div, size_t out_outer,
+          const double* __restrict__ y = nullptr, const Conv* __restrict__ srcv = nullptr) {
   const size_t N = (size_t)1 << logn;
   const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
   if (idx >= (size_t)n * 2 * N) return;
@@ -348,6 +367,8 @@ k_moddown(const double* __restrict__ u, int n, int logn, const double* __restric
   for (int i = 0; i < NK; ++i) x[i] = up[(NQ + i) * N];
   garner<NK>(x, v, cv, mods);
   const bool neg = above_half<NK>(v, NK, cv, mods);
+  double sr[NS > 0 ? NS : 1];
+  if constexpr (NS > 0) scale_round_coeff<NS>(y + (ci * 3 + part) * (size_t)NS * N + k, N, NQ, *srcv, mods, sr);
   double res[NQ];
 #pragma unroll
   for (int d = 0; d < NQ; ++d) {
@@ -357,7 +378,9 @@ k_moddown(const double* __restrict__ u, int n, int logn, const double* __restric
     for (int kk = NK - 2; kk >= 0; --kk) acc = mul_lazy(acc, cv.pm[d][kk], md) + v[kk];
     if (neg) acc -= cv.Mmod[d];                                    // |acc| < 2^43: lift_c([u]_P) mod q_d
     double r = norm(mul_lazy(up[d * N] - reduce(acc, md), cv.aux[d], md), md);
-    if (add_mode == 1) {
+    if constexpr (NS > 0) {
+      r = add_mod(r, sr[d], md);
+    } else if (add_mode == 1) {
       r = add_mod(r, add[(ci / add_div) * add_stride + (size_t)(part * NQ + d) * N + k], md);
     } else if (add_mode == 2 && part == 0) {
       const int kinv = ks.kinv ? ks.kinv[ci % ks.nk] : ks.kinv1;
@@ -723,12 +746,11 @@ void extend_qb(const Context& c, const double* in, double* out, int n, int level
   BCN_HIP(hipGetLastError());
 }
 
-void scale_round(const Context& c, const double* in, double* out, int n, int level, hipStream_t s) {
-  if (n == 0) return;
+// the scale-and-round conversion of level `level` (Q_level + B -> Q_level), cached on the device
+static const Conv* scale_round_conv(const Context& c, int level) {
   std::vector<int> src, dst;
   for (int i = 0; i < level; ++i) { src.push_back(c.idQ(i)); dst.push_back(c.idQ(i)); }
   for (int i = 0; i < c.m; ++i) src.push_back(c.idB(i));
-  const std::string key = "sr" + std::to_string(level);
   Conv cv = make_conv(c, src, dst);
   for (int d = 0; d < level; ++d) {
     uint64_t bm = 1;
@@ -737,12 +759,18 @@ void scale_round(const Context& c, const double* in, double* out, int n, int lev
     cv.aux[d] = (double)bm;
   }
   cv.aux2[0] = (double)c.t;
-  const Conv* dcv = conv_device(c, key, cv);
-  const int npoly = 3 * n;
+  return conv_device(c, "sr" + std::to_string(level), cv);
+}
+
+void scale_round(const Context& c, const double* in, double* out, int n, int level, hipStream_t s, bool only_d2) {
+  if (n == 0) return;
+  const Conv* dcv = scale_round_conv(c, level);
+  const int npoly = only_d2 ? n : 3 * n;
+  const int pmul = only_d2 ? 3 : 1, padd = only_d2 ? 2 : 0;
   const int ns = level + c.m;
   ProfScope ps(c, "scale_round", s, 8.0 * npoly * (double)c.n * (ns + level));
 #define BCN_SR(NS) hipLaunchKernelGGL(k_scale_round<NS>, dim3(nblocks((size_t)npoly * c.n)), dim3(TPB), 0, s, in, out, \
-                                      npoly, c.logn, level, dcv, c.tab.mods)
+                                      npoly, c.logn, level, pmul, padd, dcv, c.tab.mods)
   BCN_DISPATCH_NS(ns, BCN_SR)
 #undef BCN_SR
   BCN_HIP(hipGetLastError());
@@ -784,10 +812,8 @@ void ks_inner(const Context& c, const double* D, int d_div, const KeySel& ka, in
   BCN_HIP(hipGetLastError());
 }
 
-void moddown(const Context& c, const double* u, int n, int level, const double* add, int add_div, size_t add_stride,
-             int add_mode, const KeySel& ks, bool modsw, double* out, hipStream_t s, int out_div, size_t out_outer) {
-  if (n == 0) return;
-  if (modsw && level < 2) throw Error(-2, "modulus switch needs at least two primes");
+namespace {
+const Conv* moddown_conv(const Context& c, int level) {
   std::vector<int> src, dst;
   for (int i = 0; i < c.K; ++i) src.push_back(c.idP(i));
   for (int i = 0; i < level; ++i) dst.push_back(c.idQ(i));
@@ -799,7 +825,52 @@ void moddown(const Context& c, const double* u, int n, int level, const double* 
     cv.aux[d] = (double)host::invmod(pm, q);
     cv.aux2[d] = (d < level - 1) ? (double)host::invmod(c.primes[level - 1] % q, q) : 0.0;
   }
-  const Conv* dcv = conv_device(c, "md" + std::to_string(level), cv);
+  return conv_device(c, "md" + std::to_string(level), cv);
+}
+}  // namespace
+
+bool moddown_scale_round_ok(const Context& c, int level) {
+  // compiled for 1 or 2 special primes, 2..6 ciphertext primes and 4..7 auxiliary primes
+  return c.K >= 1 && c.K <= 2 && level >= 2 && level <= 6 && c.m >= 4 && c.m <= 7;
+}
+
+bool moddown_scale_round(const Context& c, const double* u, int n, int level, const double* y, bool modsw,
+                         double* out, hipStream_t s) {
+  const int ns = level + c.m;
+  if (!moddown_scale_round_ok(c, level)) return false;
+  if (n == 0) return true;
+  const Conv* dcv = moddown_conv(c, level);
+  const Conv* scv = scale_round_conv(c, level);
+  const size_t work = (size_t)n * 2 * c.n;
+  // reads u (level + K limbs) and parts 0, 1 of y (level + m limbs), writes the output
+  ProfScope ps(c, "moddown", s, 8.0 * work * ((double)level + c.K + ns + (modsw ? level - 1 : level)));
+  const KeySel ks;
+  const size_t out_outer = (size_t)2 * (modsw ? level - 1 : level) * c.n;
+  const int key = c.K * 10000 + level * 100 + ns;
+  switch (key) {
+#define BCN_MDS(NK, NQ, NS)                                                                                      \
+  case NK * 10000 + NQ * 100 + NS:                                                                               \
+    hipLaunchKernelGGL((k_moddown<NK, NQ, NS>), dim3(nblocks(work)), dim3(TPB), 0, s, u, n, c.logn, nullptr, 1,    \
+                       (size_t)0, 4, ks, modsw ? 1 : 0, dcv, c.tab.mods, out, 1, out_outer, y, scv);             \
+    break;
+#define BCN_MDS_M(NK, NQ) BCN_MDS(NK, NQ, NQ + 4) BCN_MDS(NK, NQ, NQ + 5) BCN_MDS(NK, NQ, NQ + 6) BCN_MDS(NK, NQ, NQ + 7)
+#define BCN_MDS_Q(NK) BCN_MDS_M(NK, 2) BCN_MDS_M(NK, 3) BCN_MDS_M(NK, 4) BCN_MDS_M(NK, 5) BCN_MDS_M(NK, 6)
+    BCN_MDS_Q(1)
+    BCN_MDS_Q(2)
+#undef BCN_MDS_Q
+#undef BCN_MDS_M
+#undef BCN_MDS
+    default: return false;
+  }
+  BCN_HIP(hipGetLastError());
+  return true;
+}
+
+void moddown(const Context& c, const double* u, int n, int level, const double* add, int add_div, size_t add_stride,
+             int add_mode, const KeySel& ks, bool modsw, double* out, hipStream_t s, int out_div, size_t out_outer) {
+  if (n == 0) return;
+  if (modsw && level < 2) throw Error(-2, "modulus switch needs at least two primes");
+  const Conv* dcv = moddown_conv(c, level);
   const size_t work = (size_t)n * 2 * c.n;
   ProfScope ps(c, "moddown", s, 8.0 * work * ((double)level + c.K + (add_mode ? level : 0) + (modsw ? level - 1 : level)));
 #define BCN_MD(NK, NQ) hipLaunchKernelGGL((k_moddown<NK, NQ>), dim3(nblocks(work)), dim3(TPB), 0, s, u, n, c.logn, add, \

@@ -248,24 +248,33 @@ void square_relin(Context& c, const EvalKeys& ek, const double* in, double* out,
     tensor_square(c, X, Y, n, qb, s);
     ntt_inverse(c, Y, 3 * n, qb, s);
   }
-  double* Z = ar.take((size_t)n * 3 * level * N);
-  scale_round(c, Y, Z, n, level, s);
+  // d2 = round(t y_2 / Q) feeds the key switch; parts 0 and 1 are either scaled and rounded
+  // inside ModDown (fused) or here with d2 (Z holds all three parts)
+  const bool fuse = c.fuse_moddown && moddown_scale_round_ok(c, level);
+  double* Z = ar.take((size_t)n * (fuse ? 1 : 3) * level * N);
+  scale_round(c, Y, Z, n, level, s, fuse);
+  const double* z2 = fuse ? Z : Z + 2 * level * N;
+  const size_t z2_stride = (size_t)(fuse ? 1 : 3) * level * N;
   double* U = ar.take((size_t)n * 2 * nbp * N);
   KeySel ks;
   ks.key1 = ek.relin;
   if (c.ks_mode == 1) {
-    ks_fused(c, Z + 2 * level * N, (size_t)3 * level * N, n, level, ek.relin, 1, U, s);
+    ks_fused(c, z2, z2_stride, n, level, ek.relin, 1, U, s);
   } else if (c.ks_mode == 2) {
     double* D = ar.take((size_t)n * dn * nbp * N);
-    ks_split(c, Z + 2 * level * N, (size_t)3 * level * N, n, level, ks, n, 1, D, U, s);
+    ks_split(c, z2, z2_stride, n, level, ks, n, 1, D, U, s);
   } else {
     double* D = ar.take((size_t)n * dn * nbp * N);
-    decompose_modup(c, Z + 2 * level * N, (size_t)3 * level * N, D, n, level, s);
+    decompose_modup(c, z2, z2_stride, D, n, level, s);
     ntt_forward(c, D, n * dn, qp, s);
     ks_inner(c, D, 1, ks, n, level, U, s);
     ntt_inverse(c, U, 2 * n, qp, s);
   }
-  moddown(c, U, n, level, Z, 1, (size_t)3 * level * N, 1, ks, modsw, out, s);
+  if (fuse) {
+    if (!moddown_scale_round(c, U, n, level, Y, modsw, out, s)) throw Error(-1, "no fused ModDown for this shape");
+  } else {
+    moddown(c, U, n, level, Z, 1, (size_t)3 * level * N, 1, ks, modsw, out, s);
+  }
 }
 
 void rotate_hoisted(Context& c, EvalKeys& ek, const double* in, int n_in, int level, const std::vector<int>& steps,

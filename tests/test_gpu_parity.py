@@ -281,17 +281,22 @@ _SQUARE_PATHS = [(p, fs, km, lg) for p in ("t1k", "t2k")
                                     ("1", "2", "4"))]
 _SQUARE_PATHS += [("cfg2", "0", "0", ""), ("cfg2", "1", "1", "4"), ("cfg2", "1", "1", "5"), ("cfg2", "1", "2", "4"),
                   ("cfg2", "1", "2", "5")]
+# ModDown scaling and rounding d0, d1 itself (default) or taking them from the scale-and-round kernel
+_SQUARE_PATHS = [sp + ("1",) for sp in _SQUARE_PATHS]
+_SQUARE_PATHS += [("t1k", "1", "2", "4", "0"), ("t2k", "1", "2", "4", "0"), ("t1k", "0", "0", "", "0"),
+                  ("cfg2", "1", "2", "4", "0")]
 
 
-@pytest.mark.parametrize("pname,fuse_sq,ks_mode,sq_loge", _SQUARE_PATHS)
-def test_square_paths_agree(pname, fuse_sq, ks_mode, sq_loge, monkeypatch):
-    """Fused (each transform shape) and unfused square, and every key-switching path, give the
-    oracle's exact ciphertexts."""
+@pytest.mark.parametrize("pname,fuse_sq,ks_mode,sq_loge,fuse_md", _SQUARE_PATHS)
+def test_square_paths_agree(pname, fuse_sq, ks_mode, sq_loge, fuse_md, monkeypatch):
+    """Fused (each transform shape) and unfused square, every key-switching path, and ModDown with
+    or without the scale-and-round of d0, d1 folded in, give the oracle's exact ciphertexts."""
     torch_cuda()
     from oracle import params
     from paper_2402_01296_amd import bcn
     monkeypatch.setenv("BCN_FUSE_SQUARE", fuse_sq)
     monkeypatch.setenv("BCN_KS_MODE", ks_mode)
+    monkeypatch.setenv("BCN_FUSE_MODDOWN", fuse_md)
     if sq_loge:
         monkeypatch.setenv("BCN_SQUARE_LOGE", sq_loge)
     prm, ctx = context(pname)
