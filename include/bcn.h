@@ -181,7 +181,7 @@ typedef struct {
   int32_t pos_stride;    /* HW: spacing of the valid input positions */
   const int32_t* weights;/* host; CONV2D [out_c][in_c][k][k], DENSE [out_c][in_c*in_h*in_w] */
   int32_t has_features;
-  float feature_scale;   /* 8.0 in this build's workloads */
+  float feature_scale;   /* 8.0 in the three workloads */
   int32_t feature_clamp; /* 127 */
   int32_t batch;         /* BATCH: images (slots) carrying data */
   int32_t square;        /* square + relinearise after the linear part (+features) */

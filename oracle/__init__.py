@@ -12,7 +12,7 @@ rounding on rationals.  It shares no code with the GPU path; the only shared
 module is ``synthetic`` (seeded random inputs, no scheme arithmetic).
 
 The paper runs CKKS inside SEAL (Experiments section; appendix "CKKS
-Scheme").  The workloads this build targets are integer-quantised and need
+Scheme").  The workloads here are integer-quantised and need
 decryptions that *equal* the integer network, so the oracle implements the
 exact-arithmetic sibling of that scheme, BFV with CRT batching, using the same
 operation set the appendix lists: E, D, Add(c,u), Add(c1,c2), Mult(c,u),

@@ -2,7 +2,7 @@
 
 Operation set of the appendix "CKKS Scheme": E, D, Add(c,u), Add(c1,c2),
 Mult(c,u), Mult(c1,c2), Rot(c,r).  This module gives each of them its exact
-definition in the integer (BFV) scheme this build implements, plus the key
+definition in the integer (BFV) scheme implemented here, plus the key
 switching that Mult(c1,c2) and Rot(c,r) imply, and modulus switching:
 
   [x]_M      residue in [0, M);  lift_c(x) = centred residue in (-M/2, M/2)
