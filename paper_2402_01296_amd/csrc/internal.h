@@ -210,8 +210,11 @@ struct MacPlan {
   bool centre = true;           // false: every tile's sum of |w| * (q-1) fits 2^53 uncentred
 };
 // requests > 1: independent requests at in + r*in_req, out + r*out_req (doubles)
+// out_ct, out_part (doubles): output row r's part k starts at out + r * out_ct + k * out_part
+// (0: contiguous [rows][2][level][N]); e.g. the Q limbs of a [rows][2][level+m][N] buffer
 void mac(const Context& c, const MacPlan& p, const double* in, double* out, int level, hipStream_t s, int requests = 1,
-         size_t in_req = 0, size_t out_req = 0, const double* delta_msg = nullptr);
+         size_t in_req = 0, size_t out_req = 0, const double* delta_msg = nullptr, size_t out_ct = 0,
+         size_t out_part = 0);
 
 // c0 of each ciphertext += Delta(m_i), m_i in [0, t) coefficient form, [n][N]
 void add_delta(const Context& c, double* ct, int n, int level, const double* m, hipStream_t s);

@@ -38,7 +38,7 @@ __global__ void __launch_bounds__(TPB)
 k_mac(const double* __restrict__ in, double* __restrict__ out, int words, int logn, int level,
       const double* __restrict__ Wp, const int* __restrict__ rows, const int* __restrict__ tptr,
       const int* __restrict__ tcols, int chunk, Basis b, const Mod* __restrict__ mods, size_t in_req,
-      size_t out_req, DeltaAdd da) {
+      size_t out_req, size_t out_ct, size_t out_part, DeltaAdd da) {
   const int w = blockIdx.x * TPB + threadIdx.x;
   if (w >= words) return;
   in += blockIdx.z * in_req;     // request blockIdx.z of a batch of independent requests
@@ -84,7 +84,8 @@ k_mac(const double* __restrict__ in, double* __restrict__ out, int words, int lo
     for (int o = 0; o < TO; ++o) acc[o] = fma(wr[o], x, acc[o]);
     ++cnt;
   }
-  const bool add = da.msg != nullptr && w < (words >> 1);            // part 0 words
+  const bool add_part = w < (words >> 1);                             // part 0 words
+  const bool add = da.msg != nullptr && add_part;
   const int limb = (w >> logn) % level;
   const size_t k = (size_t)w & (((size_t)1 << logn) - 1);
 #pragma unroll
@@ -99,7 +100,7 @@ k_mac(const double* __restrict__ in, double* __restrict__ out, int words, int lo
       if (2.0 * rt > da.mt.q) d = add_mod(d, 1.0, m);                 // nearest, never a tie (t odd)
       r = add_mod(r, d, m);
     }
-    out[(size_t)row * words + w] = r;
+    out[(size_t)row * out_ct + (add_part ? 0 : out_part) + (size_t)(add_part ? w : w - (words >> 1))] = r;
   }
 }
 
@@ -176,21 +177,22 @@ __global__ void k_tensor_square(const double* __restrict__ in, double* __restric
 // [n][2][level][N] over Q_level -> [n][2][level+m][N] over Q_level then B (centred lift)
 template <int NS>
 __global__ void __launch_bounds__(TPB)
-k_extend_qb(const double* __restrict__ in, double* __restrict__ out, int npoly, int logn,
-            const Conv* __restrict__ cvp, const Mod* __restrict__ mods) {
+k_extend_qb(const double* in, double* out, int npoly, int logn, int in_place, const Conv* __restrict__ cvp,
+            const Mod* __restrict__ mods) {
   const size_t N = (size_t)1 << logn;
   const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
   if (idx >= (size_t)npoly * N) return;
   const Conv& cv = *cvp;
   const size_t poly = idx >> logn, k = idx & (N - 1);
   const int nd = cv.nd;
-  const double* src = in + poly * NS * N + k;
   double* dst = out + poly * (NS + nd) * N + k;
+  // in place: the Q limbs are already the first NS limbs of each output polynomial
+  const double* src = in_place ? dst : in + poly * NS * N + k;
   double x[NS], v[NS];
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
     x[i] = src[i * N];
-    dst[i * N] = x[i];
+    if (!in_place) dst[i * N] = x[i];
   }
   garner<NS>(x, v, cv, mods);
   const bool neg = above_half<NS>(v, NS, cv, mods);
@@ -662,8 +664,12 @@ void delta_consts(const Context& c, int level, double* qmodt_out, double* neg) {
 }  // namespace
 
 void mac(const Context& c, const MacPlan& p, const double* in, double* out, int level, hipStream_t s, int requests,
-         size_t in_req, size_t out_req, const double* delta_msg) {
+         size_t in_req, size_t out_req, const double* delta_msg, size_t out_ct, size_t out_part) {
   const int words = 2 * level * c.n;
+  if (out_ct == 0) {
+    out_ct = (size_t)words;
+    out_part = (size_t)level * c.n;
+  }
   if (p.n_out == 0 || requests == 0) return;
   DeltaAdd da;
   if (delta_msg) {
@@ -681,10 +687,11 @@ void mac(const Context& c, const MacPlan& p, const double* in, double* out, int 
   case TO:                                                                                                \
     if (p.centre)                                                                                         \
       hipLaunchKernelGGL((k_mac<TO, true>), grid, dim3(TPB), 0, s, in, out, words, c.logn, level, p.W, p.rows, \
-                         p.tile_ptr, p.tile_cols, p.chunk, b, c.tab.mods, in_req, out_req, da);             \
+                         p.tile_ptr, p.tile_cols, p.chunk, b, c.tab.mods, in_req, out_req, out_ct, out_part, da); \
     else                                                                                                  \
       hipLaunchKernelGGL((k_mac<TO, false>), grid, dim3(TPB), 0, s, in, out, words, c.logn, level, p.W,    \
-                         p.rows, p.tile_ptr, p.tile_cols, p.chunk, b, c.tab.mods, in_req, out_req, da);     \
+                         p.rows, p.tile_ptr, p.tile_cols, p.chunk, b, c.tab.mods, in_req, out_req, out_ct,   \
+                         out_part, da);                                                                       \
     break;
     BCN_MAC_CASE(1) BCN_MAC_CASE(2) BCN_MAC_CASE(4) BCN_MAC_CASE(8) BCN_MAC_CASE(16) BCN_MAC_CASE(32)
     BCN_MAC_CASE(64)
@@ -738,9 +745,11 @@ void extend_qb(const Context& c, const double* in, double* out, int n, int level
   for (int i = 0; i < c.m; ++i) dst.push_back(c.idB(i));
   const Conv* cv = conv_device(c, "ext" + std::to_string(level), make_conv(c, src, dst));
   const int npoly = 2 * n;
-  ProfScope ps(c, "extend_qb", s, 8.0 * npoly * (double)c.n * (2 * level + c.m));
+  const int in_place = in == out ? 1 : 0;
+  // in place only the B limbs are written
+  ProfScope ps(c, "extend_qb", s, 8.0 * npoly * (double)c.n * (in_place ? level + c.m : 2 * level + c.m));
 #define BCN_EXT(NS) hipLaunchKernelGGL(k_extend_qb<NS>, dim3(nblocks((size_t)npoly * c.n)), dim3(TPB), 0, s, in, out, \
-                                       npoly, c.logn, cv, c.tab.mods)
+                                       npoly, c.logn, in_place, cv, c.tab.mods)
   BCN_DISPATCH_NS(level, BCN_EXT)
 #undef BCN_EXT
   BCN_HIP(hipGetLastError());

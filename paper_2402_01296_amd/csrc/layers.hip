@@ -174,7 +174,11 @@ void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, doub
   const int nin = R * L.n_in, nout = R * L.n_out;
   if (L.features && !features) throw Error(-1, "layer expects features");
   const bool direct = !L.square && !L.features && L.span == 0 && L.packing == BCN_PACK_BATCH;
-  double* A = direct ? out : ar.take((size_t)nout * ctw);
+  // a slot-batched square layer's MAC writes straight into the Q limbs of the square's
+  // Q+B input, so the extension to Q+B only adds the B limbs
+  const bool qb = L.packing == BCN_PACK_BATCH && L.square;
+  const size_t ctq = (size_t)2 * (level + c.m) * N;
+  double* A = direct ? out : ar.take((size_t)nout * (qb ? ctq : ctw));
   if (L.packing == BCN_PACK_BATCH) {
     // slot batching: the features are quantised straight into the transform domain of R_t,
     // encoded (inverse transform mod t) and added by the MAC's own stores
@@ -187,7 +191,10 @@ void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, doub
       bt.id[0] = c.id_t;
       ntt_inverse(c, fm, nout, bt, s);
     }
-    mac(c, L.mac, in, A, level, s, R, (size_t)L.n_in * ctw, (size_t)L.n_out * ctw, fm);
+    if (qb)
+      mac(c, L.mac, in, A, level, s, R, (size_t)L.n_in * ctw, (size_t)L.n_out * ctq, fm, ctq, ctq / 2);
+    else
+      mac(c, L.mac, in, A, level, s, R, (size_t)L.n_in * ctw, (size_t)L.n_out * ctw, fm);
   } else if (L.kind == BCN_CONV2D) {
     // taps [R*n_in][k2]: tap 0 = the input, taps 1.. = hoisted rotations
     double* taps = ar.take((size_t)nin * L.k2 * ctw);
@@ -225,7 +232,9 @@ void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, doub
     }
     return;
   }
-  if (L.square) {
+  if (qb) {
+    square_relin_qb(c, ek, A, out, nout, level, L.modsw, s);
+  } else if (L.square) {
     square_relin(c, ek, A, out, nout, level, L.modsw, s);
   } else {
     copy_rows(A, 0, out, 0, (size_t)nout * ctw, 1, s);

@@ -229,17 +229,14 @@ void decrypt(Context& c, const SecretKey& sk, const double* ct, int n, int level
   BCN_HIP(hipStreamSynchronize(s));
 }
 
-void square_relin(Context& c, const EvalKeys& ek, const double* in, double* out, int n, int level, bool modsw,
-                  hipStream_t s) {
-  if (!ek.relin) throw Error(-3, "missing relinearisation key");
-  if (modsw && level < 2) throw Error(-2, "modulus switch needs two primes");
-  if (n == 0) return;
+namespace {
+// square + relinearisation from X [n][2][level+m][N] whose B limbs extend_qb has filled
+void square_relin_tail(Context& c, const EvalKeys& ek, double* X, double* out, int n, int level, bool modsw,
+                       hipStream_t s) {
   Arena& ar = *c.arena;
   const size_t N = c.n;
   const Basis qb = c.basis_QB(level), qp = c.basis_QP(level);
   const int nb = qb.n, nbp = qp.n, dn = c.dnum(level);
-  double* X = ar.take((size_t)n * 2 * nb * N);
-  extend_qb(c, in, X, n, level, s);
   double* Y = ar.take((size_t)n * 3 * nb * N);
   if (c.fuse_square) {
     square_transform_fused(c, X, Y, n, qb, s);
@@ -275,6 +272,26 @@ void square_relin(Context& c, const EvalKeys& ek, const double* in, double* out,
   } else {
     moddown(c, U, n, level, Z, 1, (size_t)3 * level * N, 1, ks, modsw, out, s);
   }
+}
+}  // namespace
+
+void square_relin(Context& c, const EvalKeys& ek, const double* in, double* out, int n, int level, bool modsw,
+                  hipStream_t s) {
+  if (!ek.relin) throw Error(-3, "missing relinearisation key");
+  if (modsw && level < 2) throw Error(-2, "modulus switch needs two primes");
+  if (n == 0) return;
+  double* X = c.arena->take((size_t)n * 2 * (level + c.m) * c.n);
+  extend_qb(c, in, X, n, level, s);
+  square_relin_tail(c, ek, X, out, n, level, modsw, s);
+}
+
+void square_relin_qb(Context& c, const EvalKeys& ek, double* x, double* out, int n, int level, bool modsw,
+                     hipStream_t s) {
+  if (!ek.relin) throw Error(-3, "missing relinearisation key");
+  if (modsw && level < 2) throw Error(-2, "modulus switch needs two primes");
+  if (n == 0) return;
+  extend_qb(c, x, x, n, level, s);
+  square_relin_tail(c, ek, x, out, n, level, modsw, s);
 }
 
 void rotate_hoisted(Context& c, EvalKeys& ek, const double* in, int n_in, int level, const std::vector<int>& steps,
