@@ -24,6 +24,30 @@ float time_ms(hipStream_t s, int reps, const std::function<void()>& f) {
   BCN_HIP(hipEventDestroy(b));
   return ms / reps;
 }
+
+// Mean time of f with the caches cold, as in a step whose inputs were written long before:
+// before every repetition a fill of `flush` (larger than the L2s and the last-level cache)
+// evicts them.
+float time_ms_cold(hipStream_t s, int reps, double* flush, size_t flush_doubles, const std::function<void()>& f) {
+  hipEvent_t a, b;
+  BCN_HIP(hipEventCreate(&a));
+  BCN_HIP(hipEventCreate(&b));
+  f();  // warm-up
+  float total = 0;
+  for (int i = 0; i < reps; ++i) {
+    fill(flush, flush_doubles, (double)i, s);
+    BCN_HIP(hipEventRecord(a, s));
+    f();
+    BCN_HIP(hipEventRecord(b, s));
+    BCN_HIP(hipEventSynchronize(b));
+    float ms = 0;
+    BCN_HIP(hipEventElapsedTime(&ms, a, b));
+    total += ms;
+  }
+  BCN_HIP(hipEventDestroy(a));
+  BCN_HIP(hipEventDestroy(b));
+  return total / reps;
+}
 }  // namespace
 
 std::string autotune_ntt(Context& c, hipStream_t s) {
@@ -219,6 +243,9 @@ std::string autotune_layer_mac(Context& c, Layer& L, hipStream_t s) {
   double* in = c.arena->take((size_t)n_in_mac * ctw);
   double* out = c.arena->take((size_t)L.mac.n_out * ctw);
   BCN_HIP(hipMemsetAsync(in, 0, (size_t)n_in_mac * ctw * sizeof(double), s));
+  // the MAC streams inputs another kernel wrote long before, so candidates are timed cold
+  constexpr size_t kFlush = (size_t)1 << 26;   // 512 MiB, twice the last-level cache
+  double* flush = c.arena->take(kFlush);
   std::string report;
   float best_ms = 1e30f;
   int best_tile = L.mac.tile;
@@ -228,7 +255,7 @@ std::string autotune_layer_mac(Context& c, Layer& L, hipStream_t s) {
     MacPlan p = make_mac_plan(c, L.mac_weights, L.mac.n_out, n_in_mac, L.mac_order, tile);
     float ms = 0;
     try {
-      ms = time_ms(s, 5, [&] { mac(c, p, in, out, L.level, s); });
+      ms = time_ms_cold(s, 5, flush, kFlush, [&] { mac(c, p, in, out, L.level, s); });
     } catch (...) {
       free_mac_plan(p);
       throw;
