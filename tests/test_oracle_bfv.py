@@ -222,3 +222,185 @@ def test_budget_zero_means_failure():
     want = v * v % prm.t
     assert c.budget(sq, want) <= 0
     assert not (c.dec(sq) == want).all()
+
+
+# ---------------------------------------------------------------- bit-level known answers
+#
+# The decryption identities above cannot see a +-1 slip in a rounding or a
+# different (but still valid) choice of digit representative: every such
+# variant still decrypts correctly.  The tests below recompute the exact
+# outputs from the definitions alone (appendix "CKKS Scheme": Mult(c1,c2) and
+# Rot(c,r), whose key switch is
+#     D_j = centred [x]_{Q_j},  u = sum_j D_j * key_j over Z[X]/(X^N+1),
+#     KS = nearest integer to u / P, reduced mod Q_l;
+# and Mult(c,u) multiplies by the centred lift of u mod t), with schoolbook
+# products and Fraction rounding, never through the oracle's own helpers.
+
+def _centred(x, m):
+    r = x % m
+    return r - m if 2 * r > m else r
+
+
+def _schoolbook(a, b):
+    n = len(a)
+    c = [0] * n
+    for i in range(n):
+        for j in range(n):
+            if i + j < n:
+                c[i + j] += a[i] * b[j]
+            else:
+                c[i + j - n] -= a[i] * b[j]
+    return c
+
+
+def _nearest(num, den):
+    return math.floor(Fraction(num, den) + Fraction(1, 2))
+
+
+def _ks_by_definition(prm, x, key, level):
+    Q = 1
+    for q in prm.q[:level]:
+        Q *= q
+    P = 1
+    for p in prm.p:
+        P *= p
+    out = []
+    for part in (0, 1):
+        u = [0] * prm.n
+        ndig = -(-level // prm.alpha)
+        for j in range(ndig):
+            Qj = 1
+            for q in prm.q[j * prm.alpha:min((j + 1) * prm.alpha, level)]:
+                Qj *= q
+            D = [_centred(v, Qj) for v in x]
+            k = [v % (Q * P) for v in key.parts[j][part]]
+            u = [a + b for a, b in zip(u, _schoolbook(D, k))]
+        out.append([_nearest(v, P) % Q for v in u])
+    return out
+
+
+def _tiny_key(prm, seed):
+    rng = np.random.default_rng(seed)
+    QP = prm.Q(prm.L) * prm.P
+    parts = []
+    for _ in range(prm.dnum(prm.L)):
+        parts.append(([int(v) for v in rng.integers(0, 2 ** 62, prm.n)],
+                      [int(v) for v in rng.integers(0, 2 ** 62, prm.n)]))
+    # spread the key words over all of [0, QP)
+    parts = [([(v * 0x9E3779B97F4A7C15 + 12345) % QP for v in b], [(v * 0xC2B2AE3D27D4EB4F + 777) % QP for v in a])
+             for b, a in parts]
+    return bfv.KSKey(parts)
+
+
+KS_SHAPES = [
+    # (L, K, alpha, level): one-prime digits; two special primes; alpha = 2 with a
+    # full and with a partial (one prime left) last digit
+    (2, 1, 1, 2),
+    (3, 2, 1, 3),
+    (4, 1, 2, 4),
+    (3, 2, 2, 3),
+    (3, 2, 2, 2),
+]
+
+
+@pytest.mark.parametrize("L,K,alpha,level", KS_SHAPES)
+def test_key_switch_known_answer(L, K, alpha, level):
+    prm = params.make("ks%d%d%d" % (L, K, alpha), 8, 30, L, K, alpha, 17, insecure=True)
+    key = _tiny_key(prm, 100 + L * 10 + K)
+    rng = np.random.default_rng(7 + level)
+    Q = prm.Q(level)
+    x = [int(v) % Q for v in rng.integers(0, 2 ** 62, 8) * 0x9E3779B9]
+    x = [(v * 0xD6E8FEB86659FD93 + 99) % Q for v in x]
+    got = bfv.key_switch(prm, x, key, level)
+    want = _ks_by_definition(prm, x, key, level)
+    assert list(got[0]) == want[0] and list(got[1]) == want[1]
+    # the rounding is visible: floor(u/P) differs from round(u/P) somewhere
+    u_floor_differs = False
+    P = prm.P
+    for part in (0, 1):
+        u = [0] * 8
+        for j in range(prm.dnum(level)):
+            Qj = 1
+            for q in prm.digit_primes(j, level):
+                Qj *= q
+            D = [_centred(v, Qj) for v in x]
+            u = [a + b for a, b in zip(u, _schoolbook(D, [v % (Q * P) for v in key.parts[j][part]]))]
+        u_floor_differs |= any((v // P) % Q != _nearest(v, P) % Q for v in u)
+    assert u_floor_differs
+
+
+def test_key_switch_digits_are_centred():
+    # the same switch with digits taken in [0, Q_j) gives a different result:
+    # the known answer above fixes the representative
+    prm = params.make("ks212", 8, 30, 2, 1, 1, 17, insecure=True)
+    key = _tiny_key(prm, 5)
+    Q = prm.Q(2)
+    x = [(i * 0x1F123BB5 + 3) * 0x9E3779B97F4A7C15 % Q for i in range(8)]
+    got = bfv.key_switch(prm, x, key, 2)
+    P = prm.P
+    alt = []
+    for part in (0, 1):
+        u = [0] * 8
+        for j in range(2):
+            qj = prm.q[j]
+            D = [v % qj for v in x]
+            u = [a + b for a, b in zip(u, _schoolbook(D, [v % (Q * P) for v in key.parts[j][part]]))]
+        alt.append([_nearest(v, P) % Q for v in u])
+    assert list(got[0]) != alt[0] or list(got[1]) != alt[1]
+
+
+def test_rotation_known_answer():
+    # Rot(c, r) = (sigma_k c0 + KS(sigma_k c1)_0, KS(sigma_k c1)_1), k = 3^r mod 2N,
+    # sigma_k(X^i) = (-1)^floor(ik/N) X^(ik mod N); one rotation alone and hoisted
+    prm = params.make("rot", 8, 30, 3, 2, 2, 17, insecure=True)
+    key = _tiny_key(prm, 31)
+    Q = prm.Q(3)
+    c0 = [(i * 0x2545F4914F6CDD1D + 17) % Q for i in range(8)]
+    c1 = [(i * 0x9E3779B97F4A7C15 + 5) % Q for i in range(8)]
+    ct = bfv.Ct(c0, c1, 3)
+    r = 1
+    k = pow(3, r, 16)
+
+    def sigma(a):
+        out = [0] * 8
+        for i, v in enumerate(a):
+            e = i * k
+            sign = -1 if (e // 8) % 2 else 1
+            out[e % 8] += sign * v
+        return out
+
+    s0, s1 = sigma(c0), sigma(c1)
+    ks = _ks_by_definition(prm, [v % Q for v in s1], key, 3)
+    want0 = [(a + b) % Q for a, b in zip(s0, ks[0])]
+    want1 = ks[1]
+    for got in (bfv.rotate(prm, ct, r, key), bfv.rotate_hoisted(prm, ct, [r], [key])[0]):
+        assert list(got.c0) == want0 and list(got.c1) == want1
+
+
+def test_mul_plain_known_answer():
+    # Mult(c, u) multiplies by the centred lift of u mod t: a plaintext coefficient
+    # m > t/2 acts as the negative integer m - t (not as m)
+    prm = params.make("pm", 8, 30, 2, 1, 1, 17, insecure=True)
+    Q, t = prm.Q(2), prm.t
+    c0 = [(i * 0x2545F4914F6CDD1D + 1) % Q for i in range(8)]
+    c1 = [(i * 0x9E3779B97F4A7C15 + 2) % Q for i in range(8)]
+    m = [16, 0, 9, 3, 8, 12, 1, 15]          # 16, 9, 12, 15 > t/2
+    got = bfv.mul_plain(prm, bfv.Ct(c0, c1, 2), m)
+    lifted = [v - t if 2 * v > t else v for v in m]
+    assert lifted[0] == -1 and lifted[2] == -8
+    assert list(got.c0) == [v % Q for v in _schoolbook(c0, lifted)]
+    assert list(got.c1) == [v % Q for v in _schoolbook(c1, lifted)]
+    uncentred = [v % Q for v in _schoolbook(c0, m)]
+    assert list(got.c0) != uncentred
+
+
+def test_modswitch_known_answer_every_coefficient():
+    # c' = nearest integer to c / q_l, mod Q_{l-1}, on every coefficient of both parts
+    prm = params.make("ms", 8, 30, 3, 1, 1, 17, insecure=True)
+    Q = prm.Q(3)
+    c0 = [(i * 0x2545F4914F6CDD1D + 11) % Q for i in range(8)]
+    c1 = [(i * 0x9E3779B97F4A7C15 + 13) % Q for i in range(8)]
+    got = bfv.modswitch(prm, bfv.Ct(c0, c1, 3))
+    ql, Qn = prm.q[2], prm.Q(2)
+    assert list(got.c0) == [_nearest(v, ql) % Qn for v in c0]
+    assert list(got.c1) == [_nearest(v, ql) % Qn for v in c1]
