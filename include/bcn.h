@@ -205,9 +205,10 @@ int bcn_layer_eval(bcn_context* ctx, const bcn_eval_keys* ek, const bcn_layer* l
 /* The same layer over n_requests independent requests in one set of launches:
  * in [n_requests][n_in][2][level][N], out [n_requests][n_out][2][level_out][N],
  * features [n_requests][...] in the per-request layout above.  Request r's
- * results are bit-identical to evaluating it alone.  Issues no host
- * synchronisation, allocation (after a first call of the same shape) or
- * memset, so it can be captured into a hipGraph. */
+ * results are bit-identical to evaluating it alone.  From the second call of
+ * a shape on it issues no host synchronisation, allocation or memset, so it
+ * can then be captured into a hipGraph (the first call may grow the context's
+ * scratch arena, the second consolidates it into one block). */
 int bcn_layer_eval_batch(bcn_context* ctx, const bcn_eval_keys* ek, const bcn_layer* layer, const double* in,
                          double* out, const float* features, int n_requests, bcn_stream stream);
 
@@ -234,6 +235,21 @@ int bcn_profile_enable(bcn_context* ctx, int on);
  * entries).  Returns the number of names, or an error code. */
 int bcn_profile_read(bcn_context* ctx, char* names, int names_cap, int* launches, double* total_ms, double* bytes,
                      double* ops, int cap);
+
+/* ---- scratch arena ----
+ * Each context owns a grow-only device scratch arena used by every call.  When
+ * a call outgrows it, the next call moves to one larger block; the blocks it
+ * replaces are retired, not freed, because a hipGraph captured earlier may
+ * still use them.  Retired blocks are freed only by bcn_scratch_release or
+ * bcn_context_destroy. */
+/* Current block's device address, a counter that changes whenever the block
+ * changes, its size, the largest scratch a call has used, and the bytes held by
+ * retired blocks.  Any output pointer may be NULL. */
+int bcn_scratch_info(bcn_context* ctx, uint64_t* base, uint64_t* generation, size_t* bytes, size_t* high_bytes,
+                     size_t* retired_bytes);
+/* Frees the retired blocks (synchronises the device first).  The caller must
+ * hold no captured graph that was recorded before the last block change. */
+int bcn_scratch_release(bcn_context* ctx);
 
 #ifdef __cplusplus
 }

@@ -77,6 +77,8 @@ _SIGS = {
     "bcn_autotune": (_I, [_VP, C.c_char_p, _I, _VP]),
     "bcn_layer_autotune": (_I, [_VP, _VP, C.c_char_p, _I, _VP]),
     "bcn_profile_read": (_I, [_VP, C.c_char_p, _I, _VP, _VP, _VP, _VP, _I]),
+    "bcn_scratch_info": (_I, [_VP, _VP, _VP, _VP, _VP, _VP]),
+    "bcn_scratch_release": (_I, [_VP]),
 }
 
 
@@ -293,6 +295,19 @@ class Context:
             _check(cnt)
         keys = names.value.decode().split("\n")[:cnt]
         return {k: (int(la[i]), float(ms[i]), float(by[i]), float(op[i])) for i, k in enumerate(keys)}
+
+
+    # ------------------------------------------------------------ scratch arena
+    def scratch_info(self):
+        """{base, generation, bytes, high_bytes, retired_bytes} of the context's scratch arena."""
+        base, gen = C.c_uint64(), C.c_uint64()
+        by, hi, ret = C.c_size_t(), C.c_size_t(), C.c_size_t()
+        _check(lib().bcn_scratch_info(self.h, C.byref(base), C.byref(gen), C.byref(by), C.byref(hi), C.byref(ret)))
+        return {"base": base.value, "generation": gen.value, "bytes": by.value, "high_bytes": hi.value,
+                "retired_bytes": ret.value}
+
+    def scratch_release(self):
+        _check(lib().bcn_scratch_release(self.h))
 
 
 class SecretKey:

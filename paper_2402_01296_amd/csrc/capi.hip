@@ -499,4 +499,25 @@ int bcn_layer_eval_batch(bcn_context* ctx, const bcn_eval_keys* ek, const bcn_la
   });
 }
 
+int bcn_scratch_info(bcn_context* ctx, uint64_t* base, uint64_t* generation, size_t* bytes, size_t* high_bytes,
+                     size_t* retired_bytes) {
+  return guard([&] {
+    if (!ctx || !ctx->c) throw bcn::Error(BCN_ERR_INVALID, "null context");
+    const bcn::Arena& a = *ctx->c->arena;
+    if (base) *base = (uint64_t)(uintptr_t)a.base();
+    if (generation) *generation = a.generation();
+    if (bytes) *bytes = a.capacity();
+    if (high_bytes) *high_bytes = a.high_bytes();
+    if (retired_bytes) *retired_bytes = a.retired_bytes();
+  });
+}
+
+int bcn_scratch_release(bcn_context* ctx) {
+  return guard([&] {
+    if (!ctx || !ctx->c) throw bcn::Error(BCN_ERR_INVALID, "null context");
+    BCN_HIP(hipSetDevice(ctx->c->device));
+    ctx->c->arena->release_retired();
+  });
+}
+
 }  // extern "C"

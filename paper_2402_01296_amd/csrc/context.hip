@@ -12,24 +12,56 @@ namespace bcn {
 
 Arena::~Arena() {
   for (auto& ch : chunks_) (void)hipFree(ch.p);
+  for (auto& ch : retired_) (void)hipFree(ch.p);
 }
 
 size_t Arena::capacity() const {
   size_t c = 0;
   for (auto& ch : chunks_) c += ch.cap;
-  return c;
+  return c * sizeof(double);
+}
+
+size_t Arena::retired_bytes() const {
+  size_t c = 0;
+  for (auto& ch : retired_) c += ch.cap;
+  return c * sizeof(double);
+}
+
+size_t Arena::release_retired() {
+  const size_t b = retired_bytes();
+  if (retired_.empty()) return 0;
+  BCN_HIP(hipDeviceSynchronize());
+  for (auto& ch : retired_) BCN_HIP(hipFree(ch.p));
+  retired_.clear();
+  return b;
+}
+
+void Arena::bind_external(double* base, size_t cap) {
+  ext_ = base;
+  ext_cap_ = cap;
+  ext_off_ = 0;
+}
+
+void Arena::unbind_external() {
+  ext_ = nullptr;
+  ext_cap_ = ext_off_ = 0;
 }
 
 void Arena::reset() {
+  if (ext_) {
+    ext_off_ = 0;
+    return;
+  }
   if (chunks_.size() > 1) {
-    // consolidate: wait for in-flight users, then keep one chunk of the high-water size
-    BCN_HIP(hipDeviceSynchronize());
-    for (auto& ch : chunks_) BCN_HIP(hipFree(ch.p));
-    chunks_.clear();
+    // consolidate into one chunk of the high-water size; the old chunks are retired, not
+    // freed, because work in flight or a captured graph may still use them
     double* p = nullptr;
     const size_t cap = high_ + high_ / 4;
     if (hipMalloc(&p, cap * sizeof(double)) != hipSuccess) throw Error(-4, "device out of memory for scratch");
+    for (auto& ch : chunks_) retired_.push_back(ch);
+    chunks_.clear();
     chunks_.push_back({p, cap});
+    ++generation_;
   }
   cur_ = 0;
   off_ = 0;
@@ -37,7 +69,15 @@ void Arena::reset() {
 }
 
 double* Arena::take(size_t doubles) {
-  doubles = (doubles + 31) & ~(size_t)31;   // 256-byte alignment
+  doubles = rounded(doubles);   // 256-byte alignment
+  if (ext_) {
+    if (ext_off_ + doubles > ext_cap_)
+      throw Error(-1, "request exceeds the fixed scratch buffer (" + std::to_string(ext_cap_ * sizeof(double)) +
+                          " bytes)");
+    double* p = ext_ + ext_off_;
+    ext_off_ += doubles;
+    return p;
+  }
   while (cur_ < chunks_.size() && off_ + doubles > chunks_[cur_].cap) {
     ++cur_;
     off_ = 0;
@@ -47,6 +87,7 @@ double* Arena::take(size_t doubles) {
     double* p = nullptr;
     if (hipMalloc(&p, cap * sizeof(double)) != hipSuccess) throw Error(-4, "device out of memory for scratch");
     chunks_.push_back({p, cap});
+    if (chunks_.size() == 1) ++generation_;
     off_ = 0;
   }
   double* p = chunks_[cur_].p + off_;
@@ -141,6 +182,7 @@ const Conv* conv_device(const Context& c, const std::string& key, const Conv& cv
   std::lock_guard<std::mutex> lk(g_conv_mu);
   auto it = g_convs.find({&c, key});
   if (it != g_convs.end()) return it->second;
+  if (c.no_alloc) throw Error(-6, "conversion table " + key + " was not prepared at context creation");
   Conv* d = nullptr;
   BCN_HIP(hipMalloc(&d, sizeof(Conv)));
   BCN_HIP(hipMemcpy(d, &cv, sizeof(Conv), hipMemcpyHostToDevice));
@@ -311,6 +353,8 @@ Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uin
     c->persist_blocks = prop.multiProcessorCount * per_cu;
   }
   ntt_setup(*c);
+  preload_conversions(*c);
+  preload_ks_digits(*c);
   return c.release();
 }
 

@@ -79,20 +79,38 @@ struct Error : std::runtime_error {
 // Grow-only device scratch arena owned by a context.  take() hands out
 // stream-ordered scratch that stays valid until the next reset(); reset() is
 // called at the start of every public entry point.  When a call needed more
-// than one chunk, the next reset() synchronises the device and replaces the
-// chunks by one chunk of the high-water size, so steady state is one
-// allocation and no hipMalloc on the hot path.
+// than one chunk, the next reset() replaces them by one chunk of 1.25x the
+// high-water size, so from the second call of a shape on there is one chunk
+// and no hipMalloc on the hot path.  The replaced chunks are not freed: a
+// hipGraph captured earlier may still read and write them.  They stay
+// allocated (retired) until release_retired() or the arena's destruction.
+//
+// While bound to caller memory (bind_external), take() bumps through that
+// buffer only and throws when it is exhausted: no allocation of any kind.
 class Arena {
  public:
   ~Arena();
   double* take(size_t doubles);
   void reset();
   size_t capacity() const;
+  size_t high_bytes() const { return high_ * sizeof(double); }
+  size_t retired_bytes() const;
+  // frees the retired chunks; the caller guarantees no pending work or graph uses them
+  size_t release_retired();
+  const double* base() const { return chunks_.empty() ? nullptr : chunks_[0].p; }
+  uint64_t generation() const { return generation_; }
+  void bind_external(double* base, size_t cap);
+  void unbind_external();
+  // doubles that take(d_1), ..., take(d_k) consume from an empty arena
+  static size_t rounded(size_t doubles) { return (doubles + 31) & ~(size_t)31; }
 
  private:
   struct Chunk { double* p; size_t cap; };
-  std::vector<Chunk> chunks_;
+  std::vector<Chunk> chunks_, retired_;
   size_t cur_ = 0, off_ = 0, used_total_ = 0, high_ = 0;
+  uint64_t generation_ = 0;
+  double* ext_ = nullptr;
+  size_t ext_cap_ = 0, ext_off_ = 0;
 };
 
 // Optional per-kernel timing: hipEvents recorded around launches on the
@@ -122,6 +140,9 @@ struct Context {
   uint32_t* d_slot_pos = nullptr;        // [N] position of slot s in the transform of R_t
   uint32_t* d_slot_of_word = nullptr;    // [N] inverse of d_slot_pos: the slot held at each word
   std::unique_ptr<Arena> arena;
+  mutable bool no_alloc = false;         // set while an entry point that must not allocate runs
+  double* fixed_scratch = nullptr;       // this device's static scratch array (device address)
+  size_t fixed_scratch_doubles = 0;
 
   int ntt_loge = 0;                      // registers per thread = 2^ntt_loge in the transform
   int square_loge = 0;                   // the same for the fused square's transforms
@@ -195,6 +216,11 @@ struct Conv {
 };
 
 Conv make_conv(const Context& c, const std::vector<int>& src, const std::vector<int>& dst);
+// device copy of a conversion table, cached per (context, key); allocates on a miss
+const Conv* conv_device(const Context& c, const std::string& key, const Conv& cv);
+// fill that cache for every level at context creation (kernels.hip, ntt.hip)
+void preload_conversions(const Context& c);
+void preload_ks_digits(const Context& c);
 
 // ---- element kernels (kernels.hip); all buffers are limb-major [..][limb][N]
 // out[o] = sum_j W[o][j] * in[j]; W dense f64 [n_out][n_in] (device),

@@ -736,14 +736,16 @@ void tensor_square(const Context& c, const double* in, double* out, int n, const
   BCN_HIP(hipGetLastError());
 }
 
-const Conv* conv_device(const Context& c, const std::string& key, const Conv& cv);
-
-void extend_qb(const Context& c, const double* in, double* out, int n, int level, hipStream_t s) {
-  if (n == 0) return;
+static const Conv* extend_conv(const Context& c, int level) {
   std::vector<int> src, dst;
   for (int i = 0; i < level; ++i) src.push_back(c.idQ(i));
   for (int i = 0; i < c.m; ++i) dst.push_back(c.idB(i));
-  const Conv* cv = conv_device(c, "ext" + std::to_string(level), make_conv(c, src, dst));
+  return conv_device(c, "ext" + std::to_string(level), make_conv(c, src, dst));
+}
+
+void extend_qb(const Context& c, const double* in, double* out, int n, int level, hipStream_t s) {
+  if (n == 0) return;
+  const Conv* cv = extend_conv(c, level);
   const int npoly = 2 * n;
   const int in_place = in == out ? 1 : 0;
   // in place only the B limbs are written
@@ -785,6 +787,21 @@ void scale_round(const Context& c, const double* in, double* out, int n, int lev
   BCN_HIP(hipGetLastError());
 }
 
+// digit j of level `level` raised to Q_level + P
+static const Conv* modup_conv(const Context& c, int level, int j) {
+  const Basis dstb = c.basis_QP(level);
+  const int lo = j * c.alpha, hi = std::min((j + 1) * c.alpha, level);
+  std::vector<int> src, dst;
+  for (int i = lo; i < hi; ++i) src.push_back(c.idQ(i));
+  for (int i = 0; i < dstb.n; ++i) dst.push_back(dstb.id[i]);
+  Conv cv = make_conv(c, src, dst);
+  for (int d = 0; d < dstb.n; ++d) {
+    cv.aux[d] = (d >= lo && d < hi) ? 1.0 : 0.0;
+    cv.aux2[d] = (d >= lo && d < hi) ? (double)(d - lo) : 0.0;
+  }
+  return conv_device(c, "mu" + std::to_string(level) + "_" + std::to_string(j), cv);
+}
+
 void decompose_modup(const Context& c, const double* in, size_t in_stride, double* out, int n, int level,
                      hipStream_t s) {
   if (n == 0) return;
@@ -793,15 +810,7 @@ void decompose_modup(const Context& c, const double* in, size_t in_stride, doubl
   ProfScope ps(c, "modup", s, 8.0 * n * (double)c.n * (level + dnum * dstb.n));
   for (int j = 0; j < dnum; ++j) {
     const int lo = j * c.alpha, hi = std::min((j + 1) * c.alpha, level);
-    std::vector<int> src, dst;
-    for (int i = lo; i < hi; ++i) src.push_back(c.idQ(i));
-    for (int i = 0; i < dstb.n; ++i) dst.push_back(dstb.id[i]);
-    Conv cv = make_conv(c, src, dst);
-    for (int d = 0; d < dstb.n; ++d) {
-      cv.aux[d] = (d >= lo && d < hi) ? 1.0 : 0.0;
-      cv.aux2[d] = (d >= lo && d < hi) ? (double)(d - lo) : 0.0;
-    }
-    const Conv* dcv = conv_device(c, "mu" + std::to_string(level) + "_" + std::to_string(j), cv);
+    const Conv* dcv = modup_conv(c, level, j);
     const int ns = hi - lo;
 #define BCN_MU(NS) hipLaunchKernelGGL(k_modup<NS>, dim3(nblocks((size_t)n * c.n)), dim3(TPB), 0, s, in, in_stride, out, \
                                       n, c.logn, j, dnum, dcv, c.tab.mods, lo)
@@ -953,11 +962,15 @@ void tdomain_to_slots(const Context& c, const double* in, int64_t* slots, int n,
   BCN_HIP(hipGetLastError());
 }
 
-void dec_round(const Context& c, const double* x, double* m, int n, int level, hipStream_t s) {
-  if (n == 0) return;
+static const Conv* dec_conv(const Context& c, int level) {
   std::vector<int> src;
   for (int i = 0; i < level; ++i) src.push_back(c.idQ(i));
-  const Conv* dcv = conv_device(c, "dec" + std::to_string(level), make_conv(c, src, {}));
+  return conv_device(c, "dec" + std::to_string(level), make_conv(c, src, {}));
+}
+
+void dec_round(const Context& c, const double* x, double* m, int n, int level, hipStream_t s) {
+  if (n == 0) return;
+  const Conv* dcv = dec_conv(c, level);
 #define BCN_DEC(NS) hipLaunchKernelGGL(k_dec_round<NS>, dim3(nblocks((size_t)n * c.n)), dim3(TPB), 0, s, x, m, n, c.logn, \
                                        (double)c.t, dcv, c.tab.mods)
   BCN_DISPATCH_NS(level, BCN_DEC)
@@ -1028,6 +1041,18 @@ void quantise_features(const Context& c, const float* f, int n_pt, int mode, int
   hipLaunchKernelGGL(k_quantise, dim3(nblocks(work)), dim3(TPB), 0, s, f, n_pt, mode, batch, stride_b, slot_of, per,
                      scale, clampv, slots, c.logn);
   BCN_HIP(hipGetLastError());
+}
+
+// Builds every conversion table the library uses at each level up front, so that
+// no later call has to allocate device memory for one.
+void preload_conversions(const Context& c) {
+  for (int level = 1; level <= c.L; ++level) {
+    extend_conv(c, level);
+    scale_round_conv(c, level);
+    moddown_conv(c, level);
+    dec_conv(c, level);
+    for (int j = 0; j < c.dnum(level); ++j) modup_conv(c, level, j);
+  }
 }
 
 }  // namespace bcn

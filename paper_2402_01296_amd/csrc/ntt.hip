@@ -838,8 +838,6 @@ void square_transform_fused(const Context& c, const double* in, double* out, int
   }
 }
 
-const Conv* conv_device(const Context& c, const std::string& key, const Conv& cv);
-
 namespace {
 KsDigits ks_digits(const Context& c, int level, const Basis& qp) {
   if (c.alpha > 2) throw Error(-1, "fused key switching supports digits of at most two primes");
@@ -919,6 +917,12 @@ void ntt_forward(const Context& c, double* data, int n_polys, const Basis& b, hi
 
 void ntt_inverse(const Context& c, double* data, int n_polys, const Basis& b, hipStream_t s) {
   dispatch<true>(c, data, n_polys, b, s);
+}
+
+// Builds the two-prime digit tables of the fused key-switching paths at every level.
+void preload_ks_digits(const Context& c) {
+  if (c.alpha > 2) return;
+  for (int level = 1; level <= c.L; ++level) ks_digits(c, level, c.basis_QP(level));
 }
 
 }  // namespace bcn
