@@ -56,6 +56,10 @@ def parse():
                     help="serving loop: Poisson arrivals at --rates, continuous batching vs unbatched")
     ap.add_argument("--rates", default="50,200,800")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--no-legs", action="store_true",
+                    help="only the headline workload (no CIFAR-shaped, transform or serving legs)")
+    ap.add_argument("--legs-rates", default="200,800", help="Poisson rates of the serving leg")
+    ap.add_argument("--legs-requests", type=int, default=1000, help="requests per rate in the serving leg")
     return ap.parse_args()
 
 
@@ -225,19 +229,62 @@ def serve_bench(args):
     }), flush=True)
 
 
-def cpu_baseline(workload: str):
-    """The oracle on a bounded sample of one step, scaled to inferences/s.
+def _host_cpu():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, avail
 
-    Sample (about 10 s on one core): three conv outputs (each with its feature
-    add, square, relinearisation and modulus switch), three dense-100 outputs
-    with square and modulus switch, all ten dense-10 outputs, on random
-    ciphertexts of the right level.  The step time is each layer's mean time per
-    output times its number of outputs (245, 100, 10).
+
+# oracle state shared with forked workers of the all-core leg (set before the pool forks)
+_ORACLE = {}
+
+
+def _oracle_output(task):
+    """One output ciphertext of one layer of the MNIST-shaped step, computed by the oracle."""
+    from oracle import bfv
+    O, w, feats, cts = _ORACLE["O"], _ORACLE["w"], _ORACLE["feats"], _ORACLE["cts"]
+    prm = O.prm
+    layer, idx = task
+    t0 = time.perf_counter()
+    if layer == 0:
+        c, y, x = idx
+        ct = bfv.mac(prm, cts[0], w[0][c, 0].reshape(-1))
+        ct = bfv.add_plain(prm, ct, O.enc.encode(feats[:, c, y, x]))
+        bfv.modswitch(prm, bfv.square(prm, ct, O.rk))
+    elif layer == 1:
+        ct = bfv.mac(prm, cts[1], w[1][idx])
+        bfv.modswitch(prm, bfv.square(prm, ct, O.rk))
+    else:
+        bfv.mac(prm, cts[2], w[2][idx])
+    return layer, time.perf_counter() - t0
+
+
+def cpu_baseline(workload: str, workers: int):
+    """The oracle on a bounded sample of one step, scaled to inferences/s, on one core and on
+    `workers` cores (a process pool over independent output ciphertexts).
+
+    Sample: output ciphertexts of the three layers (conv outputs with their feature add,
+    square, relinearisation and modulus switch; dense-100 outputs with square and modulus
+    switch; dense-10 outputs) on random ciphertexts of the right level.  The step time is
+    each layer's time per output times its number of outputs (245, 100, 10).  Runs before
+    the GPU is touched, so the pool may fork.
     """
-    import numpy as np
+    import multiprocessing as mp
 
     import synthetic
-    from oracle import bfv, network, programs
+    from oracle import network, programs
+    from oracle import bfv
     from synthetic import workloads as W
 
     assert workload == "cfg2"
@@ -253,48 +300,272 @@ def cpu_baseline(workload: str):
             out.append(bfv.Ct(bfv.from_rns(r0, prm.q[:level]), bfv.from_rns(r1, prm.q[:level]), level))
         return out
 
-    w = O.inputs["weights"]
-    feats = network.quantise(O.inputs["features"][0])
-    # layer 1: three outputs (channel, row, column), 25 taps each, with feature add, square,
-    # relinearisation and modulus switch
-    cts = rand_cts(prm.L, 25, 101)
-    picks = [(0, 3, 3), (2, 0, 5), (4, 6, 1)]
-    t0 = time.perf_counter()
-    for (c, y, x) in picks:
-        ct = bfv.mac(prm, cts, w[0][c, 0].reshape(-1))
-        ct = bfv.add_plain(prm, ct, O.enc.encode(feats[:, c, y, x]))
-        ct = bfv.modswitch(prm, bfv.square(prm, ct, O.rk))
-    t1 = (time.perf_counter() - t0) / len(picks)
-    # layer 2: three of the 100 outputs over 245 inputs at level L-1
-    cts = rand_cts(prm.L - 1, 245, 102)
-    rows2 = (0, 41, 99)
-    t0 = time.perf_counter()
-    for o in rows2:
-        ct = bfv.mac(prm, cts, w[1][o])
-        ct = bfv.modswitch(prm, bfv.square(prm, ct, O.rk))
-    t2 = (time.perf_counter() - t0) / len(rows2)
-    # layer 3: all 10 outputs over 100 inputs at level L-2
-    cts = rand_cts(prm.L - 2, 100, 103)
-    t0 = time.perf_counter()
-    for o in range(10):
-        ct = bfv.mac(prm, cts, w[2][o])
-    t3 = (time.perf_counter() - t0) / 10
+    _ORACLE.update(O=O, w=O.inputs["weights"], feats=network.quantise(O.inputs["features"][0]),
+                   cts=[rand_cts(prm.L, 25, 101), rand_cts(prm.L - 1, 245, 102), rand_cts(prm.L - 2, 100, 103)])
     shapes = W.layer_shapes(workload)
-    n1 = shapes[0][1][0] * shapes[0][1][1] * shapes[0][1][2]
-    n2, n3 = shapes[1][1][0], shapes[2][1][0]
-    step_s = n1 * t1 + n2 * t2 + n3 * t3
+    n_out = [shapes[0][1][0] * shapes[0][1][1] * shapes[0][1][2], shapes[1][1][0], shapes[2][1][0]]
     batch = W.WORKLOADS[workload]["batch"]
-    sampled = len(picks) * t1 + len(rows2) * t2 + 10 * t3
-    return {
-        "value": batch / step_s,
-        "unit": "encrypted inferences/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": "3 + 3 + 10 output ciphertexts of the three layers on random ciphertexts of the right level "
-                  "(%.1f s of oracle work; per output: layer1 %.2fs, layer2 %.2fs, layer3 %.3fs), scaled by the "
-                  "outputs per layer (%d, %d, %d) to one step of %d images: %.0f s/step; wall time incl. setup "
-                  "%.1fs" % (sampled, t1, t2, t3, n1, n2, n3, batch, step_s, time.perf_counter() - t_all),
+    setup_s = time.perf_counter() - t_all
+    # one core: 3 + 3 + 10 outputs
+    single = [(0, (0, 3, 3)), (0, (2, 0, 5)), (0, (4, 6, 1)), (1, 0), (1, 41), (1, 99)] + [(2, o) for o in range(10)]
+    per = {0: [], 1: [], 2: []}
+    for task in single:
+        layer, dt = _oracle_output(task)
+        per[layer].append(dt)
+    t1 = [sum(v) / len(v) for v in (per[0], per[1], per[2])]
+    step1 = sum(n * t for n, t in zip(n_out, t1))
+    sampled1 = sum(sum(v) for v in per.values())
+    out = {
+        "value": batch / step1, "unit": "encrypted inferences/s (images)", "cores": 1, "kind": "oracle",
+        "requests_per_s": 1.0 / step1,
+        "sample": "one core: 3 + 3 + 10 output ciphertexts of the three layers on random ciphertexts of the "
+                  "right level (%.1f s of oracle work; per output: layer1 %.2fs, layer2 %.2fs, layer3 %.3fs), "
+                  "scaled by the outputs per layer (%d, %d, %d) to one step of %d images: %.0f s/step"
+                  % (sampled1, t1[0], t1[1], t1[2], n_out[0], n_out[1], n_out[2], batch, step1),
     }
+    model, ncpu, avail = _host_cpu()
+    out["host"] = {"cpu_model": model, "nproc": ncpu, "cpus_available": avail}
+    if workers > 1:
+        # all cores: `workers` outputs of each of the two big layers and all ten dense-10 outputs,
+        # each layer's tasks run together on the pool; per-output time = wall time / outputs
+        ctx = mp.get_context("fork")
+        tasks = {0: [(0, (k % 5, (k // 5) % 7, (3 * k) % 7)) for k in range(workers)],
+                 1: [(1, (17 * k) % 100) for k in range(workers)],
+                 2: [(2, o) for o in range(10)]}
+        wall = {}
+        with ctx.Pool(workers) as pool:
+            pool.map(_oracle_output, [(2, 0)] * workers)          # start the workers
+            for layer in (0, 1, 2):
+                t0 = time.perf_counter()
+                pool.map(_oracle_output, tasks[layer], chunksize=1)
+                wall[layer] = (time.perf_counter() - t0) / len(tasks[layer])
+        stepw = sum(n * wall[k] for k, n in enumerate(n_out))
+        out["all_cores"] = {
+            "value": batch / stepw, "requests_per_s": 1.0 / stepw, "cores": workers,
+            "sample": "%d worker processes (fork) over %d + %d + 10 independent output ciphertexts; per output "
+                      "wall time: layer1 %.3fs, layer2 %.3fs, layer3 %.4fs; %.0f s/step"
+                      % (workers, workers, workers, wall[0], wall[1], wall[2], stepw)}
+        # the reported baseline is the all-core figure
+        out["single_core"] = {"value": out["value"], "requests_per_s": out["requests_per_s"]}
+        out["value"] = out["all_cores"]["value"]
+        out["requests_per_s"] = out["all_cores"]["requests_per_s"]
+        out["cores"] = workers
+    out["sample"] += "; setup %.1fs, total wall %.1fs" % (setup_s, time.perf_counter() - t_all)
+    _ORACLE.clear()
+    return out
+
+
+def run_workload(name: str, steps: int, warmup: int, autotune: bool = True, graph: bool = False,
+                 verify: bool = True, log_prefix: str = "bench"):
+    """Times `steps` steps (one request each) of a workload's whole ciphertext branch, then an
+    instrumented pass with per-kernel launch timing; returns the measurements."""
+    import torch
+
+    from paper_2402_01296_amd.workload import GpuSession
+    from synthetic import workloads as W
+
+    wl = W.WORKLOADS[name]
+    g = GpuSession(name)
+    tuning = g.autotune() if autotune else None
+    for ln in (tuning or "").splitlines():
+        print("%s: %s autotune %s" % (log_prefix, name, ln), file=sys.stderr, flush=True)
+    ct_in = g.encrypt_inputs()
+    torch.cuda.synchronize()
+    print("%s: %s keys+encryption ready, %d input ciphertexts" % (log_prefix, name, ct_in.shape[0]),
+          file=sys.stderr, flush=True)
+
+    def step():
+        return g.run(ct_in)
+
+    for _ in range(max(2, warmup)):
+        out = step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        eager_out = step()
+    torch.cuda.synchronize()
+    eager_ms = (time.perf_counter() - t0) * 1000.0 / steps
+    graph_ok = None
+    if graph:
+        # the whole step captured once as a hipGraph and replayed, checked against the eager result
+        cg = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(cg):
+            graph_out = step()
+        cg.replay()
+        torch.cuda.synchronize()
+        graph_ok = bool(torch.equal(graph_out, eager_out))
+        if not graph_ok:
+            raise RuntimeError("captured step differs from the eager step")
+
+        def step():  # noqa: F811
+            cg.replay()
+            return graph_out
+        for _ in range(warmup):
+            out = step()
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        starts[i].record()
+        out = step()
+        ends[i].record()
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    lat = sorted(s.elapsed_time(e) for s, e in zip(starts, ends))
+    ms_per_step = total * 1000.0 / steps
+    print("%s: %s timed %d steps, %.3f ms/step" % (log_prefix, name, steps, ms_per_step), file=sys.stderr, flush=True)
+
+    # instrumented eager pass over the same steps: per-kernel launch durations (library hipEvents
+    # around each launch, on the launch stream)
+    g.ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.run(ct_in)
+    torch.cuda.synchronize()
+    inst_ms = (time.perf_counter() - t0) * 1000.0 / steps
+    g.ctx.profile(False)
+    prof = g.ctx.profile_read()
+    kern = {}
+    for k, (la, ms, by, ops) in prof.items():
+        sec = ms * 1e-3
+        kern[k] = dict(launches=la, ms=ms, bytes=by, ops=ops,
+                       gbs=by / sec / 1e9 if sec > 0 else 0.0, tops=ops / sec / 1e12 if sec > 0 else 0.0)
+    dom = max(kern, key=lambda k: kern[k]["ms"])
+    roof = roofline(kern[dom], dom, name)
+    # transform-bearing kernels: the plain transforms and the kernels that run transforms inside
+    tk = [k for k in kern if k.startswith("ntt") or k in ("square_fused", "ks_intt", "ks_fused")]
+    t_bytes = sum(kern[k]["bytes"] for k in tk)
+    t_ms = sum(kern[k]["ms"] for k in tk)
+    verified = None
+    if not wl.get("decrypts", True):
+        verified = "n/a: two 30-bit limbs leave no noise budget after the square, so the output does not decrypt"
+    elif verify:
+        from oracle import network   # test-only check of this run's outputs
+        vals = g.output_values(out)
+        want = network.run_mod_t(name, g.inputs, g.ctx.t)
+        verified = bool((vals == want).all())
+    res = {
+        "workload": WORKLOAD_TEXT.get(name, name), "name": name, "n": g.n, "limbs": g.ctx.L,
+        "images_per_request": wl["batch"], "steps": steps, "ms_per_step": round(ms_per_step, 3),
+        "requests_per_s": round(steps / total, 3), "images_per_s": round(wl["batch"] * steps / total, 1),
+        "step_time_ms": {"p50": round(statistics.median(lat), 3),
+                         "p99": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 3),
+                         "note": "device time of one step (one request) back to back, not a served latency"},
+        "transform_kernels": {"kernels": sorted(tk),
+                              "gbs": round(t_bytes / (t_ms * 1e-3) / 1e9, 1) if t_ms else None,
+                              "frac_of_hbm_peak": round(t_bytes / (t_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if t_ms
+                              else None,
+                              "ms_per_step": round(t_ms / steps, 3)},
+        "roofline": roof,
+        "kernels": {k: {"ms_per_step": round(v["ms"] / steps, 3), "launches": v["launches"],
+                        "gbs": round(v["gbs"], 1), "fp64_tops": round(v["tops"], 3)}
+                    for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])},
+        "instrumented_ms_per_step": round(inst_ms, 3),
+        "timed_as": "hipGraph replay of the whole step" if graph else "eager launches",
+        "eager_ms_per_step": round(eager_ms, 3),
+        "graph_matches_eager": graph_ok,
+        "autotune": [ln for ln in (tuning or "").splitlines() if "chosen" in ln],
+        "verified_vs_integer_network": verified,
+    }
+    del g, ct_in, out, eager_out
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return res
+
+
+def roofline(d: dict, kernel: str, workload: str):
+    """The kernel's bound is the larger of its two floors: algorithmic bytes at the HBM peak and
+    algorithmic FP64 operations at the vector peak; achieved = algorithmic units / launch time."""
+    hbm_floor = d["bytes"] / (HBM_PEAK_GBS * 1e9)
+    alu_floor = d["ops"] / (ALU_PEAK_TOPS * 1e12)
+    la = max(1, d["launches"])
+    if alu_floor > hbm_floor:
+        roof = {"kernel": kernel, "bound": "alu", "achieved": round(d["tops"], 3), "peak": round(ALU_PEAK_TOPS, 3),
+                "unit": "T fp64 op/s", "frac": round(d["tops"] / ALU_PEAK_TOPS, 4)}
+    else:
+        roof = {"kernel": kernel, "bound": "hbm", "achieved": round(d["gbs"], 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(d["gbs"] / HBM_PEAK_GBS, 4)}
+    traffic = measured_traffic(kernel, workload)
+    roof.update({
+        "traffic": traffic["bytes_per_launch"] if traffic else None,
+        "traffic_unit": "bytes per launch (HBM read + write, rocprofv3 counters)",
+        "traffic_over_algorithmic": round(traffic["bytes_per_launch"] / (d["bytes"] / la), 3) if traffic else None,
+        "traffic_profile": traffic["profile"] if traffic else None,
+        "launches": d["launches"],
+        "avg_launch_us": round(d["ms"] * 1000.0 / la, 2),
+        "bytes_per_launch": d["bytes"] / la,
+        "fp64_ops_per_launch": d["ops"] / la,
+        "hbm_gbs": round(d["gbs"], 1),
+        "hbm_frac": round(d["gbs"] / HBM_PEAK_GBS, 4),
+        "alu_frac": round(d["tops"] / ALU_PEAK_TOPS, 4),
+    })
+    return roof
+
+
+def ntt_leg(workload: str, steps: int, autotune: bool = True):
+    """Plain forward + inverse limb transforms on the square's batch shape (HBM GB/s vs peak)."""
+    import torch
+
+    from paper_2402_01296_amd import bcn
+    from synthetic import workloads as W
+    spec = W.PARAMS[W.WORKLOADS[workload]["params"]]
+    ctx = bcn.Context(spec["n"], spec["bits"], spec["L"], spec["K"], spec["alpha"], spec["t"])
+    if autotune:
+        ctx.autotune()
+    nl = ctx.n_q + ctx.n_aux
+    polys = 490
+    x = torch.zeros((polys, nl, spec["n"]), dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        ctx.ntt(x, 0)
+        ctx.ntt(x, 0, inverse=True)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    for _ in range(steps):
+        ctx.ntt(x, 0)
+        ctx.ntt(x, 0, inverse=True)
+    torch.cuda.synchronize()
+    ctx.profile(False)
+    out = {"n": spec["n"], "limb_transforms_per_launch": polys * nl}
+    for k, (la, ms, by, ops) in ctx.profile_read().items():
+        out[k] = {"launches": la, "avg_launch_us": round(ms * 1000.0 / la, 2),
+                  "gbs": round(by / (ms * 1e-3) / 1e9, 1),
+                  "frac_of_hbm_peak": round(by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                  "limb_transforms_per_s": round(polys * nl * la / (ms * 1e-3), 1)}
+    del x, ctx
+    torch.cuda.empty_cache()
+    return out
+
+
+def serving_leg(rates, n_requests: int, autotune: bool = True, window_ms: float = None):
+    from paper_2402_01296_amd.serve import Server, poisson_arrivals
+    t0 = time.perf_counter()
+    srv = Server(autotune=autotune, max_batch={"cfg1": 64, "cfg2": 8, "cfg3": 16})
+    if window_ms is not None:
+        srv.window = window_ms * 1e-3
+    print("bench: server ready in %.1fs, keys %.1f MB, per-request bytes %s" % (
+        time.perf_counter() - t0, srv.key_bytes / 1e6, {k: round(v / 1e6, 1) for k, v in srv.req_bytes.items()}),
+        file=sys.stderr, flush=True)
+    rows = []
+    for rate in rates:
+        arr = poisson_arrivals(rate, n_requests)
+        row = {"rate": rate, "requests": len(arr)}
+        for label, mb in (("batched", None), ("unbatched", {n: 1 for n in srv.mix})):
+            r = srv.serve(arr, max_batch=mb, window=None if mb is None else 0.0)
+            row[label] = {"p50_ms": round(r["p50_ms"], 3), "p99_ms": round(r["p99_ms"], 3),
+                          "throughput": round(r["throughput"], 1), "batches": r["batches"],
+                          "mean_batch": {k: round(v, 2) for k, v in r["mean_batch"].items()}}
+            print("bench: rate %g %s p50 %.2f ms p99 %.2f ms %.1f req/s" % (
+                rate, label, r["p50_ms"], r["p99_ms"], r["throughput"]), file=sys.stderr, flush=True)
+        rows.append(row)
+    info = {"max_batch": srv.max_batch, "window_ms": srv.window * 1e3, "depth": srv.depth,
+            "hbm_budget_gb": srv.budget / 1e9, "key_bytes": srv.key_bytes,
+            "request_bytes": srv.req_bytes, "request_bytes_fixed": srv.req_fixed,
+            "admission": "per-request bytes measured: arena high-water + torch peak of batches of 1 and 2"}
+    srv.close()
+    return rows, info
 
 
 def main():
@@ -302,9 +573,6 @@ def main():
     if args.gpus != 1:
         print("bench.py: runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
-    import torch
-
     if args.copy_calibration:
         copy_calibration()
         return
@@ -317,152 +585,63 @@ def main():
     if args.serve:
         serve_bench(args)
         return
-    from paper_2402_01296_amd.workload import GpuSession
-    from synthetic import workloads as W
-
-    wl = W.WORKLOADS[args.workload]
-    g = GpuSession(args.workload)
-    tuning = None if args.no_autotune else g.autotune()
-    for ln in (tuning or "").splitlines():
-        print("bench: autotune %s" % ln, file=sys.stderr, flush=True)
-    ct_in = g.encrypt_inputs()
-    torch.cuda.synchronize()
-    print("bench: %s keys+encryption ready, %d input ciphertexts" % (args.workload, ct_in.shape[0]),
-          file=sys.stderr, flush=True)
-
-    def step():
-        return g.run(ct_in)
-
-    for _ in range(max(2, args.warmup)):
-        out = step()
-    torch.cuda.synchronize()
-    # eager reference time of the same step (host launch overhead included)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        eager_out = step()
-    torch.cuda.synchronize()
-    eager_ms = (time.perf_counter() - t0) * 1000.0 / args.steps
-    graph_ok = None
-    if args.graph:
-        # the whole step captured once as a hipGraph (every kernel of the three layers) and
-        # replayed: removes host launch gaps; checked bit-exact against the eager result
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            graph_out = step()
-        graph.replay()
-        torch.cuda.synchronize()
-        graph_ok = bool(torch.equal(graph_out, eager_out))
-        if not graph_ok:
-            raise RuntimeError("captured step differs from the eager step")
-
-        def step():  # noqa: F811
-            graph.replay()
-            return graph_out
-        for _ in range(args.warmup):
-            out = step()
-    torch.cuda.synchronize()
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        starts[i].record()
-        out = step()
-        ends[i].record()
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
-    lat = sorted(s.elapsed_time(e) for s, e in zip(starts, ends))
-    ms_per_step = total * 1000.0 / args.steps
-    batch = wl["batch"]
-    value = batch * args.steps / total
-    print("bench: timed %d steps, %.3f ms/step" % (args.steps, ms_per_step), file=sys.stderr, flush=True)
-
-    # instrumented eager pass over the same steps: per-kernel launch durations (library
-    # hipEvents around each launch, on the launch stream)
-    g.ctx.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        g.run(ct_in)
-    torch.cuda.synchronize()
-    inst_ms = (time.perf_counter() - t0) * 1000.0 / args.steps
-    g.ctx.profile(False)
-    prof = g.ctx.profile_read()
-    kern = {}
-    for k, (la, ms, by, ops) in prof.items():
-        sec = ms * 1e-3
-        kern[k] = dict(launches=la, ms=ms, bytes=by, ops=ops,
-                       gbs=by / sec / 1e9 if sec > 0 else 0.0, tops=ops / sec / 1e12 if sec > 0 else 0.0)
-    dom = max(kern, key=lambda k: kern[k]["ms"])
-    d = kern[dom]
-    # the kernel's bound is the larger of its two floors: algorithmic bytes at the HBM peak and
-    # algorithmic FP64 operations at the vector peak
-    hbm_floor = d["bytes"] / (HBM_PEAK_GBS * 1e9)
-    alu_floor = d["ops"] / (ALU_PEAK_TOPS * 1e12)
-    la = max(1, d["launches"])
-    if alu_floor > hbm_floor:
-        roof = {"kernel": dom, "bound": "alu", "achieved": round(d["tops"], 3), "peak": round(ALU_PEAK_TOPS, 3),
-                "unit": "T fp64 op/s", "frac": round(d["tops"] / ALU_PEAK_TOPS, 4)}
-    else:
-        roof = {"kernel": dom, "bound": "hbm", "achieved": round(d["gbs"], 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(d["gbs"] / HBM_PEAK_GBS, 4)}
-    traffic = measured_traffic(dom, args.workload)
-    roof.update({
-        "traffic": traffic["bytes_per_launch"] if traffic else None,
-        "traffic_unit": "bytes per launch (HBM read + write, rocprofv3 counters)",
-        "traffic_over_algorithmic": round(traffic["bytes_per_launch"] / (d["bytes"] / la), 3) if traffic else None,
-        "launches": d["launches"],
-        "avg_launch_us": round(d["ms"] * 1000.0 / la, 2),
-        "bytes_per_launch": d["bytes"] / la,
-        "fp64_ops_per_launch": d["ops"] / la,
-        "hbm_gbs": round(d["gbs"], 1),
-        "hbm_frac": round(d["gbs"] / HBM_PEAK_GBS, 4),
-        "alu_frac": round(d["tops"] / ALU_PEAK_TOPS, 4),
-    })
-    ntt_bytes = sum(kern[k]["bytes"] for k in kern if k.startswith("ntt"))
-    ntt_ms = sum(kern[k]["ms"] for k in kern if k.startswith("ntt"))
-    verified = None
-    if not wl.get("decrypts", True):
-        verified = "n/a: two 30-bit limbs leave no noise budget after the square, so the output does not decrypt"
-    elif not args.no_verify:
-        from oracle import network   # test-only check of this run's outputs
-        vals = g.output_values(out)
-        want = network.run_mod_t(args.workload, g.inputs, g.ctx.t)
-        verified = bool((vals == want).all())
+    # the oracle baseline runs first, before anything touches the GPU (its pool forks)
+    cpu = None
+    if not args.no_cpu_baseline and args.workload == "cfg2":
+        print("bench: timing the oracle sample on the host", file=sys.stderr, flush=True)
+        _, _, avail = _host_cpu()
+        cpu = cpu_baseline(args.workload, workers=min(16, avail))
+        print("bench: oracle baseline %.1f images/s on %d cores" % (cpu["value"], cpu["cores"]),
+              file=sys.stderr, flush=True)
+    head = run_workload(args.workload, args.steps, args.warmup, autotune=not args.no_autotune, graph=args.graph,
+                        verify=not args.no_verify)
+    legs = {}
+    if not args.no_legs:
+        other = "cfg3" if args.workload != "cfg3" else "cfg2"
+        legs[other] = run_workload(other, max(5, args.steps // 2), args.warmup, autotune=not args.no_autotune,
+                                   verify=not args.no_verify)
+        legs["ntt_" + args.workload] = ntt_leg(args.workload, max(5, args.steps // 2), not args.no_autotune)
+        rows, info = serving_leg([float(r) for r in args.legs_rates.split(",")], args.legs_requests,
+                                 autotune=not args.no_autotune)
+        legs["serving"] = {"rates": rows, **info}
+    served = None
+    if "serving" in legs:
+        r0 = legs["serving"]["rates"][0]
+        served = {"rate_req_per_s": r0["rate"], "p50": r0["batched"]["p50_ms"], "p99": r0["batched"]["p99_ms"],
+                  "unbatched_p50": r0["unbatched"]["p50_ms"], "unbatched_p99": r0["unbatched"]["p99_ms"],
+                  "note": "served end-to-end latency (arrival to completion) under Poisson arrivals of the "
+                          "mixed workload"}
     line = {
         "metric": "encrypted inferences/sec + p50/p99 latency; NTT HBM GB/s vs peak",
-        "value": round(value, 1),
-        "unit": "encrypted inferences/s",
+        "value": head["requests_per_s"],
+        "unit": "encrypted inferences/s (requests)",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD_TEXT.get(args.workload, args.workload), "name": args.workload,
-                   "n": g.n, "limbs": g.ctx.L, "batch": batch, "requests_per_s": round(args.steps / total, 3)},
-        "latency_ms": {"p50": round(statistics.median(lat), 3),
-                       "p99": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 3)},
-        "ntt": {"gbs": round(ntt_bytes / (ntt_ms * 1e-3) / 1e9, 1) if ntt_ms else None,
-                "frac_of_peak": round(ntt_bytes / (ntt_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ntt_ms else None,
-                "ms_per_step": round(ntt_ms / args.steps, 3)},
-        "roofline": roof,
-        "kernels": {k: {"ms_per_step": round(v["ms"] / args.steps, 3), "launches": v["launches"],
-                        "gbs": round(v["gbs"], 1), "fp64_tops": round(v["tops"], 3)}
-                    for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])},
-        "instrumented_ms_per_step": round(inst_ms, 3),
-        "timed_as": "hipGraph replay of the whole step" if args.graph else "eager launches",
-        "eager_ms_per_step": round(eager_ms, 3),
-        "graph_matches_eager": graph_ok,
-        "autotune": [ln for ln in (tuning or "").splitlines() if "chosen" in ln],
-        "verified_vs_integer_network": verified,
+        "config": {"workload": head["workload"], "name": head["name"], "n": head["n"], "limbs": head["limbs"],
+                   "images_per_request": head["images_per_request"]},
+        "images_per_s": head["images_per_s"],
+        "latency_ms": served,
+        "step_time_ms": head["step_time_ms"],
+        "roofline": head["roofline"],
+        "transform_kernels": head["transform_kernels"],
+        "kernels": head["kernels"],
+        "instrumented_ms_per_step": head["instrumented_ms_per_step"],
+        "timed_as": head["timed_as"],
+        "eager_ms_per_step": head["eager_ms_per_step"],
+        "graph_matches_eager": head["graph_matches_eager"],
+        "autotune": head["autotune"],
+        "verified_vs_integer_network": head["verified_vs_integer_network"],
+        "legs": legs,
     }
-    if not args.no_cpu_baseline and args.workload == "cfg2":
-        print("bench: timing the oracle sample on the host", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(args.workload)
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 

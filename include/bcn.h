@@ -124,7 +124,9 @@ int bcn_ct_import(bcn_context* ctx, const uint64_t* host_in, int n, int level, d
 int bcn_ntt(bcn_context* ctx, double* data, int n_polys, int n_limbs, int first_prime, int inverse,
             bcn_stream stream);
 
-/* out[o] = sum_j w[o][j] in[j] (Mult(c,u) by scalars, Add(c1,c2)); w host int32 [n_out][n_in]. */
+/* out[o] = sum_j w[o][j] in[j] (Mult(c,u) by scalars, Add(c1,c2)); w host int32 [n_out][n_in].
+ * The environment variable BCN_MAC_TILE (a power of two, 1..64) pins the number of
+ * outputs per tile; results are the same for every tile size. */
 int bcn_mac(bcn_context* ctx, const double* in, int n_in, double* out, int n_out, int level, const int32_t* w,
             bcn_stream stream);
 /* Add(c, u): c0 += round(Q_level [m]_t / t), m = encode(slots[i]); slots host int64 [n][N]. */
@@ -243,7 +245,8 @@ int bcn_profile_read(bcn_context* ctx, char* names, int names_cap, int* launches
  * still use them.  Retired blocks are freed only by bcn_scratch_release or
  * bcn_context_destroy. */
 /* Current block's device address, a counter that changes whenever the block
- * changes, its size, the largest scratch a call has used, and the bytes held by
+ * changes, its size, the most scratch any one call has used since the previous
+ * bcn_scratch_info (the mark restarts at each query), and the bytes held by
  * retired blocks.  Any output pointer may be NULL. */
 int bcn_scratch_info(bcn_context* ctx, uint64_t* base, uint64_t* generation, size_t* bytes, size_t* high_bytes,
                      size_t* retired_bytes);

@@ -213,18 +213,23 @@ class OracleSession:
             res[o] = self._activation(ct, info)
         return res
 
-    def conv_hw(self, li: int, cts: dict, outputs=None) -> dict:
+    def rotated_input(self, li: int, ct):
+        """One input channel of HW conv layer li rotated by every kernel offset (hoisted)."""
+        offs = self.plan["layers"][li]["offsets"]
+        nz = [o for o in offs if o]
+        rots = bfv.rotate_hoisted(self.prm, ct, nz, [self.gk[o] for o in nz])
+        table = dict(zip(nz, rots))
+        table[0] = ct
+        return [table[o] for o in offs]
+
+    def conv_hw(self, li: int, cts: dict, outputs=None, rot=None) -> dict:
+        """HW conv layer li for output maps ``outputs``; ``rot`` may carry the inputs already
+        rotated by rotated_input (channel -> list over the kernel offsets)."""
         prm, info = self.prm, self.plan["layers"][li]
         w = self.inputs["weights"][li]
         O, cin, k, _ = w.shape
-        rot = {}
-        for c in range(cin):
-            offs = info["offsets"]
-            nz = [o for o in offs if o]
-            rots = bfv.rotate_hoisted(prm, cts[c], nz, [self.gk[o] for o in nz])
-            table = dict(zip(nz, rots))
-            table[0] = cts[c]
-            rot[c] = [table[o] for o in offs]
+        if rot is None:
+            rot = {c: self.rotated_input(li, cts[c]) for c in range(cin)}
         mask = self.enc.encode(self.mask_slots(li))
         outputs = range(O) if outputs is None else outputs
         res = {}

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libbcn.so")
 BCN_KEY_RELIN, BCN_KEY_ROTATION = 0, 1
 BCN_CONV2D, BCN_DENSE = 0, 1
 BCN_PACK_BATCH, BCN_PACK_HW = 0, 1
+BCN_OK, BCN_ERR_INVALID, BCN_ERR_LEVEL, BCN_ERR_KEY, BCN_ERR_NOMEM, BCN_ERR_HIP, BCN_ERR_INTERNAL = 0, -1, -2, -3, -4, -5, -6
 
 
 class BcnError(RuntimeError):

@@ -1,4 +1,5 @@
 // extern "C" entry points: argument checks, error translation, arena reset.
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -263,7 +264,13 @@ int bcn_mac(bcn_context* ctx, const double* in, int n_in, double* out, int n_out
     check_ptr(out, "out");
     check_ptr(w, "w");
     std::vector<int32_t> W(w, w + (size_t)n_in * n_out);
-    bcn::MacPlan p = bcn::make_mac_plan(c, W, n_out, n_in);
+    int tile = 0;   // automatic
+    if (const char* env = std::getenv("BCN_MAC_TILE")) {
+      tile = std::atoi(env);
+      if (tile < 1 || tile > 64 || (tile & (tile - 1)))
+        throw bcn::Error(BCN_ERR_INVALID, "BCN_MAC_TILE must be a power of two in 1..64");
+    }
+    bcn::MacPlan p = bcn::make_mac_plan(c, W, n_out, n_in, {}, tile);
     try {
       bcn::mac(c, p, in, out, level, (hipStream_t)stream);
       BCN_HIP(hipStreamSynchronize((hipStream_t)stream));
@@ -503,11 +510,12 @@ int bcn_scratch_info(bcn_context* ctx, uint64_t* base, uint64_t* generation, siz
                      size_t* retired_bytes) {
   return guard([&] {
     if (!ctx || !ctx->c) throw bcn::Error(BCN_ERR_INVALID, "null context");
-    const bcn::Arena& a = *ctx->c->arena;
+    bcn::Arena& a = *ctx->c->arena;
     if (base) *base = (uint64_t)(uintptr_t)a.base();
     if (generation) *generation = a.generation();
     if (bytes) *bytes = a.capacity();
-    if (high_bytes) *high_bytes = a.high_bytes();
+    const size_t recent = a.take_recent_high();
+    if (high_bytes) *high_bytes = recent;
     if (retired_bytes) *retired_bytes = a.retired_bytes();
   });
 }

@@ -7,6 +7,7 @@
 #include <mutex>
 
 #include "internal.h"
+#include "scheme.h"
 
 namespace bcn {
 
@@ -94,6 +95,7 @@ double* Arena::take(size_t doubles) {
   off_ += doubles;
   used_total_ += doubles;
   high_ = std::max(high_, used_total_);
+  recent_high_ = std::max(recent_high_, used_total_);
   return p;
 }
 

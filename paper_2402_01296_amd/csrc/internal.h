@@ -93,7 +93,12 @@ class Arena {
   double* take(size_t doubles);
   void reset();
   size_t capacity() const;
-  size_t high_bytes() const { return high_ * sizeof(double); }
+  // the most scratch one call has used since the previous take_recent_high()
+  size_t take_recent_high() {
+    const size_t b = recent_high_ * sizeof(double);
+    recent_high_ = 0;
+    return b;
+  }
   size_t retired_bytes() const;
   // frees the retired chunks; the caller guarantees no pending work or graph uses them
   size_t release_retired();
@@ -107,7 +112,7 @@ class Arena {
  private:
   struct Chunk { double* p; size_t cap; };
   std::vector<Chunk> chunks_, retired_;
-  size_t cur_ = 0, off_ = 0, used_total_ = 0, high_ = 0;
+  size_t cur_ = 0, off_ = 0, used_total_ = 0, high_ = 0, recent_high_ = 0;
   uint64_t generation_ = 0;
   double* ext_ = nullptr;
   size_t ext_cap_ = 0, ext_off_ = 0;

@@ -2,13 +2,17 @@
 
 Requests of the three parameter sets arrive by a Poisson process.  The server
 keeps every model's evaluation keys resident, admits queued requests into a
-batch of their parameter set when the batch's HBM footprint fits the budget
-(keys plus ciphertext state), and launches the batch on that parameter set's
-stream.  Requests that arrive while batches are on the GPU wait only until
-their stream can take another batch (at most `depth` batches in flight per
-stream), so their work overlaps on the device with the other parameter sets'.
-Latency = completion (event observed) - arrival.  Results are exact: a request
-returns the same ciphertexts alone or in any batch.
+batch of their parameter set when the device bytes of everything in flight fit
+the budget (keys plus ciphertext state), and launches the batch on that
+parameter set's stream.  A request that finds its stream idle is launched at
+once; requests that arrive while a batch of their parameter set runs wait at
+most `window` seconds (the latency budget) or until `max_batch` of them are
+queued, then share one launch as the next batch (at most `depth` batches in
+flight per stream), and their work overlaps on the device with the other
+parameter sets'.  Per-request device bytes are measured, not modelled: the
+scratch arena's high-water mark plus torch's peak allocation for batches of one
+and two requests.  Latency = completion (event observed) - arrival.  Results
+are exact: a request returns the same ciphertexts alone or in any batch.
 """
 from __future__ import annotations
 
@@ -33,15 +37,16 @@ def poisson_arrivals(rate: float, n: int, seed: int = 11, mix=MIX):
 
 class Server:
     def __init__(self, mix=MIX, pool: int = 8, hbm_budget: float = 200e9, max_batch=None, depth: int = 2,
-                 autotune: bool = True):
+                 autotune: bool = True, window: float = 0.002):
         import torch
         self.torch = torch
         self.mix = mix
         self.budget = hbm_budget
         self.depth = depth
+        self.window = window
         self.max_batch = dict(max_batch or {})
         self.sessions, self.pools, self.streams = {}, {}, {}
-        self.req_bytes, self.key_bytes = {}, 0
+        self.req_bytes, self.req_fixed, self.key_bytes = {}, {}, 0
         for name in mix:
             s = GpuSession(name)
             if autotune:
@@ -53,7 +58,13 @@ class Server:
             self.key_bytes += self._key_bytes(s)
         torch.cuda.synchronize()
         for name in mix:
-            self.req_bytes[name] = self._measure_request_bytes(name)
+            self.req_fixed[name], self.req_bytes[name] = self._measure_request_bytes(name)
+
+    def close(self):
+        self.torch.cuda.synchronize()
+        self.sessions.clear()
+        self.pools.clear()
+        self.torch.cuda.empty_cache()
 
     @staticmethod
     def _key_bytes(s: GpuSession) -> int:
@@ -61,33 +72,30 @@ class Server:
         per_key = c.dnum() * 2 * (c.L + c.K) * c.n * 8
         return per_key * (1 + len(s.steps))
 
-    def _measure_request_bytes(self, name: str) -> int:
-        """Upper bound of one request's device bytes: the largest layer working set
-        (inputs, outputs, rotation taps and key-switching buffers, the square's
-        extended / tensor / rounded / key-switching intermediates)."""
+    def _measure_request_bytes(self, name: str):
+        """(fixed, per-request) device bytes of a batch of this parameter set, measured: for
+        batches of one and two requests, the largest scratch any library call used (the
+        context's arena high-water mark) plus torch's peak allocation above the resident state
+        (stacked inputs, every layer's outputs).  The two points give the slope and intercept."""
+        torch = self.torch
         s = self.sessions[name]
-        c = s.ctx
-        n, K, m = c.n, c.K, c.n_aux
-        worst = 0
-        for lay in s.layers:
-            lv = lay.level
-            ct = 2 * lv * n * 8
-            dn = c.dnum(lv)
-            b = (lay.n_in + lay.n_out) * ct
-            conv_hw = lay.desc.packing == 1 and lay.desc.kind == 0
-            if conv_hw:
-                k2 = lay.desc.k * lay.desc.k
-                b += lay.n_in * k2 * ct                                        # taps
-                b += lay.n_in * (dn * (lv + K) + (k2 - 1) * 2 * (lv + K)) * n * 8   # digits + products
-            if lay.desc.square:
-                b += lay.n_out * (5 * (lv + m) + 3 * lv + (dn + 2) * (lv + K)) * n * 8
-            if lay.steps:
-                b += lay.n_out * (dn + 2) * (lv + K) * n * 8 + lay.n_out * ct       # rotate-and-sum
-            worst = max(worst, b)
-        return int(worst)
+        tot = {}
+        for r in (1, 2, 1, 2):     # the first pair settles the arena and allocator
+            torch.cuda.synchronize()
+            torch.cuda.reset_peak_memory_stats()
+            base = torch.cuda.memory_allocated()
+            s.ctx.scratch_info()                     # restarts the per-call high-water mark
+            ct, feats = self._stack(name, list(range(r)))
+            s.run_batch(ct, feats, r)
+            torch.cuda.synchronize()
+            peak = torch.cuda.max_memory_allocated() - base
+            tot[r] = peak + s.ctx.scratch_info()["high_bytes"]
+            del ct, feats
+        per = max(1, tot[2] - tot[1])
+        return int(max(0, tot[1] - per)), int(per)
 
     def footprint(self, name: str, r: int) -> int:
-        return self.req_bytes[name] * r
+        return self.req_fixed[name] + self.req_bytes[name] * r
 
     def _stack(self, name: str, ks):
         torch = self.torch
@@ -104,10 +112,11 @@ class Server:
                 feats.append(torch.cat([f[k * per:(k + 1) * per] for k in ks]))
         return ct, feats
 
-    def serve(self, arrivals, keep_outputs: bool = False, max_batch=None):
+    def serve(self, arrivals, keep_outputs: bool = False, max_batch=None, window=None):
         """Runs the trace in real time; returns per-request latencies (s) and summary numbers."""
         torch = self.torch
         max_batch = dict(self.max_batch, **(max_batch or {}))
+        window = self.window if window is None else window
         pending = collections.deque(sorted((t, i, name) for i, (t, name) in enumerate(arrivals)))
         queues = {name: collections.deque() for name in self.mix}
         inflight = {name: collections.deque() for name in self.mix}
@@ -146,7 +155,12 @@ class Server:
                 q = queues[name]
                 if not q or len(inflight[name]) >= self.depth:
                     continue
-                r = min(len(q), max_batch.get(name, 64))
+                mb = max_batch.get(name, 64)
+                # an idle stream takes the queue at once; a busy one waits for a full batch or
+                # until the oldest queued request has used up the window
+                if inflight[name] and len(q) < mb and now - q[0][0] < window:
+                    continue
+                r = min(len(q), mb)
                 while r > 0 and used + self.key_bytes + self.footprint(name, r) > self.budget:
                     r -= 1
                 if r == 0:

@@ -42,7 +42,7 @@ def test_graph_survives_arena_growth():
     assert after["generation"] != before["generation"]
     assert after["base"] != before["base"]
     assert after["retired_bytes"] >= before["bytes"]
-    assert after["high_bytes"] > before["bytes"]
+    assert after["high_bytes"] > before["bytes"]   # the big calls, since the query before the capture
     for rep in range(3):
         g.replay()
         torch.cuda.synchronize()

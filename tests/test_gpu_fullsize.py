@@ -1,6 +1,10 @@
 """Parity at the workloads' full sizes, in the configuration bench.py times:
 sampled output ciphertexts against the oracle (computed one by one), and the
 any-size property Dec(Eval(c)) = integer network mod t over every image."""
+import hashlib
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -9,6 +13,39 @@ from oracle import bfv, network, programs
 from gpu_util import torch_cuda
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden(name):
+    """Oracle digests of every ciphertext of a workload at full size (written by
+    tests/golden/make_fullsize_digests.py from the oracle alone)."""
+    path = os.path.join(GOLDEN, "%s_fullsize.json" % name)
+    if not os.path.exists(path):
+        pytest.skip("no oracle digests for %s" % name)
+    with open(path) as f:
+        return json.load(f)
+
+
+def _digests(ctx, ct):
+    got = ctx.export(ct)
+    return [hashlib.sha256(np.ascontiguousarray(got[k], dtype="<u8").tobytes()).hexdigest()
+            for k in range(got.shape[0])]
+
+
+def _check_every_layer(g, ct, gold):
+    """Runs the session's layers from `ct`, comparing every ciphertext with the oracle's digests."""
+    layers = gold["layers"]
+    assert len(layers) == len(g.layers) + 1
+    assert _digests(g.ctx, ct) == layers[0]["digests"], "encrypted inputs"
+    for li, lay in enumerate(g.layers):
+        ct = lay(g.ek, ct, g.features[li])
+        want = layers[li + 1]["digests"]
+        got = _digests(g.ctx, ct)
+        assert ct.shape[2] == layers[li + 1]["level"]
+        bad = [k for k in range(len(want)) if got[k] != want[k]]
+        assert len(got) == len(want) and not bad, "layer %d: outputs %s differ from the oracle" % (li + 1, bad[:8])
+    return ct
 
 
 @pytest.fixture(scope="module")
@@ -19,6 +56,13 @@ def cfg2_gpu():
     g.autotune()
     ct = g.encrypt_inputs()
     return g, ct
+
+
+def test_cfg2_full_every_ciphertext_matches_oracle(cfg2_gpu):
+    """Every ciphertext of every layer at full size (245 conv outputs, 100 dense outputs at the
+    autotuned MAC tile, 10 dense outputs at theirs) bit-exact against the oracle's digests."""
+    g, ct = cfg2_gpu
+    _check_every_layer(g, ct, _golden("cfg2"))
 
 
 def test_cfg2_full_decrypts_to_network(cfg2_gpu):
@@ -79,31 +123,28 @@ def test_cfg1d_full_decrypts_to_network():
     assert (vals == want).all()
 
 
-def test_cfg3_full_decrypts_to_network():
+@pytest.fixture(scope="module")
+def cfg3_gpu():
     torch_cuda()
     from paper_2402_01296_amd.workload import GpuSession
     g = GpuSession("cfg3")
     g.autotune()
-    out = g.run(g.encrypt_inputs())
+    return g, g.encrypt_inputs()
+
+
+def test_cfg3_full_every_ciphertext_matches_oracle(cfg3_gpu):
+    """Every ciphertext of the CIFAR-shaped branch at N = 16384 bit-exact against the oracle's
+    digests: layer 1 (24 hoisted rotations, MAC, mask, features, square, relinearisation, modulus
+    switch), layer 2 (256 hoisted rotations at five primes with a one-prime last digit, MAC, mask,
+    features, square, relinearisation, modulus switch, rotate-and-sum over 128 slots) and the
+    dense outputs."""
+    g, ct = cfg3_gpu
+    _check_every_layer(g, ct, _golden("cfg3"))
+
+
+def test_cfg3_full_decrypts_to_network(cfg3_gpu):
+    g, ct = cfg3_gpu
+    out = g.run(ct)
     vals = g.output_values(out)
     want = network.run_mod_t("cfg3", g.inputs, g.ctx.t)
     assert (vals == want).all()
-
-
-@pytest.mark.slow
-def test_cfg3_full_first_layer_sampled():
-    """One output channel of the first CIFAR-shaped layer (24 hoisted rotations at N = 16384,
-    MAC, mask, features, square, relinearisation, modulus switch) against the oracle."""
-    torch_cuda()
-    from paper_2402_01296_amd.workload import GpuSession
-    g = GpuSession("cfg3")
-    ct = g.encrypt_inputs()
-    first = g.layers[0](g.ek, ct, g.features[0])
-    got = g.ctx.export(first[5:6])[0]
-    O = programs.OracleSession("cfg3", with_galois=False)
-    for r in O.plan["layers"][0]["offsets"]:
-        if r:
-            O.galois(r)
-    cts = O.encrypt_inputs()
-    ref = O.conv_hw(0, cts, outputs=[5])[5]
-    assert (got == bfv.ct_to_rns(O.prm, ref)).all()

@@ -153,6 +153,29 @@ def test_mac_parity(env_t1k, n_in, n_out, bound):
         assert (out[o] == ref).all(), "output %d" % o
 
 
+@pytest.mark.parametrize("tile", [1, 2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("regime", ["uncentred", "centred"])
+def test_mac_parity_every_tile(env_t1k, tile, regime, monkeypatch):
+    """Each compiled output-tile width, on the uncentred path (a tile's sum of |w| (q-1) fits
+    2^53) and on the centred path with partial reductions (it does not)."""
+    ev = env_t1k
+    prm, ctx = ev["prm"], ev["ctx"]
+    level = prm.L
+    # one full tile and a partial one; centred: |w| up to 30000 makes a tile's sum of |w| (q-1)
+    # exceed 2^53 and forces a partial reduction every few inputs
+    n_out = tile + 3
+    n_in, bound = (37, 15) if regime == "uncentred" else (13, 30000)
+    res = random_ct_residues(prm, level, n_in, 20 + tile)
+    w = np.random.default_rng(tile).integers(-bound, bound + 1, (n_out, n_in)).astype(np.int32)
+    w[2] = 0
+    monkeypatch.setenv("BCN_MAC_TILE", str(tile))
+    out = ctx.export(ctx.mac(ctx.import_(res), w))
+    cts = [oracle_ct(prm, r) for r in res]
+    for o in range(n_out):
+        ref = bfv.ct_to_rns(prm, bfv.mac(prm, cts, w[o]))
+        assert (out[o] == ref).all(), "tile %d output %d" % (tile, o)
+
+
 def test_plain_ops_parity(env_t1k):
     ev = env_t1k
     prm, ctx, enc = ev["prm"], ev["ctx"], ev["enc"]
