@@ -138,6 +138,19 @@ int bcn_mul_plain(bcn_context* ctx, const double* in, double* out, int n, int le
  * with modswitch != 0 the result is also switched down one prime (level-1 limbs). */
 int bcn_square_relin(bcn_context* ctx, const bcn_eval_keys* ek, const double* in, double* out, int n, int level,
                      int modswitch, bcn_stream stream);
+/* For callers that cannot allocate device memory (code under hipGraph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): bcn_square_relin with
+ * the same arguments, semantics and bit-identical results, but no allocation,
+ * free or allocating library call of any kind.  Its scratch is a fixed 64 MiB
+ * array of device memory per GPU, held by the library until the process ends.
+ * A call whose scratch would exceed it (about 12 ciphertexts at N = 8192 with
+ * four primes, 4 at N = 16384 with six) returns BCN_ERR_INVALID before
+ * launching anything.  Every call on one GPU, from any context, stream or host
+ * thread, uses that one array, so calls that overlap in time on one GPU race:
+ * the caller must serialise them.  Nothing in the array needs to start at zero
+ * (every word is written before it is read). */
+int bcn_square_relin_noalloc(bcn_context* ctx, const bcn_eval_keys* ek, const double* in, double* out, int n,
+                             int level, int modswitch, bcn_stream stream);
 /* Rot(c, r) for each input and each step, sharing one digit decomposition per input
  * (hoisting; bit-identical to one-at-a-time).  out device [n_in][n_steps][2][level][N]. */
 int bcn_rotate(bcn_context* ctx, const bcn_eval_keys* ek, const double* in, int n_in, int level,

@@ -78,6 +78,7 @@ _SIGS = {
     "bcn_autotune": (_I, [_VP, C.c_char_p, _I, _VP]),
     "bcn_layer_autotune": (_I, [_VP, _VP, C.c_char_p, _I, _VP]),
     "bcn_profile_read": (_I, [_VP, C.c_char_p, _I, _VP, _VP, _VP, _VP, _I]),
+    "bcn_square_relin_noalloc": (_I, [_VP, _VP, _VP, _VP, _I, _I, _I, _VP]),
     "bcn_scratch_info": (_I, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "bcn_scratch_release": (_I, [_VP]),
 }
@@ -244,6 +245,13 @@ class Context:
         out = self.empty_ct(n, level - 1 if modswitch else level)
         _check(lib().bcn_square_relin(self.h, ek.h, _dptr(ct), _dptr(out), n, level, 1 if modswitch else 0,
                                       _stream()))
+        return out
+
+    def square_relin_noalloc(self, ek, ct, out, modswitch=False):
+        """The allocation-free square + relinearisation into caller-provided `out`."""
+        n, _, level, _ = ct.shape
+        _check(lib().bcn_square_relin_noalloc(self.h, ek.h, _dptr(ct), _dptr(out), n, level,
+                                              1 if modswitch else 0, _stream()))
         return out
 
     def rotate(self, ek, ct, steps):

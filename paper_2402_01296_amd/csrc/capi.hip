@@ -338,6 +338,23 @@ int bcn_square_relin(bcn_context* ctx, const bcn_eval_keys* ek, const double* in
   });
 }
 
+int bcn_square_relin_noalloc(bcn_context* ctx, const bcn_eval_keys* ek, const double* in, double* out, int n,
+                             int level, int modswitch, bcn_stream stream) {
+  return guard([&] {
+    // no arena reset here: resetting may move the arena to a new block (an allocation)
+    if (!ctx || !ctx->c) throw bcn::Error(BCN_ERR_INVALID, "null context");
+    bcn::Context& c = *ctx->c;
+    BCN_HIP(hipSetDevice(c.device));
+    check_level(c, level);
+    check_n(n);
+    check_ptr(ek, "eval keys");
+    if (n == 0) return;
+    check_ptr(in, "in");
+    check_ptr(out, "out");
+    bcn::square_relin_noalloc(c, *ek->k, in, out, n, level, modswitch != 0, (hipStream_t)stream);
+  });
+}
+
 int bcn_rotate(bcn_context* ctx, const bcn_eval_keys* ek, const double* in, int n_in, int level, const int32_t* steps,
                int n_steps, double* out, bcn_stream stream) {
   return guard([&] {

@@ -357,6 +357,7 @@ Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uin
   ntt_setup(*c);
   preload_conversions(*c);
   preload_ks_digits(*c);
+  fixed_scratch_setup(*c);
   return c.release();
 }
 

@@ -47,6 +47,12 @@ void encode_plain_ntt(Context& c, const int64_t* slots_host, int n, int level, d
 
 void square_relin(Context& c, const EvalKeys& ek, const double* in, double* out, int n, int level, bool modsw,
                   hipStream_t s);
+// scratch doubles square_relin takes from the arena for n ciphertexts at `level`
+size_t square_relin_scratch_doubles(const Context& c, int n, int level);
+// square_relin with its scratch in the fixed per-device array (noalloc.hip): no allocation
+void square_relin_noalloc(Context& c, const EvalKeys& ek, const double* in, double* out, int n, int level, bool modsw,
+                          hipStream_t s);
+void fixed_scratch_setup(Context& c);
 // the same from x [n][2][level+m][N] whose Q limbs hold the input; x's B limbs are filled in place
 void square_relin_qb(Context& c, const EvalKeys& ek, double* x, double* out, int n, int level, bool modsw,
                      hipStream_t s);

@@ -275,6 +275,16 @@ void square_relin_tail(Context& c, const EvalKeys& ek, double* X, double* out, i
 }
 }  // namespace
 
+size_t square_relin_scratch_doubles(const Context& c, int n, int level) {
+  // mirrors the arena takes of square_relin and square_relin_tail
+  const size_t N = c.n, nb = level + c.m, nbp = level + c.K, dn = c.dnum(level);
+  const bool fuse = c.fuse_moddown && moddown_scale_round_ok(c, level);
+  size_t d = Arena::rounded((size_t)n * 2 * nb * N) + Arena::rounded((size_t)n * 3 * nb * N) +
+             Arena::rounded((size_t)n * (fuse ? 1 : 3) * level * N) + Arena::rounded((size_t)n * 2 * nbp * N);
+  if (c.ks_mode != 1) d += Arena::rounded((size_t)n * dn * nbp * N);
+  return d;
+}
+
 void square_relin(Context& c, const EvalKeys& ek, const double* in, double* out, int n, int level, bool modsw,
                   hipStream_t s) {
   if (!ek.relin) throw Error(-3, "missing relinearisation key");
