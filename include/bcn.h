@@ -201,7 +201,10 @@ typedef struct {
   int32_t batch;         /* BATCH: images (slots) carrying data */
   int32_t square;        /* square + relinearise after the linear part (+features) */
   int32_t modswitch;     /* after the square, switch down one prime (needs level >= 2) */
-  int32_t sum;           /* HW CONV2D: global sum of each output map, left in slot 0 */
+  int32_t sum;           /* HW CONV2D: nonzero = global sum of each output map, left in slot 0;
+                            BATCH DENSE (scalar weights): 0, or a span S (power of two): each
+                            output is then rotated-and-summed over S slots (a global sum moved
+                            after the dense layer, which commutes with it) */
 } bcn_layer_desc;
 
 /* Prepares a layer for inputs at `level`: uploads weights, encodes masks and

@@ -48,6 +48,7 @@ def plan(name: str):
     steps = set()
     layers = []
     spatial = True
+    moved_span = 0
     for li, lay in enumerate(wl["layers"]):
         (cin, *hw_in), out = shapes[li]
         info = dict(lay)
@@ -63,9 +64,16 @@ def plan(name: str):
                 ps = ps_out
                 if lay.get("sum"):
                     span = _span(max(info["out_slots"]))
-                    info["sum_span"] = span
+                    if wl.get("sum_after_dense"):
+                        # the global sum moves after the following (scalar) dense layer
+                        moved_span = span
+                    else:
+                        info["sum_span"] = span
                     steps.update(span >> (k + 1) for k in range(span.bit_length() - 1))
                     spatial = False
+            elif moved_span:
+                info["sum_span"] = moved_span
+                moved_span = 0
             elif spatial:
                 # dense over spatially laid out channels: weight vectors + rotate-and-sum
                 prev = layers[-1]
@@ -203,6 +211,8 @@ class OracleSession:
         return res
 
     def dense_scalar(self, li: int, cts: dict, outputs=None) -> dict:
+        """Scalar dense layer over ciphertexts; with a global sum moved after it (HW packing),
+        each output is then rotated-and-summed."""
         prm, info = self.prm, self.plan["layers"][li]
         w = self.inputs["weights"][li]
         n_out, n_in = w.shape
@@ -210,7 +220,10 @@ class OracleSession:
         res = {}
         for o in outputs:
             ct = bfv.mac(prm, [cts[i] for i in range(n_in)], [int(x) for x in w[o]])
-            res[o] = self._activation(ct, info)
+            ct = self._activation(ct, info)
+            if info.get("sum_span"):
+                ct = self.rotate_sum(ct, info["sum_span"])
+            res[o] = ct
         return res
 
     def rotated_input(self, li: int, ct):
@@ -292,7 +305,7 @@ class OracleSession:
         for li, info in enumerate(self.plan["layers"]):
             if info["kind"] == "conv":
                 cts = self.conv_hw(li, cts) if hw else self.conv_batch(li, cts)
-                if info.get("sum_span"):
+                if info.get("sum"):
                     spatial = False
             elif hw and spatial:
                 cts = self.dense_hw(li, cts)

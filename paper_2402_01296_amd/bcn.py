@@ -366,7 +366,7 @@ class Layer:
         d.batch = desc.get("batch", 0)
         d.square = 1 if desc.get("square") else 0
         d.modswitch = 1 if desc.get("modswitch") else 0
-        d.sum = 1 if desc.get("sum") else 0
+        d.sum = int(desc.get("sum") or 0)
         self.desc = d
         h = C.c_void_p()
         _check(lib().bcn_layer_create(ctx.h, C.byref(d), level, C.byref(h)))

@@ -82,7 +82,17 @@ Layer* layer_create(Context& c, const bcn_layer_desc& d, int level) {
       L->mac_weights = W;
     }
     L->stride_b = L->n_out;
-    if (d.sum) throw Error(-1, "global sum needs HW packing");
+    if (d.sum) {
+      // a global sum moved after a scalar dense layer (sum and dense are linear): rotate-and-sum
+      // of each output over d.sum slots
+      if (d.kind != BCN_DENSE || d.has_features || d.square)
+        throw Error(-1, "a batch-packed layer's sum must follow a plain dense layer");
+      if (d.sum < 2 || (d.sum & (d.sum - 1)) || d.sum > N / 2)
+        throw Error(-1, "sum span must be a power of two in 2..N/2");
+      L->span = d.sum;
+      for (int r = L->span / 2; r >= 1; r /= 2) L->all_steps.push_back(r);
+      std::sort(L->all_steps.begin(), L->all_steps.end());
+    }
     return L.release();
   }
   if (d.packing != BCN_PACK_HW) throw Error(-1, "unknown packing");

@@ -25,20 +25,29 @@ def layer_descs(name: str):
     row = wl["crop"][1]
     ps = 1
     spatial = True
+    moved_span = 0
     out = []
     for li, lay in enumerate(wl["layers"]):
         (inp, outp) = shapes[li]
         d = dict(square=lay["square"], modswitch=lay["square"], batch=wl["batch"])
         if lay["kind"] == "conv":
             c, h, w = inp
+            # with sum_after_dense the global sum runs after the next (scalar) dense layer
+            conv_sum = lay.get("sum", False) and not (hw and wl.get("sum_after_dense"))
             d.update(kind=bcn.BCN_CONV2D, packing=bcn.BCN_PACK_HW if hw else bcn.BCN_PACK_BATCH,
                      in_c=c, in_h=h, in_w=w, out_c=lay["out"], k=lay["k"], stride=lay["stride"],
                      pad=lay["pad"], row=row, pos_stride=ps, features=lay.get("features", False),
-                     sum=lay.get("sum", False))
+                     sum=conv_sum)
             if hw:
                 ps *= lay["stride"]
                 if lay.get("sum"):
                     spatial = False
+                    if not conv_sum:
+                        oh, ow = outp[1], outp[2]
+                        last = ps * (row * (oh - 1) + ow - 1)
+                        moved_span = 1
+                        while moved_span < last + 1:
+                            moved_span *= 2
         else:
             if hw and spatial:
                 c, h, w = shapes[li - 1][1]
@@ -47,7 +56,8 @@ def layer_descs(name: str):
                 spatial = False
             else:
                 d.update(kind=bcn.BCN_DENSE, packing=bcn.BCN_PACK_BATCH, in_c=inp[0], in_h=1, in_w=1,
-                         out_c=lay["out"], batch=max(1, wl["batch"]))
+                         out_c=lay["out"], batch=max(1, wl["batch"]), sum=moved_span)
+                moved_span = 0
         out.append(d)
     return out
 

@@ -56,8 +56,11 @@ WORKLOADS = {
                  layers=[dict(kind="conv", out=5, k=5, stride=2, pad=1, bound=15, features=True, square=True),
                          dict(kind="dense", out=100, bound=15, square=True),
                          dict(kind="dense", out=10, bound=15, square=False)]),
-    # one 32x32x3 image, HW packing (one channel per ciphertext), central 16x16 crop
-    "cfg3": dict(params="cfg3", packing="hw", batch=1, image=(3, 32, 32), crop=(8, 16),
+    # one 32x32x3 image, HW packing (one channel per ciphertext), central 16x16 crop.
+    # sum_after_dense: the HE program applies the dense layer's scalar weights to the 64 channel
+    # ciphertexts first and rotates-and-sums the 10 results (10 x 8 rotations instead of 64 x 8);
+    # global sum and dense are linear, so the network is the same
+    "cfg3": dict(params="cfg3", packing="hw", batch=1, image=(3, 32, 32), crop=(8, 16), sum_after_dense=True,
                  layers=[dict(kind="conv", out=32, k=3, stride=1, pad=0, bound=31, features=True, square=True),
                          dict(kind="conv", out=64, k=3, stride=2, pad=0, bound=31, features=True, square=True,
                               sum=True),
@@ -70,7 +73,7 @@ WORKLOADS = {
     "cfg1_small": dict(params="t1k5", packing="hw", batch=1, image=(1, 28, 28), crop=(8, 12),
                        layers=[dict(kind="conv", out=2, k=5, stride=2, pad=0, bound=7, features=False, square=True),
                                dict(kind="dense", out=3, bound=7, square=False)]),
-    "cfg3_small": dict(params="t2k3", packing="hw", batch=1, image=(3, 32, 32), crop=(8, 16),
+    "cfg3_small": dict(params="t2k3", packing="hw", batch=1, image=(3, 32, 32), crop=(8, 16), sum_after_dense=True,
                        layers=[dict(kind="conv", out=3, k=3, stride=1, pad=0, bound=31, features=True, square=True),
                                dict(kind="conv", out=2, k=3, stride=2, pad=0, bound=31, features=True, square=True,
                                     sum=True),

@@ -78,7 +78,7 @@ def main():
             if hw:
                 _S["rot"] = _pool_map(_rotate, sorted(cts), workers)
                 _S["kind"] = "conv_hw"
-                if info.get("sum_span"):
+                if info.get("sum"):
                     spatial = False
             else:
                 _S["kind"] = "conv_batch"
