@@ -32,6 +32,8 @@ WORKLOAD_TEXT = {
             "conv5x5s2(5)+features+square, dense100+square, dense10",
     "cfg1": "tiny HW-packed branch: N=4096, 2x30-bit primes, t=65537, one 28x28 image",
     "cfg3": "CIFAR-shaped HW-packed branch: N=16384, 6x40-bit primes, dnum=3, one 32x32x3 image",
+    "cfg3_bhw": "CIFAR-shaped branch with BHW packing: N=16384, 6x40-bit primes, dnum=3, 64 32x32x3 images "
+                "per ciphertext (one 256-slot block each)",
 }
 
 
@@ -600,6 +602,8 @@ def main():
         other = "cfg3" if args.workload != "cfg3" else "cfg2"
         legs[other] = run_workload(other, max(5, args.steps // 2), args.warmup, autotune=not args.no_autotune,
                                    verify=not args.no_verify)
+        legs["cfg3_bhw"] = run_workload("cfg3_bhw", max(5, args.steps // 2), args.warmup,
+                                        autotune=not args.no_autotune, verify=not args.no_verify)
         legs["ntt_" + args.workload] = ntt_leg(args.workload, max(5, args.steps // 2), not args.no_autotune)
         rows, info = serving_leg([float(r) for r in args.legs_rates.split(",")], args.legs_requests,
                                  autotune=not args.no_autotune)

@@ -176,7 +176,10 @@ enum { BCN_PACK_BATCH = 0, BCN_PACK_HW = 1 };
  *   DENSE: out[o] = sum_j w[o][j] in[j] (also the scalar layer over
  *   ciphertexts that each carry one value).
  * HW packing (one ciphertext per channel, input position (y, x) at slot
- *   pos_stride*(row*y + x)): CONV2D (valid, pad 0) rotates each input by
+ *   pos_stride*(row*y + x)); BHW packing (appendix "Implementation Details",
+ *   BHW packing) is HW packing with `batch` images per ciphertext, image b's
+ *   positions offset by base(b) = (b mod P) * block + floor(b / P) * N/2,
+ *   P = (N/2) / block (blocks fill slot row 0, then row 1): CONV2D (valid, pad 0) rotates each input by
  *   pos_stride*(row*di + dj), multiplies by w[o][c][di][dj], sums and keeps the
  *   outputs at slots pos_stride*stride*(row*i + j) with a mask; DENSE weights
  *   w[o][c*in_h*in_w + y*in_w + x] multiply the slot of (y, x) of input c,
@@ -184,7 +187,7 @@ enum { BCN_PACK_BATCH = 0, BCN_PACK_HW = 1 };
  *   out[o] in slot 0.
  * Features (has_features): FP32 device array; q(f) = clamp(rint(scale f),
  *   -clamp, clamp) in FP32 arithmetic is added as a plaintext.  BATCH: layout
- *   [batch][n_out] (image-major); HW: [out_c][oh][ow].
+ *   [batch][n_out] (image-major); HW: [out_c][oh][ow]; BHW: [out_c][batch][oh][ow].
  */
 typedef struct {
   int32_t kind;          /* BCN_CONV2D or BCN_DENSE */
@@ -198,13 +201,15 @@ typedef struct {
   int32_t has_features;
   float feature_scale;   /* 8.0 in the three workloads */
   int32_t feature_clamp; /* 127 */
-  int32_t batch;         /* BATCH: images (slots) carrying data */
+  int32_t batch;         /* BATCH: images (slots) carrying data; HW with block > 0: images per ciphertext */
   int32_t square;        /* square + relinearise after the linear part (+features) */
   int32_t modswitch;     /* after the square, switch down one prime (needs level >= 2) */
   int32_t sum;           /* HW CONV2D: nonzero = global sum of each output map, left in slot 0;
                             BATCH DENSE (scalar weights): 0, or a span S (power of two): each
                             output is then rotated-and-summed over S slots (a global sum moved
                             after the dense layer, which commutes with it) */
+  int32_t block;         /* HW: 0 (one image at base 0), or the slot distance between the blocks of
+                            `batch` images packed in one ciphertext (BHW packing) */
 } bcn_layer_desc;
 
 /* Prepares a layer for inputs at `level`: uploads weights, encodes masks and

@@ -67,7 +67,7 @@ def run(name: str, inputs, images=None, t=None):
     dt = object if t is None else np.int64
     idx = np.arange(wl["batch"]) if images is None else np.asarray(images)
     x = inputs["images"][idx][:, :, y0:y0 + size, y0:y0 + size].astype(dt)
-    batch = wl["packing"] == "batch"
+    batch = wl["packing"] in ("batch", "bhw")
     for li, lay in enumerate(wl["layers"]):
         w = inputs["weights"][li]
         if lay["kind"] == "conv":
@@ -104,6 +104,6 @@ def first_layer_linear(name: str, inputs, images=None, t=None):
     x = conv2d(x, inputs["weights"][0], lay["stride"], lay["pad"], t)
     f = inputs["features"][0]
     if f is not None:
-        fq = quantise(f[idx] if wl["packing"] == "batch" else f[None])
+        fq = quantise(f[idx] if wl["packing"] in ("batch", "bhw") else f[None])
         x = _red(x + fq.astype(dt), t)
     return x

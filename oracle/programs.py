@@ -5,7 +5,8 @@ The programs follow the appendix "Implementation Details":
     a conv or dense layer is a multiply-accumulate of ciphertexts with scalar
     weights (Mult(c,u) by a constant, Add(c1,c2));
   * HW packing: one ciphertext per input channel, pixel (y, x) at slot
-    row*y + x of slot row 0; a convolution rotates the channel ciphertext by
+    row*y + x of slot row 0 (BHW packing: the same layout in one block of
+    slots per image, `batch` images per ciphertext); a convolution rotates the channel ciphertext by
     each kernel offset, multiplies by the scalar kernel weight, sums, and
     multiplies by a mask that keeps the valid output slots;
   * sum pooling ("Homomorphic pooling layer") and the HW dense layer end with
@@ -53,7 +54,7 @@ def plan(name: str):
         (cin, *hw_in), out = shapes[li]
         info = dict(lay)
         info["in_shape"], info["out_shape"] = shapes[li][0], out
-        if wl["packing"] == "hw":
+        if wl["packing"] in ("hw", "bhw"):
             if lay["kind"] == "conv":
                 offs = [ps * (row * di + dj) for di in range(lay["k"]) for dj in range(lay["k"])]
                 info["offsets"] = offs
@@ -83,7 +84,12 @@ def plan(name: str):
                 steps.update(span >> (k + 1) for k in range(span.bit_length() - 1))
                 spatial = False
         layers.append(info)
-    return dict(row=row, layers=layers, steps=sorted(steps))
+    if wl["packing"] == "bhw":
+        n = params.get(wl["params"]).n
+        bases = [W.image_base(b, wl["block"], n) for b in range(wl["batch"])]
+    else:
+        bases = [0]
+    return dict(row=row, layers=layers, steps=sorted(steps), bases=bases)
 
 
 class OracleSession:
@@ -136,9 +142,10 @@ class OracleSession:
             return out
         c = crop.shape[1]
         out = np.zeros((c, n), dtype=np.int64)
-        for ch in range(c):
-            for y in range(size):
-                out[ch, size * y:size * y + size] = crop[0, ch, y]
+        for b, base in enumerate(self.plan["bases"]):
+            for ch in range(c):
+                for y in range(size):
+                    out[ch, base + size * y:base + size * y + size] = crop[b, ch, y]
         return out
 
     def encrypt_slots(self, slots, index: int, level=None) -> bfv.Ct:
@@ -166,14 +173,17 @@ class OracleSession:
         out = np.zeros(n, dtype=np.int64)
         if wl["packing"] == "batch":
             return f[:, o]                             # [batch][oh][ow]; caller picks (i, j)
-        for pos, slot in enumerate(info["out_slots"]):
-            i, j = divmod(pos, info["out_shape"][2])
-            out[slot] = f[o, i, j]
+        per_image = f if wl["packing"] == "bhw" else f[None]
+        for b, base in enumerate(self.plan["bases"]):
+            for pos, slot in enumerate(info["out_slots"]):
+                i, j = divmod(pos, info["out_shape"][2])
+                out[base + slot] = per_image[b, o, i, j]
         return out
 
     def mask_slots(self, li: int) -> np.ndarray:
         out = np.zeros(self.prm.n, dtype=np.int64)
-        out[self.plan["layers"][li]["out_slots"]] = 1
+        for base in self.plan["bases"]:
+            out[[base + v for v in self.plan["layers"][li]["out_slots"]]] = 1
         return out
 
     # ------------------------------------------------------------ layers
@@ -276,7 +286,8 @@ class OracleSession:
             acc = None
             for c in range(cin):
                 v = np.zeros(prm.n, dtype=np.int64)
-                v[slots_in] = w[kk, c * per:(c + 1) * per]
+                for base in self.plan["bases"]:
+                    v[[base + x for x in slots_in]] = w[kk, c * per:(c + 1) * per]
                 term = bfv.mul_plain(prm, cts[c], self.enc.encode(v))
                 acc = term if acc is None else bfv.add(prm, acc, term)
             acc = self.rotate_sum(acc, info["sum_span"])
@@ -300,7 +311,7 @@ class OracleSession:
     # ------------------------------------------------------------ whole program
 
     def run(self, cts: dict) -> dict:
-        hw = self.wl["packing"] == "hw"
+        hw = self.wl["packing"] in ("hw", "bhw")
         spatial = True
         for li, info in enumerate(self.plan["layers"]):
             if info["kind"] == "conv":
@@ -315,9 +326,10 @@ class OracleSession:
         return cts
 
     def output_values(self, outs: dict) -> np.ndarray:
-        """Decrypted network outputs: batch -> [batch][n_out]; HW -> [1][n_out] (slot 0)."""
+        """Decrypted network outputs: batch -> [batch][n_out]; HW -> [1][n_out] (slot 0);
+        BHW -> [batch][n_out] (the first slot of each image's block)."""
         vals = [self.decrypt_slots(outs[k]) for k in sorted(outs)]
         if self.wl["packing"] == "batch":
             b = self.wl["batch"]
             return np.stack([v[:b] for v in vals], axis=1)
-        return np.array([[v[0] for v in vals]])
+        return np.array([[v[base] for v in vals] for base in self.plan["bases"]])

@@ -38,7 +38,7 @@ class LayerDesc(C.Structure):
                 ("pad", C.c_int32), ("row", C.c_int32), ("pos_stride", C.c_int32),
                 ("weights", C.POINTER(C.c_int32)), ("has_features", C.c_int32), ("feature_scale", C.c_float),
                 ("feature_clamp", C.c_int32), ("batch", C.c_int32), ("square", C.c_int32),
-                ("modswitch", C.c_int32), ("sum", C.c_int32)]
+                ("modswitch", C.c_int32), ("sum", C.c_int32), ("block", C.c_int32)]
 
 
 _lib = None
@@ -367,6 +367,7 @@ class Layer:
         d.square = 1 if desc.get("square") else 0
         d.modswitch = 1 if desc.get("modswitch") else 0
         d.sum = int(desc.get("sum") or 0)
+        d.block = int(desc.get("block") or 0)
         self.desc = d
         h = C.c_void_p()
         _check(lib().bcn_layer_create(ctx.h, C.byref(d), level, C.byref(h)))

@@ -101,6 +101,18 @@ Layer* layer_create(Context& c, const bcn_layer_desc& d, int level) {
   L->n_in = d.in_c;
   L->n_out = d.out_c;
   auto slot = [&](int ps, int y, int x) { return ps * (d.row * y + x); };
+  // BHW packing: image b's block starts at bases[b]; HW packing: one image at slot 0
+  std::vector<int> bases(1, 0);
+  int extent = half;              // slots one image may use
+  if (d.block > 0) {
+    if (d.block > half || half % d.block) throw Error(-1, "BHW block must divide N/2");
+    const int per_row = half / d.block;
+    if (d.batch < 1 || d.batch > 2 * per_row) throw Error(-1, "BHW: 1..N/block images per ciphertext");
+    bases.clear();
+    for (int b = 0; b < d.batch; ++b) bases.push_back((b % per_row) * d.block + (b / per_row) * half);
+    extent = d.block;
+  }
+  if (slot(d.pos_stride, d.in_h - 1, d.in_w - 1) >= extent) throw Error(-1, "input positions beyond the image block");
   if (d.kind == BCN_CONV2D) {
     if (d.pad != 0) throw Error(-1, "HW convolution is valid (pad 0)");
     const int k2 = d.k * d.k;
@@ -109,7 +121,7 @@ Layer* layer_create(Context& c, const bcn_layer_desc& d, int level) {
     for (int di = 0; di < d.k; ++di)
       for (int dj = 0; dj < d.k; ++dj) {
         const int off = slot(d.pos_stride, di, dj);
-        if (off >= half) throw Error(-1, "rotation offset beyond the slot row");
+        if (off >= extent) throw Error(-1, "rotation offset beyond the image block");
         if (off == 0) {
           tap_of[di * d.k + dj] = 0;
         } else {
@@ -132,18 +144,23 @@ Layer* layer_create(Context& c, const bcn_layer_desc& d, int level) {
     for (int i = 0; i < L->oh; ++i)
       for (int j = 0; j < L->ow; ++j) so.push_back(slot(ops, i, j));
     const int maxs = *std::max_element(so.begin(), so.end());
-    if (maxs >= half) throw Error(-1, "output positions beyond the slot row");
+    if (maxs >= extent) throw Error(-1, "output positions beyond the image block");
     std::vector<int64_t> mask(N, 0);
-    for (int v : so) mask[v] = 1;
+    for (int b : bases)
+      for (int v : so) mask[b + v] = 1;
     BCN_HIP(hipMalloc(&L->mask_hat, (size_t)level * N * sizeof(double)));
     c.arena->reset();
     encode_plain_ntt(c, mask.data(), 1, level, L->mask_hat, nullptr);
-    L->per = (int)so.size();
-    BCN_HIP(hipMalloc(&L->slot_of, so.size() * sizeof(int)));
-    BCN_HIP(hipMemcpy(L->slot_of, so.data(), so.size() * sizeof(int), hipMemcpyHostToDevice));
+    // feature slots of one output map: images in order, positions in (i, j) order
+    std::vector<int> fo;
+    for (int b : bases)
+      for (int v : so) fo.push_back(b + v);
+    L->per = (int)fo.size();
+    BCN_HIP(hipMalloc(&L->slot_of, fo.size() * sizeof(int)));
+    BCN_HIP(hipMemcpy(L->slot_of, fo.data(), fo.size() * sizeof(int), hipMemcpyHostToDevice));
     if (d.sum) {
       L->span = next_pow2(maxs + 1);
-      if (L->span > half) throw Error(-1, "sum span beyond the slot row");
+      if (L->span > extent) throw Error(-1, "sum span beyond the image block");
       for (int r = L->span / 2; r >= 1; r /= 2) L->all_steps.push_back(r);
     }
   } else {
@@ -153,17 +170,19 @@ Layer* layer_create(Context& c, const bcn_layer_desc& d, int level) {
     for (int y = 0; y < d.in_h; ++y)
       for (int x = 0; x < d.in_w; ++x) si.push_back(slot(d.pos_stride, y, x));
     const int maxs = *std::max_element(si.begin(), si.end());
-    if (maxs >= half) throw Error(-1, "input positions beyond the slot row");
+    if (maxs >= extent) throw Error(-1, "input positions beyond the image block");
     std::vector<int64_t> vec((size_t)d.out_c * d.in_c * N, 0);
     for (int o = 0; o < d.out_c; ++o)
       for (int ci = 0; ci < d.in_c; ++ci)
         for (int p = 0; p < per; ++p)
-          vec[((size_t)o * d.in_c + ci) * N + si[p]] = d.weights[(size_t)o * d.in_c * per + ci * per + p];
+          for (int b : bases)
+            vec[((size_t)o * d.in_c + ci) * N + b + si[p]] = d.weights[(size_t)o * d.in_c * per + ci * per + p];
     BCN_HIP(hipMalloc(&L->ptv_hat, (size_t)d.out_c * d.in_c * level * N * sizeof(double)));
     c.arena->reset();
     encode_plain_ntt(c, vec.data(), d.out_c * d.in_c, level, L->ptv_hat, nullptr);
     L->span = next_pow2(maxs + 1);
     if (L->span < 2) L->span = 2;
+    if (L->span > extent) throw Error(-1, "sum span beyond the image block");
     for (int r = L->span / 2; r >= 1; r /= 2) L->all_steps.push_back(r);
     if (d.has_features) throw Error(-1, "features are supported on convolutions");
   }

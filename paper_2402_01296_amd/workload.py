@@ -5,6 +5,8 @@ Slot layouts (client-side data placement):
   batch packing: one ciphertext per crop pixel (c, y, x); slot b = image b.
   HW packing: one ciphertext per channel; crop pixel (y, x) at slot row*y + x
   of slot row 0, with row the crop width.
+  BHW packing: HW packing of `batch` images per ciphertext, image b's block
+  starting at slot image_base(b, block, N).
 Every homomorphic step is a call into libbcn.
 """
 from __future__ import annotations
@@ -21,7 +23,8 @@ def layer_descs(name: str):
     """Layer descriptions of a workload's ciphertext branch (dicts for bcn.Layer)."""
     wl = W.WORKLOADS[name]
     shapes = W.layer_shapes(name)
-    hw = wl["packing"] == "hw"
+    hw = wl["packing"] in ("hw", "bhw")
+    bhw = dict(batch=wl["batch"], block=wl["block"]) if wl["packing"] == "bhw" else {}
     row = wl["crop"][1]
     ps = 1
     spatial = True
@@ -39,6 +42,8 @@ def layer_descs(name: str):
                      pad=lay["pad"], row=row, pos_stride=ps, features=lay.get("features", False),
                      sum=conv_sum)
             if hw:
+                d.update(bhw)
+            if hw:
                 ps *= lay["stride"]
                 if lay.get("sum"):
                     spatial = False
@@ -52,7 +57,7 @@ def layer_descs(name: str):
             if hw and spatial:
                 c, h, w = shapes[li - 1][1]
                 d.update(kind=bcn.BCN_DENSE, packing=bcn.BCN_PACK_HW, in_c=c, in_h=h, in_w=w,
-                         out_c=lay["out"], row=row, pos_stride=ps)
+                         out_c=lay["out"], row=row, pos_stride=ps, **bhw)
                 spatial = False
             else:
                 d.update(kind=bcn.BCN_DENSE, packing=bcn.BCN_PACK_BATCH, in_c=inp[0], in_h=1, in_w=1,
@@ -93,14 +98,7 @@ class GpuSession:
             lay = self.ctx.layer(d, level)
             self.layers.append(lay)
             level = lay.level_out
-        self.features = []
-        for li, f in enumerate(self.inputs["features"]):
-            if f is None:
-                self.features.append(None)
-            elif self.wl["packing"] == "batch":
-                self.features.append(torch.from_numpy(np.ascontiguousarray(f.reshape(f.shape[0], -1))).cuda())
-            else:
-                self.features.append(torch.from_numpy(np.ascontiguousarray(f)).cuda())
+        self.features = self.request_features(self.inputs)
         self.steps = sorted({s for lay in self.layers for s in lay.steps})
         self._keygen()
 
@@ -139,9 +137,16 @@ class GpuSession:
             return out
         c = crop.shape[1]
         out = np.zeros((c, n), dtype=np.int64)
-        for ch in range(c):
-            out[ch, :size * size] = crop[0, ch].reshape(-1)
+        for b, base in enumerate(self.image_bases()):
+            for ch in range(c):
+                out[ch, base:base + size * size] = crop[b, ch].reshape(-1)
         return out
+
+    def image_bases(self):
+        """First slot of each image's block (HW: one image at slot 0)."""
+        if self.wl["packing"] != "bhw":
+            return [0]
+        return [W.image_base(b, self.wl["block"], self.n) for b in range(self.wl["batch"])]
 
     def encryption_randomness(self, indices, level=None):
         level = self.ctx.L if level is None else level
@@ -188,6 +193,9 @@ class GpuSession:
                 out.append(None)
             elif self.wl["packing"] == "batch":
                 out.append(self.torch.from_numpy(np.ascontiguousarray(f.reshape(f.shape[0], -1))).cuda())
+            elif self.wl["packing"] == "bhw":
+                # per image [batch][C][h][w] -> the layer's [C][batch][h][w]
+                out.append(self.torch.from_numpy(np.ascontiguousarray(f.transpose(1, 0, 2, 3))).cuda())
             else:
                 out.append(self.torch.from_numpy(np.ascontiguousarray(f)).cuda())
         return out
@@ -217,4 +225,4 @@ class GpuSession:
         vals = self.ctx.decrypt(self.sk, ct)
         if self.wl["packing"] == "batch":
             return vals[:, :self.wl["batch"]].T
-        return vals[:, 0][None, :]
+        return vals[:, self.image_bases()].T

@@ -12,6 +12,9 @@ Layer entries:
   For 'hw' packing a conv output (y, x) lives at the slot of its top-left tap,
   so a strided conv leaves its outputs spread at the stride; 'sum' on a layer
   asks for a global sum of each output map (sum pooling over all positions).
+  'bhw' packing (appendix "Implementation Details", BHW packing) puts `batch`
+  images' h x w crops into one ciphertext per channel: image b's block starts
+  at slot image_base(b, block, N) and is laid out as in 'hw' packing.
 """
 from __future__ import annotations
 
@@ -73,12 +76,32 @@ WORKLOADS = {
     "cfg1_small": dict(params="t1k5", packing="hw", batch=1, image=(1, 28, 28), crop=(8, 12),
                        layers=[dict(kind="conv", out=2, k=5, stride=2, pad=0, bound=7, features=False, square=True),
                                dict(kind="dense", out=3, bound=7, square=False)]),
+    # CIFAR-shaped branch with BHW packing: 64 images per ciphertext, one 256-slot block per image
+    "cfg3_bhw": dict(params="cfg3", packing="bhw", batch=64, block=256, image=(3, 32, 32), crop=(8, 16),
+                     sum_after_dense=True,
+                     layers=[dict(kind="conv", out=32, k=3, stride=1, pad=0, bound=31, features=True, square=True),
+                             dict(kind="conv", out=64, k=3, stride=2, pad=0, bound=31, features=True, square=True,
+                                  sum=True),
+                             dict(kind="dense", out=10, bound=31, square=False)]),
     "cfg3_small": dict(params="t2k3", packing="hw", batch=1, image=(3, 32, 32), crop=(8, 16), sum_after_dense=True,
                        layers=[dict(kind="conv", out=3, k=3, stride=1, pad=0, bound=31, features=True, square=True),
                                dict(kind="conv", out=2, k=3, stride=2, pad=0, bound=31, features=True, square=True,
                                     sum=True),
                                dict(kind="dense", out=3, bound=31, square=False)]),
+    "cfg3_bhw_small": dict(params="t2k3", packing="bhw", batch=8, block=256, image=(3, 32, 32), crop=(8, 16),
+                           sum_after_dense=True,
+                           layers=[dict(kind="conv", out=3, k=3, stride=1, pad=0, bound=31, features=True,
+                                        square=True),
+                                   dict(kind="conv", out=2, k=3, stride=2, pad=0, bound=31, features=True,
+                                        square=True, sum=True),
+                                   dict(kind="dense", out=3, bound=31, square=False)]),
 }
+
+
+def image_base(b: int, block: int, n: int) -> int:
+    """First slot of image b's block in BHW packing: blocks fill slot row 0, then row 1."""
+    per_row = (n // 2) // block
+    return (b % per_row) * block + (b // per_row) * (n // 2)
 
 
 def layer_shapes(name: str):
@@ -134,7 +157,7 @@ def make_inputs(name: str, seeds=SEEDS):
         weights.append(int_weights(seeds["weights"], li, weight_shape(name, li), lay["bound"]))
         if lay.get("features"):
             fs = feature_shape(name, li)
-            shape = (w["batch"],) + fs if w["packing"] == "batch" else fs
+            shape = (w["batch"],) + fs if w["packing"] in ("batch", "bhw") else fs
             feats.append(_features(seeds["features"], li, shape))
         else:
             feats.append(None)

@@ -148,3 +148,16 @@ def test_cfg3_full_decrypts_to_network(cfg3_gpu):
     vals = g.output_values(out)
     want = network.run_mod_t("cfg3", g.inputs, g.ctx.t)
     assert (vals == want).all()
+
+
+def test_cfg3_bhw_full_decrypts_to_network():
+    """BHW packing at full size: 64 CIFAR-shaped images per ciphertext; every image's ten
+    outputs equal its integer network mod t."""
+    torch_cuda()
+    from paper_2402_01296_amd.workload import GpuSession
+    g = GpuSession("cfg3_bhw")
+    out = g.run(g.encrypt_inputs())
+    vals = g.output_values(out)
+    want = network.run_mod_t("cfg3_bhw", g.inputs, g.ctx.t)
+    assert vals.shape == (64, 10)
+    assert (vals == want).all()

@@ -11,7 +11,7 @@ from gpu_util import torch_cuda
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("name", ["cfg1_small", "cfg2_small", "cfg3_small"])
+@pytest.mark.parametrize("name", ["cfg1_small", "cfg2_small", "cfg3_small", "cfg3_bhw_small"])
 def test_program_parity(name):
     torch_cuda()
     from paper_2402_01296_amd.workload import GpuSession
@@ -40,7 +40,7 @@ def test_program_parity(name):
 
 def _oracle_layer(O, li, cts):
     info = O.plan["layers"][li]
-    hw = O.wl["packing"] == "hw"
+    hw = O.wl["packing"] in ("hw", "bhw")
     if info["kind"] == "conv":
         return O.conv_hw(li, cts) if hw else O.conv_batch(li, cts)
     if hw and "in_slots" in info:
