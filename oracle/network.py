@@ -82,6 +82,10 @@ def run(name: str, inputs, images=None, t=None):
                 x = _red(x.reshape(x.shape[0], x.shape[1], -1).sum(axis=2), t)
         else:
             x = dense(x.reshape(x.shape[0], -1), w, t)
+            f = inputs["features"][li]
+            if f is not None:
+                # plaintext terms of the integration layer's ciphertext neurons (batch packing)
+                x = _red(x + quantise(f[idx]).astype(dt), t)
             if lay["square"]:
                 x = _red(x * x, t)
     return x

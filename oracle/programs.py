@@ -26,7 +26,7 @@ import numpy as np
 import synthetic
 from synthetic import workloads as W
 
-from . import bfv, network, params
+from . import bfv, network, params, plain
 from .encoder import BatchEncoder
 
 RELIN_KEY_ID = W.RELIN_KEY_ID
@@ -95,7 +95,9 @@ def plan(name: str):
 class OracleSession:
     """Keys, encryptions and evaluation of one workload on the oracle."""
 
-    def __init__(self, name: str, seeds=None, with_galois=True):
+    def __init__(self, name: str, seeds=None, with_galois=True, plain_features=None):
+        """plain_features: FP32 outputs 'z1', 'u1', 'u2' of the plaintext side for a workload with
+        a plaintext branch (default: the FP64 reference of oracle.plain, rounded to FP32)."""
         self.name = name
         self.wl = W.WORKLOADS[name]
         self.prm = params.get(self.wl["params"])
@@ -112,6 +114,11 @@ class OracleSession:
             for r in self.plan["steps"]:
                 self.gk[r] = self.galois(r)
         self.inputs = W.make_inputs(name, self.seeds)
+        if "plain" in self.inputs:
+            if plain_features is None:
+                ref = plain.run(name, self.inputs)
+                plain_features = {k: ref[k].astype(np.float32) for k in ("z1", "u1", "u2")}
+            self.inputs = W.with_plain_features(self.inputs, name, plain_features)
 
     def key_randomness(self, key_id: int):
         prm = self.prm
@@ -230,6 +237,12 @@ class OracleSession:
         res = {}
         for o in outputs:
             ct = bfv.mac(prm, [cts[i] for i in range(n_in)], [int(x) for x in w[o]])
+            if info.get("features"):
+                # batch packing: slot b gets image b's feature of output o
+                fq = network.quantise(self.inputs["features"][li])[:, o]
+                slots = np.zeros(prm.n, dtype=np.int64)
+                slots[:len(fq)] = fq
+                ct = bfv.add_plain(prm, ct, self.enc.encode(slots))
             ct = self._activation(ct, info)
             if info.get("sum_span"):
                 ct = self.rotate_sum(ct, info["sum_span"])

@@ -61,7 +61,8 @@ def layer_descs(name: str):
                 spatial = False
             else:
                 d.update(kind=bcn.BCN_DENSE, packing=bcn.BCN_PACK_BATCH, in_c=inp[0], in_h=1, in_w=1,
-                         out_c=lay["out"], batch=max(1, wl["batch"]), sum=moved_span)
+                         out_c=lay["out"], batch=max(1, wl["batch"]), sum=moved_span,
+                         features=bool(lay.get("features")))
                 moved_span = 0
         out.append(d)
     return out
@@ -89,6 +90,11 @@ class GpuSession:
         self.sk = self.ctx.secret_key(self.s)
         self.ek = self.ctx.eval_keys()
         self.inputs = W.make_inputs(name, self.seeds)
+        self.plain = None
+        if "plain" in self.inputs:
+            from .plain_branch import PlainBranch
+            self.plain = PlainBranch(name, self.inputs["plain"])
+            self.inputs = self.with_plain(self.inputs)
         self.descs = layer_descs(name)
         for d, w in zip(self.descs, self.inputs["weights"]):
             d["weights"] = w
@@ -123,6 +129,19 @@ class GpuSession:
         for r in self.steps:
             a, e = self.key_randomness(W.rotation_key_id(r))
             self.ctx.keygen(self.sk, self.ek, bcn.BCN_KEY_ROTATION, r, a, e)
+
+    # ------------------------------------------------------------ plaintext side
+    def plain_inputs(self, inputs):
+        """Device images and perturbation of a request (for the plaintext branch)."""
+        torch = self.torch
+        return (torch.from_numpy(np.ascontiguousarray(inputs["images"])).cuda(),
+                torch.from_numpy(np.ascontiguousarray(inputs["plain"]["noise"])).cuda())
+
+    def with_plain(self, inputs):
+        """inputs with the plaintext side's FP32 outputs (computed on the GPU) in the feature
+        slots it feeds (host copies: the integer network reads them too)."""
+        outs = self.plain(*self.plain_inputs(inputs))
+        return W.with_plain_features(inputs, self.name, {k: v.cpu().numpy() for k, v in outs.items()})
 
     # ------------------------------------------------------------ inputs
     def input_slots(self) -> np.ndarray:
@@ -167,6 +186,35 @@ class GpuSession:
             ct = lay(self.ek, ct, self.features[li])
         return ct
 
+    def run_bi(self, ct, images, noise, side_stream):
+        """The whole bi-CryptoNets model for one request: the plaintext branch on `side_stream`
+        in parallel with the ciphertext branch on the current stream.  Ciphertext layer 1 waits
+        for z1 only; the integration layers wait for u1, u2.  Returns the output ciphertexts."""
+        torch = self.torch
+        cur = torch.cuda.current_stream()
+        side_stream.wait_stream(cur)
+        with torch.cuda.stream(side_stream):
+            h1, z1 = self.plain.first(images, noise)
+            ev1 = torch.cuda.Event()
+            ev1.record(side_stream)
+            u1, u2 = self.plain.rest(h1)
+            ev2 = torch.cuda.Event()
+            ev2.record(side_stream)
+        feats = {}
+        for li, key in W.plain_feature_layers(self.name).items():
+            feats[li] = key
+        out = {"z1": z1.reshape(z1.shape[0], -1), "u1": u1, "u2": u2}
+        for li, lay in enumerate(self.layers):
+            f = self.features[li]
+            if li in feats:
+                cur.wait_event(ev1 if feats[li] == "z1" else ev2)
+                f = out[feats[li]]
+            ct = lay(self.ek, ct, f)
+        # the side stream's tensors were used on this stream
+        for t in (z1, u1, u2):
+            t.record_stream(cur)
+        return ct
+
     # ------------------------------------------------------------ independent requests
     def request_seeds(self, rid: int) -> dict:
         """Seeds of request rid: the model's keys and weights, the request's own data."""
@@ -175,7 +223,8 @@ class GpuSession:
         return s
 
     def request_inputs(self, rid: int):
-        return W.make_inputs(self.name, self.request_seeds(rid))
+        inputs = W.make_inputs(self.name, self.request_seeds(rid))
+        return self.with_plain(inputs) if self.plain is not None else inputs
 
     def request_slots(self, inputs) -> np.ndarray:
         saved = self.inputs

@@ -29,6 +29,8 @@ PURPOSES = {
     "feat": 8,      # FP32 plaintext-branch features (layer index)
     "req": 9,       # request mix / arrival times of the batched workloads
     "poly": 10,     # generic test polynomials
+    "pw": 11,       # FP32 weights of the plaintext branch and the integration layer (tensor index)
+    "pnoise": 12,   # Gaussian perturbation of the insensitive segment (image index range)
 }
 
 SIGMA = 3.2          # standard deviation of the error distribution
@@ -85,3 +87,13 @@ def features(seed: int, layer: int, shape) -> np.ndarray:
 def test_poly(seed: int, index: int, moduli, n: int) -> np.ndarray:
     """Generic uniform RNS test polynomial; uint64 [len(moduli)][n]."""
     return uniform_residues(seed, "poly", (index,), moduli, n)
+
+
+def float_weights(seed: int, index: int, shape, scale: float) -> np.ndarray:
+    """FP32 weights uniform in [-scale, scale]; float32 of the given shape."""
+    return (rng(seed, "pw", index).uniform(-1.0, 1.0, size=shape) * scale).astype(np.float32)
+
+
+def perturbation(seed: int, shape, sigma: float) -> np.ndarray:
+    """Gaussian perturbation N(0, sigma^2) on the uint8 pixel scale; float32 of the given shape."""
+    return rng(seed, "pnoise").normal(0.0, sigma, size=shape).astype(np.float32)

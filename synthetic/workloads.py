@@ -15,6 +15,15 @@ Layer entries:
   'bhw' packing (appendix "Implementation Details", BHW packing) puts `batch`
   images' h x w crops into one ciphertext per channel: image b's block starts
   at slot image_base(b, block, N) and is laid out as in 'hw' packing.
+
+A workload with a 'plain' entry is the whole bi-CryptoNets model (section "Our
+bi-CryptoNets"): an FP32 plaintext branch on the image with the sensitive crop
+zeroed and the rest perturbed, whose layer-1 map is resized (centre crop) and
+channel-rotated (1x1 mix) into the features of ciphertext layer 1 (features =
+"plain"), and a two-layer feature integration whose ciphertext neurons are the
+last two dense layers (integration 1, 2): their plaintext-branch terms
+W_p1 x_p + b_1 and W_p2 x_p^<1> + b_2 enter as features, x_p^<1> being the
+plaintext neurons (section "The feature integration").
 """
 from __future__ import annotations
 
@@ -35,6 +44,8 @@ PARAMS = {
     "t1k5": dict(n=1024, bits=30, L=5, K=1, alpha=1, t=65537, insecure=True),
     "t2k3": dict(n=2048, bits=40, L=6, K=2, alpha=2, t=65537, insecure=True),
     "t4k": dict(n=4096, bits=36, L=4, K=1, alpha=1, t=40961, insecure=True),
+    # the MNIST-shaped branch plus the feature-integration layers: one more prime of noise budget
+    "cfg2i": dict(n=8192, bits=36, L=5, K=1, alpha=1, t=1032193),
 }
 
 # key ids of the key-switching-key randomness streams
@@ -83,6 +94,23 @@ WORKLOADS = {
                              dict(kind="conv", out=64, k=3, stride=2, pad=0, bound=31, features=True, square=True,
                                   sum=True),
                              dict(kind="dense", out=10, bound=31, square=False)]),
+    # the whole bi-CryptoNets model on the MNIST-shaped batch (ciphertext branch as in cfg2)
+    "cfg2_bi": dict(params="cfg2i", packing="batch", batch=8192, image=(1, 28, 28), crop=(6, 16),
+                    plain=dict(ch1=8, k1=5, stride1=2, pad1=1, ch2=8, k2=3, stride2=2, noise=16.0),
+                    layers=[dict(kind="conv", out=5, k=5, stride=2, pad=1, bound=15, features="plain", square=True),
+                            dict(kind="dense", out=100, bound=15, square=True),
+                            dict(kind="dense", out=10, bound=15, square=False),
+                            dict(kind="dense", out=8, bound=7, features="plain", square=True, integration=1),
+                            dict(kind="dense", out=10, bound=7, features="plain", square=False, integration=2)]),
+    "cfg2_bi_small": dict(params="t1k5", packing="batch", batch=512, image=(1, 28, 28), crop=(6, 16),
+                          plain=dict(ch1=4, k1=5, stride1=2, pad1=1, ch2=4, k2=3, stride2=2, noise=16.0),
+                          layers=[dict(kind="conv", out=2, k=5, stride=2, pad=1, bound=15, features="plain",
+                                       square=True),
+                                  dict(kind="dense", out=7, bound=15, square=True),
+                                  dict(kind="dense", out=3, bound=15, square=False),
+                                  dict(kind="dense", out=4, bound=7, features="plain", square=True, integration=1),
+                                  dict(kind="dense", out=3, bound=7, features="plain", square=False,
+                                       integration=2)]),
     "cfg3_small": dict(params="t2k3", packing="hw", batch=1, image=(3, 32, 32), crop=(8, 16), sum_after_dense=True,
                        layers=[dict(kind="conv", out=3, k=3, stride=1, pad=0, bound=31, features=True, square=True),
                                dict(kind="conv", out=2, k=3, stride=2, pad=0, bound=31, features=True, square=True,
@@ -146,19 +174,76 @@ def feature_shape(name: str, li: int):
     return layer_shapes(name)[li][1]
 
 
+def plain_shapes(name: str):
+    """Shapes of the FP32 plaintext-branch and integration parameters, and its map sizes."""
+    w = WORKLOADS[name]
+    p = w["plain"]
+    c, h, _ = w["image"]
+    s1 = (h + 2 * p["pad1"] - p["k1"]) // p["stride1"] + 1
+    s2 = (s1 - p["k2"]) // p["stride2"] + 1
+    out1 = w["layers"][0]["out"]
+    oh = layer_shapes(name)[0][1][1]
+    n_half = [lay for lay in w["layers"] if lay.get("integration") == 1][0]["out"]
+    n_out = [lay for lay in w["layers"] if lay.get("integration") == 2][0]["out"]
+    n_p = p["ch2"] * s2 * s2
+    return dict(
+        tensors=dict(w1=(p["ch1"], c, p["k1"], p["k1"]), b1=(p["ch1"],), crot=(out1, p["ch1"]),
+                     w2=(p["ch2"], p["ch1"], p["k2"], p["k2"]), b2=(p["ch2"],),
+                     wpp=(n_half, n_p), bpp=(n_half,), wpc=(n_half, n_p), bpc=(n_half,),
+                     wo=(n_out, n_half), bo=(n_out,)),
+        fan_in=dict(w1=c * p["k1"] ** 2, crot=p["ch1"], w2=p["ch1"] * p["k2"] ** 2, wpp=n_p, wpc=n_p, wo=n_half),
+        # weights uniform in +-gain/sqrt(fan_in): the features reach a few units before quantisation
+        gain=dict(w1=1.0, crot=16.0, w2=1.0, wpp=4.0, wpc=16.0, wo=16.0),
+        s1=s1, s2=s2, n_p=n_p, resize=(s1 - oh) // 2, out_hw=oh)
+
+
+def plain_feature_layers(name: str) -> dict:
+    """Layer index -> which plaintext-side output feeds it: 'z1' (ciphertext layer 1),
+    'u1' / 'u2' (the two integration layers)."""
+    out = {}
+    for li, lay in enumerate(WORKLOADS[name]["layers"]):
+        if lay.get("features") == "plain":
+            out[li] = {None: "z1", 1: "u1", 2: "u2"}[lay.get("integration")]
+    return out
+
+
+def with_plain_features(inputs: dict, name: str, outs: dict) -> dict:
+    """A copy of inputs whose plaintext-fed feature slots hold the given FP32 arrays
+    (outs: 'z1', 'u1', 'u2' -> [B][...] arrays)."""
+    feats = list(inputs["features"])
+    for li, key in plain_feature_layers(name).items():
+        feats[li] = outs[key]
+    return dict(inputs, features=feats)
+
+
 def make_inputs(name: str, seeds=SEEDS):
-    """All raw inputs of a workload: images, weights and features."""
-    from . import images as _images, int_weights, features as _features
+    """All raw inputs of a workload: images, weights and features.  Features that the
+    plaintext branch produces (features = "plain") are left None; inputs["plain"] then
+    holds that branch's FP32 parameters and perturbation."""
+    from . import images as _images, int_weights, features as _features, float_weights, perturbation
     w = WORKLOADS[name]
     c, h, wd = w["image"]
     imgs = _images(seeds["images"], w["batch"], h, wd, c)
     weights, feats = [], []
+    plain = None
+    if "plain" in w:
+        ps = plain_shapes(name)
+        plain = {}
+        for i, (k, shape) in enumerate(sorted(ps["tensors"].items())):
+            fan = ps["fan_in"].get(k)
+            plain[k] = float_weights(seeds["weights"], i, shape, ps["gain"][k] / fan ** 0.5 if fan else 0.1)
+        plain["noise"] = perturbation(seeds["images"], (w["batch"], c, h, wd), w["plain"]["noise"])
     for li, lay in enumerate(w["layers"]):
         weights.append(int_weights(seeds["weights"], li, weight_shape(name, li), lay["bound"]))
-        if lay.get("features"):
+        if lay.get("features") == "plain":
+            feats.append(None)
+        elif lay.get("features"):
             fs = feature_shape(name, li)
             shape = (w["batch"],) + fs if w["packing"] in ("batch", "bhw") else fs
             feats.append(_features(seeds["features"], li, shape))
         else:
             feats.append(None)
-    return dict(images=imgs, weights=weights, features=feats)
+    out = dict(images=imgs, weights=weights, features=feats)
+    if plain is not None:
+        out["plain"] = plain
+    return out

@@ -161,3 +161,19 @@ def test_cfg3_bhw_full_decrypts_to_network():
     want = network.run_mod_t("cfg3_bhw", g.inputs, g.ctx.t)
     assert vals.shape == (64, 10)
     assert (vals == want).all()
+
+
+def test_cfg2_bi_full_decrypts_to_network():
+    """The whole bi-CryptoNets model on 8192 MNIST-shaped images (plaintext branch on a side
+    stream, ciphertext branch, feature integration): Dec(Eval) equals the integer network for
+    every image, on five 36-bit primes."""
+    torch = torch_cuda()
+    from paper_2402_01296_amd.workload import GpuSession
+    g = GpuSession("cfg2_bi")
+    g.autotune()
+    images, noise = g.plain_inputs(g.inputs)
+    out = g.run_bi(g.encrypt_inputs(), images, noise, torch.cuda.Stream())
+    vals = g.output_values(out)
+    want = network.run_mod_t("cfg2_bi", g.inputs, g.ctx.t)
+    assert vals.shape == (8192, 10)
+    assert (vals == want).all()

@@ -11,12 +11,16 @@ from gpu_util import torch_cuda
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("name", ["cfg1_small", "cfg2_small", "cfg3_small", "cfg3_bhw_small"])
+@pytest.mark.parametrize("name", ["cfg1_small", "cfg2_small", "cfg3_small", "cfg3_bhw_small", "cfg2_bi_small"])
 def test_program_parity(name):
     torch_cuda()
     from paper_2402_01296_amd.workload import GpuSession
+    from synthetic import workloads as W
     g = GpuSession(name)
-    O = programs.OracleSession(name)
+    # a plaintext branch's FP32 outputs are inputs of the ciphertext branch: both sides take the
+    # same ones (the plaintext branch itself is checked against its FP64 reference)
+    pf = {key: g.inputs["features"][li] for li, key in W.plain_feature_layers(name).items()} or None
+    O = programs.OracleSession(name, plain_features=pf)
     assert g.steps == O.plan["steps"]
     ct = g.encrypt_inputs()
     ref_in = O.encrypt_inputs()
@@ -46,3 +50,30 @@ def _oracle_layer(O, li, cts):
     if hw and "in_slots" in info:
         return O.dense_hw(li, cts)
     return O.dense_scalar(li, cts)
+
+
+def test_bi_model_overlapped_equals_serial_and_network():
+    """The whole bi-CryptoNets model: plaintext branch (FP32) on a side stream in parallel with
+    the ciphertext branch; the same ciphertexts as the serial run, the plaintext side within FP32
+    rounding of its FP64 reference, and Dec(Eval) equal to the integer network mod t."""
+    torch = torch_cuda()
+    from oracle import plain
+    from paper_2402_01296_amd.workload import GpuSession
+    name = "cfg2_bi_small"
+    g = GpuSession(name)
+    ref = plain.run(name, g.inputs)
+    outs = g.plain(*g.plain_inputs(g.inputs))
+    for k in ("z1", "u1", "u2"):
+        a = outs[k].cpu().numpy().astype(np.float64)
+        assert np.abs(a - ref[k]).max() <= 1e-4 * max(1.0, np.abs(ref[k]).max()), k
+    ct = g.encrypt_inputs()
+    serial = g.run(ct)
+    side = torch.cuda.Stream()
+    images, noise = g.plain_inputs(g.inputs)
+    for _ in range(2):
+        over = g.run_bi(ct, images, noise, side)
+        torch.cuda.synchronize()
+        assert bool((over == serial).all())
+    vals = g.output_values(over)
+    want = network.run_mod_t(name, g.inputs, g.ctx.t)
+    assert (vals == want).all()

@@ -49,7 +49,7 @@ def test_mod_t_network_equals_exact_network(name):
     assert (np.where(2 * ex > t, ex - t, ex) == red).all()
 
 
-@pytest.mark.parametrize("name", ["cfg1_small", "cfg2_small", "cfg3_small", "cfg3_bhw_small"])
+@pytest.mark.parametrize("name", ["cfg1_small", "cfg2_small", "cfg3_small", "cfg3_bhw_small", "cfg2_bi_small"])
 def test_dec_eval_equals_network(name):
     S = programs.OracleSession(name)
     out = S.run(S.encrypt_inputs())
@@ -84,3 +84,52 @@ def test_workload1_first_layer_and_noise_floor():
     sq = bfv.square(S.prm, A, S.rk)
     m_exp = S.enc.encode(want * want % t)
     assert bfv.noise_budget(S.prm, S.s, sq, m_exp) <= 0
+
+
+def test_plain_reference_conv_is_the_integer_conv():
+    """The plaintext-side reference's convolution equals the integer network's convolution
+    (brute-force definition) on integer inputs, bias zero."""
+    from oracle import plain
+    rng = np.random.default_rng(3)
+    x = rng.integers(0, 256, (2, 3, 11, 11))
+    w = rng.integers(-7, 8, (4, 3, 5, 5))
+    for stride, pad in [(1, 0), (2, 1)]:
+        got = plain._conv(x.astype(np.float64), w.astype(np.float64), None, stride, pad)
+        want = np.stack([network.conv2d(x[b].astype(object), w, stride, pad) for b in range(2)]).astype(np.float64)
+        assert (got == want).all()
+
+
+def test_plain_branch_fp32_matches_fp64_reference():
+    """The FP32 plaintext side (torch ops, here on the CPU) against the FP64 reference:
+    resize = centre crop aligned with ciphertext layer 1, CRot, plaintext neurons."""
+    torch = pytest.importorskip("torch")
+    from oracle import plain
+    from paper_2402_01296_amd import plain_branch
+    name = "cfg2_bi_small"
+    inp = W.make_inputs(name)
+    ref = plain.run(name, inp)
+
+    class OnCpu(plain_branch.PlainBranch):
+        def __init__(self, nm, params):
+            self.torch = torch
+            self.wl = W.WORKLOADS[nm]
+            self.p = self.wl["plain"]
+            self.sp = W.plain_shapes(nm)
+            self.w = {k: torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32))
+                      for k, v in params.items() if k != "noise"}
+
+    out = OnCpu(name, inp["plain"])(torch.from_numpy(inp["images"]), torch.from_numpy(inp["plain"]["noise"]))
+    for k in ("z1", "u1", "u2"):
+        a = out[k].numpy().astype(np.float64)
+        assert a.shape == ref[k].shape
+        assert np.abs(a - ref[k]).max() <= 1e-5 * max(1.0, np.abs(ref[k]).max()), k
+    # the centre crop of layer 1 lines up with ciphertext layer 1's outputs: output (i, j) of both
+    # convolutions is centred on the same image pixel
+    sp = W.plain_shapes(name)
+    wl = W.WORKLOADS[name]
+    lay, p = wl["layers"][0], wl["plain"]
+    y0 = wl["crop"][0]
+    for i in (0, sp["out_hw"] - 1):
+        c_cipher = y0 + lay["stride"] * i - lay["pad"] + lay["k"] // 2
+        c_plain = p["stride1"] * (i + sp["resize"]) - p["pad1"] + p["k1"] // 2
+        assert c_cipher == c_plain
