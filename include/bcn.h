@@ -163,7 +163,8 @@ int bcn_rotate_sum(bcn_context* ctx, const bcn_eval_keys* ek, double* ct, int n,
 int bcn_modswitch(bcn_context* ctx, const double* in, double* out, int n, int level, bcn_stream stream);
 
 /* ---- layers ---- */
-enum { BCN_CONV2D = 0, BCN_DENSE = 1 };
+enum { BCN_CONV2D = 0, BCN_DENSE = 1, BCN_POOL = 2 };
+enum { BCN_DENSE_WEIGHT_VECTORS = 0, BCN_DENSE_DIAGONAL = 1 };
 enum { BCN_PACK_BATCH = 0, BCN_PACK_HW = 1 };
 
 /* One layer of the ciphertext branch: linear part, then (HW conv) the mask of
@@ -184,7 +185,16 @@ enum { BCN_PACK_BATCH = 0, BCN_PACK_HW = 1 };
  *   outputs at slots pos_stride*stride*(row*i + j) with a mask; DENSE weights
  *   w[o][c*in_h*in_w + y*in_w + x] multiply the slot of (y, x) of input c,
  *   products are summed and then summed over slots (rotate-and-sum), leaving
- *   out[o] in slot 0.
+ *   out[o] in slot 0.  DENSE with method BCN_DENSE_DIAGONAL (appendix
+ *   "Implementation Details", fully connected layer): each input channel holds
+ *   its n1 = in_h*in_w inputs at slots 0..n1-1 (pos_stride 1, in_w = row or
+ *   in_h = 1); for r = 1-n2 .. n1-1 (n2 = out_c; n1 + n2 - 1 hoisted rotations)
+ *   Rot(in[c], r) is multiplied by the vector whose slot j holds
+ *   w[j][c*n1 + j + r] (0 where j + r falls outside 0..n1-1) and everything is
+ *   summed: one output ciphertext with out[j] in slot j.  POOL (local sum
+ *   pooling, "similar to the convolution without weights"): channel by channel,
+ *   the sum of each k x k window at the stride, then the mask; in_c = out_c,
+ *   weights unused.
  * Features (has_features): FP32 device array; q(f) = clamp(rint(scale f),
  *   -clamp, clamp) in FP32 arithmetic is added as a plaintext.  BATCH: layout
  *   [batch][n_out] (image-major); HW: [out_c][oh][ow]; BHW: [out_c][batch][oh][ow].
@@ -210,6 +220,7 @@ typedef struct {
                             after the dense layer, which commutes with it) */
   int32_t block;         /* HW: 0 (one image at base 0), or the slot distance between the blocks of
                             `batch` images packed in one ciphertext (BHW packing) */
+  int32_t method;        /* HW DENSE: BCN_DENSE_WEIGHT_VECTORS (default) or BCN_DENSE_DIAGONAL */
 } bcn_layer_desc;
 
 /* Prepares a layer for inputs at `level`: uploads weights, encodes masks and

@@ -50,6 +50,18 @@ def conv2d(x, w, stride: int, pad: int, t=None):
     return _red(out, t)
 
 
+def sum_pool(x, k: int, stride: int, t=None):
+    """Local sum pooling: x [..., C, H, W] -> [..., C, oh, ow], each output the sum of its
+    k x k window (no weights)."""
+    *lead, C, H, Wd = x.shape
+    oh, ow = (H - k) // stride + 1, (Wd - k) // stride + 1
+    out = np.zeros(tuple(lead) + (C, oh, ow), dtype=x.dtype)
+    for i in range(oh):
+        for j in range(ow):
+            out[..., i, j] = x[..., stride * i:stride * i + k, stride * j:stride * j + k].sum(axis=(-2, -1))
+    return _red(out, t)
+
+
 def dense(x, w, t=None):
     """x [..., n_in], w [n_out][n_in] -> [..., n_out]."""
     dt = object if t is None else np.int64
@@ -70,7 +82,9 @@ def run(name: str, inputs, images=None, t=None):
     batch = wl["packing"] in ("batch", "bhw")
     for li, lay in enumerate(wl["layers"]):
         w = inputs["weights"][li]
-        if lay["kind"] == "conv":
+        if lay["kind"] == "pool":
+            x = sum_pool(x, lay["k"], lay["stride"], t)
+        elif lay["kind"] == "conv":
             x = conv2d(x, w, lay["stride"], lay["pad"], t)
             f = inputs["features"][li]
             if f is not None:

@@ -55,7 +55,34 @@ def plan(name: str):
         info = dict(lay)
         info["in_shape"], info["out_shape"] = shapes[li][0], out
         if wl["packing"] in ("hw", "bhw"):
-            if lay["kind"] == "conv":
+            if lay["kind"] == "pool":
+                # local sum pooling: like a convolution without weights (channel by channel)
+                offs = [ps * (row * di + dj) for di in range(lay["k"]) for dj in range(lay["k"])]
+                info["offsets"] = offs
+                steps.update(o for o in offs if o)
+                ps_out = ps * lay["stride"]
+                oh, ow = out[1], out[2]
+                info["out_slots"] = [ps_out * (row * i + j) for i in range(oh) for j in range(ow)]
+                ps = ps_out
+            elif lay["kind"] == "dense" and lay.get("method") == "diag":
+                # diagonal method: n1 + n2 - 1 rotations of the input (n1 inputs per channel).  With the
+                # outputs in slots 0..n2-1 the steps are r = i - n2, i = 1 .. n1 + n2 - 1, i.e. 1 - n2 .. n1 - 1
+                # (the mirror of the printed range n2 - 1 .. 1 - n1, which leaves the outputs at the top
+                # of the input range instead)
+                # inputs per channel at slots 0..n1-1: the image crop (row = crop width, so the
+                # pixels are contiguous) or the previous diagonal layer's outputs
+                if li == 0:
+                    n1 = row * row
+                elif layers[-1].get("method") == "diag":
+                    n1 = layers[-1]["out"]
+                else:
+                    raise ValueError("the diagonal method needs its inputs at slots 0..n1-1")
+                n2 = lay["out"]
+                info["diag_n1"] = n1
+                info["diag_steps"] = [i - n2 for i in range(1, n1 + n2)]
+                steps.update(r for r in info["diag_steps"] if r)
+                spatial = False
+            elif lay["kind"] == "conv":
                 offs = [ps * (row * di + dj) for di in range(lay["k"]) for dj in range(lay["k"])]
                 info["offsets"] = offs
                 steps.update(o for o in offs if o)
@@ -286,6 +313,43 @@ class OracleSession:
             res[o] = ct
         return res
 
+    def pool_hw(self, li: int, cts: dict) -> dict:
+        """Local sum pooling, channel by channel: rotations by the window offsets, summed,
+        then the mask of the strided outputs (appendix "Implementation Details", pooling
+        layer: a convolution without weights)."""
+        prm, info = self.prm, self.plan["layers"][li]
+        mask = self.enc.encode(self.mask_slots(li))
+        res = {}
+        for c in sorted(cts):
+            taps = self.rotated_input(li, cts[c])
+            res[c] = bfv.mul_plain(prm, bfv.mac(prm, taps, [1] * len(taps)), mask)
+        return res
+
+    def dense_diag(self, li: int, cts: dict) -> dict:
+        """Fully connected layer by the diagonal method (appendix "Implementation Details"):
+        channel c holds its n1 inputs at slots 0..n1-1; for i = 1 .. n1 + n2 - 1 the input is
+        rotated by r = i - n2 and multiplied by the weight vector whose slot j is W[j][c*n1 + j + r]
+        (0 where j + r is outside 0..n1-1); the products are summed.  Output j lands in slot j."""
+        prm, info = self.prm, self.plan["layers"][li]
+        w = self.inputs["weights"][li]
+        n2 = w.shape[0]
+        n1 = info["diag_n1"]
+        acc = None
+        for c in sorted(cts):
+            nz = [r for r in info["diag_steps"] if r]
+            table = dict(zip(nz, bfv.rotate_hoisted(prm, cts[c], nz, [self.gk[r] for r in nz])))
+            table[0] = cts[c]
+            for r in info["diag_steps"]:
+                v = np.zeros(prm.n, dtype=np.int64)
+                for j in range(n2):
+                    if 0 <= j + r < n1:
+                        v[j] = w[j, c * n1 + j + r]
+                if not v.any():
+                    continue
+                term = bfv.mul_plain(prm, table[r], self.enc.encode(v))
+                acc = term if acc is None else bfv.add(prm, acc, term)
+        return {0: self._activation(acc, info)}
+
     def dense_hw(self, li: int, cts: dict, outputs=None) -> dict:
         prm, info = self.prm, self.plan["layers"][li]
         w = self.inputs["weights"][li]
@@ -327,7 +391,12 @@ class OracleSession:
         hw = self.wl["packing"] in ("hw", "bhw")
         spatial = True
         for li, info in enumerate(self.plan["layers"]):
-            if info["kind"] == "conv":
+            if info["kind"] == "pool":
+                cts = self.pool_hw(li, cts)
+            elif info.get("method") == "diag":
+                cts = self.dense_diag(li, cts)
+                spatial = False
+            elif info["kind"] == "conv":
                 cts = self.conv_hw(li, cts) if hw else self.conv_batch(li, cts)
                 if info.get("sum"):
                     spatial = False
@@ -340,7 +409,11 @@ class OracleSession:
 
     def output_values(self, outs: dict) -> np.ndarray:
         """Decrypted network outputs: batch -> [batch][n_out]; HW -> [1][n_out] (slot 0);
-        BHW -> [batch][n_out] (the first slot of each image's block)."""
+        BHW -> [batch][n_out] (the first slot of each image's block); after a diagonal-method
+        layer -> [1][n2] (slots 0..n2-1 of its one ciphertext)."""
+        if self.plan["layers"][-1].get("method") == "diag":
+            n2 = self.plan["layers"][-1]["out"]
+            return self.decrypt_slots(outs[0])[None, :n2]
         vals = [self.decrypt_slots(outs[k]) for k in sorted(outs)]
         if self.wl["packing"] == "batch":
             b = self.wl["batch"]

@@ -16,7 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libbcn.so")
 
 BCN_KEY_RELIN, BCN_KEY_ROTATION = 0, 1
-BCN_CONV2D, BCN_DENSE = 0, 1
+BCN_CONV2D, BCN_DENSE, BCN_POOL = 0, 1, 2
+BCN_DENSE_WEIGHT_VECTORS, BCN_DENSE_DIAGONAL = 0, 1
 BCN_PACK_BATCH, BCN_PACK_HW = 0, 1
 BCN_OK, BCN_ERR_INVALID, BCN_ERR_LEVEL, BCN_ERR_KEY, BCN_ERR_NOMEM, BCN_ERR_HIP, BCN_ERR_INTERNAL = 0, -1, -2, -3, -4, -5, -6
 
@@ -38,7 +39,8 @@ class LayerDesc(C.Structure):
                 ("pad", C.c_int32), ("row", C.c_int32), ("pos_stride", C.c_int32),
                 ("weights", C.POINTER(C.c_int32)), ("has_features", C.c_int32), ("feature_scale", C.c_float),
                 ("feature_clamp", C.c_int32), ("batch", C.c_int32), ("square", C.c_int32),
-                ("modswitch", C.c_int32), ("sum", C.c_int32), ("block", C.c_int32)]
+                ("modswitch", C.c_int32), ("sum", C.c_int32), ("block", C.c_int32),
+                ("method", C.c_int32)]
 
 
 _lib = None
@@ -350,7 +352,8 @@ class Layer:
 
     def __init__(self, ctx, desc: dict, level: int):
         self.ctx = ctx
-        w = np.ascontiguousarray(desc["weights"], dtype=np.int32)
+        w = np.ascontiguousarray(desc["weights"] if desc.get("weights") is not None else np.zeros(1),
+                                 dtype=np.int32)
         self._w = w
         d = LayerDesc()
         d.kind = desc["kind"]
@@ -368,6 +371,7 @@ class Layer:
         d.modswitch = 1 if desc.get("modswitch") else 0
         d.sum = int(desc.get("sum") or 0)
         d.block = int(desc.get("block") or 0)
+        d.method = int(desc.get("method") or 0)
         self.desc = d
         h = C.c_void_p()
         _check(lib().bcn_layer_create(ctx.h, C.byref(d), level, C.byref(h)))

@@ -12,6 +12,7 @@ struct Layer {
   int kind = 0, packing = 0, level = 0, level_out = 0;
   int n_in = 0, n_out = 0;
   int oh = 0, ow = 0, k2 = 0;
+  bool diag = false;             // HW dense by the diagonal method (taps as in a convolution)
   bool square = false, modsw = false, features = false;
   float fscale = 8.0f;
   int fclamp = 127;

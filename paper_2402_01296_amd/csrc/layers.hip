@@ -27,6 +27,24 @@ int next_pow2(int x) {
 
 Layer* layer_create(Context& c, const bcn_layer_desc& d, int level) {
   if (level < 1 || level > c.L) throw Error(-2, "bad level");
+  if (d.kind == BCN_POOL) {
+    // local sum pooling = a valid HW convolution whose weights are 1 on the channel itself
+    if (d.packing != BCN_PACK_HW) throw Error(-1, "pooling needs HW packing");
+    if (d.in_c < 1 || d.k < 1) throw Error(-1, "bad pooling shape");
+    std::vector<int32_t> w((size_t)d.in_c * d.in_c * d.k * d.k, 0);
+    for (int ch = 0; ch < d.in_c; ++ch)
+      for (int t = 0; t < d.k * d.k; ++t) w[((size_t)ch * d.in_c + ch) * d.k * d.k + t] = 1;
+    bcn_layer_desc dc = d;
+    dc.kind = BCN_CONV2D;
+    dc.out_c = d.in_c;
+    dc.pad = 0;
+    dc.weights = w.data();
+    dc.has_features = 0;
+    dc.square = 0;
+    dc.modswitch = 0;
+    dc.sum = 0;
+    return layer_create(c, dc, level);
+  }
   if (!d.weights) throw Error(-1, "layer weights missing");
   if (d.in_c < 1 || d.in_h < 1 || d.in_w < 1 || d.out_c < 1) throw Error(-1, "bad layer shape");
   auto L = std::make_unique<Layer>();
@@ -163,6 +181,38 @@ Layer* layer_create(Context& c, const bcn_layer_desc& d, int level) {
       if (L->span > extent) throw Error(-1, "sum span beyond the image block");
       for (int r = L->span / 2; r >= 1; r /= 2) L->all_steps.push_back(r);
     }
+  } else if (d.method == BCN_DENSE_DIAGONAL) {
+    // diagonal method: n1 + n2 - 1 rotations of each input channel (steps 1 - n2 .. n1 - 1), each
+    // multiplied by one weight vector; outputs at slots 0..n2-1 of one ciphertext
+    if (d.block > 0) throw Error(-1, "the diagonal method packs one image");
+    if (d.pos_stride != 1 || (d.in_h > 1 && d.in_w != d.row)) throw Error(-1, "diagonal method needs contiguous inputs");
+    const int n1 = d.in_h * d.in_w, n2 = d.out_c;
+    if (n1 + n2 > half) throw Error(-1, "diagonal method: n1 + n2 must not exceed N/2");
+    std::vector<int> rs;
+    for (int i = 1; i < n1 + n2; ++i) rs.push_back(i - n2);
+    const int k2 = (int)rs.size();
+    std::vector<int> tap_r(k2);        // tap 0 = offset 0, then the nonzero steps in order
+    tap_r[0] = 0;
+    for (int r : rs)
+      if (r != 0) {
+        L->steps.push_back(r);
+        tap_r[L->steps.size()] = r;
+      }
+    L->k2 = k2;
+    L->diag = true;
+    L->n_out = 1;
+    std::vector<int64_t> vec((size_t)d.in_c * k2 * N, 0);
+    for (int ci = 0; ci < d.in_c; ++ci)
+      for (int t = 0; t < k2; ++t) {
+        const int r = tap_r[t];
+        for (int j = 0; j < n2; ++j)
+          if (j + r >= 0 && j + r < n1)
+            vec[((size_t)ci * k2 + t) * N + j] = d.weights[(size_t)j * d.in_c * n1 + ci * n1 + j + r];
+      }
+    BCN_HIP(hipMalloc(&L->ptv_hat, (size_t)d.in_c * k2 * level * N * sizeof(double)));
+    c.arena->reset();
+    encode_plain_ntt(c, vec.data(), d.in_c * k2, level, L->ptv_hat, nullptr);
+    if (d.has_features) throw Error(-1, "features are supported on convolutions");
   } else {
     // dense over spatially laid out channels: weight vectors, then rotate-and-sum
     const int per = d.in_h * d.in_w;
@@ -224,6 +274,14 @@ void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, doub
       mac(c, L.mac, in, A, level, s, R, (size_t)L.n_in * ctw, (size_t)L.n_out * ctq, fm, ctq, ctq / 2);
     else
       mac(c, L.mac, in, A, level, s, R, (size_t)L.n_in * ctw, (size_t)L.n_out * ctw, fm);
+  } else if (L.diag) {
+    // taps [R*n_in][k2] as for a convolution, then all taps times their weight vectors, summed
+    double* taps = ar.take((size_t)nin * L.k2 * ctw);
+    copy_rows(in, ctw, taps, L.k2 * ctw, ctw, nin, s);
+    rotate_hoisted(c, ek, in, nin, level, L.steps, taps + ctw, s, (int)L.steps.size(), L.k2 * ctw);
+    ntt_forward(c, taps, 2 * nin * L.k2, c.basis_Q(level), s);
+    ptvec_mac_ntt(c, taps, L.n_in * L.k2, A, 1, level, L.ptv_hat, s, R);
+    ntt_inverse(c, A, 2 * nout, c.basis_Q(level), s);
   } else if (L.kind == BCN_CONV2D) {
     // taps [R*n_in][k2]: tap 0 = the input, taps 1.. = hoisted rotations
     double* taps = ar.take((size_t)nin * L.k2 * ctw);
@@ -250,7 +308,7 @@ void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, doub
     add_delta(c, A, nout, level, m, s);
   }
   if (direct) return;
-  const bool hw_dense = L.packing == BCN_PACK_HW && L.kind == BCN_DENSE;
+  const bool hw_dense = L.packing == BCN_PACK_HW && L.kind == BCN_DENSE && !L.diag;
   if (hw_dense) {
     // rotate-and-sum before the (optional) square
     rotate_sum(c, ek, A, nout, level, L.span, s);

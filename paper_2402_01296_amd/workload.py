@@ -32,8 +32,22 @@ def layer_descs(name: str):
     out = []
     for li, lay in enumerate(wl["layers"]):
         (inp, outp) = shapes[li]
-        d = dict(square=lay["square"], modswitch=lay["square"], batch=wl["batch"])
-        if lay["kind"] == "conv":
+        d = dict(square=lay.get("square", False), modswitch=lay.get("square", False), batch=wl["batch"])
+        if lay["kind"] == "pool":
+            c, h, w = inp
+            d.update(kind=bcn.BCN_POOL, packing=bcn.BCN_PACK_HW, in_c=c, in_h=h, in_w=w, out_c=c, k=lay["k"],
+                     stride=lay["stride"], pad=0, row=row, pos_stride=ps, **bhw)
+            ps *= lay["stride"]
+        elif lay["kind"] == "dense" and lay.get("method") == "diag":
+            # diagonal method: inputs at slots 0..n1-1 (the crop, or the previous diagonal layer)
+            if li == 0:
+                c, h, w = wl["image"][0], wl["crop"][1], wl["crop"][1]
+            else:
+                c, h, w = 1, 1, out[-1]["out_c"]
+            d.update(kind=bcn.BCN_DENSE, packing=bcn.BCN_PACK_HW, method=bcn.BCN_DENSE_DIAGONAL, in_c=c, in_h=h,
+                     in_w=w, out_c=lay["out"], row=row, pos_stride=1)
+            spatial = False
+        elif lay["kind"] == "conv":
             c, h, w = inp
             # with sum_after_dense the global sum runs after the next (scalar) dense layer
             conv_sum = lay.get("sum", False) and not (hw and wl.get("sum_after_dense"))
@@ -272,6 +286,9 @@ class GpuSession:
 
     def output_values(self, ct) -> np.ndarray:
         vals = self.ctx.decrypt(self.sk, ct)
+        last = self.wl["layers"][-1]
+        if last.get("method") == "diag":
+            return vals[0, :last["out"]][None, :]
         if self.wl["packing"] == "batch":
             return vals[:, :self.wl["batch"]].T
         return vals[:, self.image_bases()].T

@@ -8,7 +8,13 @@ never dataset items.
 
 Layer entries:
   conv  : out channels, kernel k, stride, pad, weight bound, features?, square?
-  dense : out units, weight bound, square?
+  pool  : local sum pooling, window k, stride (no weights; appendix "Implementation
+          Details", pooling layer), channel by channel
+  dense : out units, weight bound, square?; method "diag" (HW packing, input
+          values at slots 0..n1-1 of each channel) uses the diagonal method of the
+          appendix's fully connected layer: n1 + n2 - 1 rotations of the input (steps
+          1 - n2 .. n1 - 1), each multiplied by one weight vector, summed; outputs at
+          slots 0..n2-1
   For 'hw' packing a conv output (y, x) lives at the slot of its top-left tap,
   so a strided conv leaves its outputs spread at the stride; 'sum' on a layer
   asks for a global sum of each output map (sum pooling over all positions).
@@ -111,6 +117,30 @@ WORKLOADS = {
                                   dict(kind="dense", out=4, bound=7, features="plain", square=True, integration=1),
                                   dict(kind="dense", out=3, bound=7, features="plain", square=False,
                                        integration=2)]),
+    # a fully connected branch on one HW-packed 12x12 MNIST-shaped crop by the diagonal method
+    # (on the N = 16384 parameters: each weight-vector product costs about log2(N t / 2) bits of
+    # noise budget, two of them need more than four 36-bit primes)
+    "fc_diag": dict(params="cfg3", packing="hw", batch=1, image=(1, 28, 28), crop=(8, 12),
+                    layers=[dict(kind="dense", out=32, bound=7, square=True, method="diag"),
+                            dict(kind="dense", out=10, bound=7, square=False, method="diag")]),
+    "fc_diag_small": dict(params="t2k3", packing="hw", batch=1, image=(1, 28, 28), crop=(10, 8),
+                          layers=[dict(kind="dense", out=16, bound=7, square=True, method="diag"),
+                                  dict(kind="dense", out=4, bound=7, square=False, method="diag")]),
+    # the CIFAR-shaped branch with a local sum-pooling layer between the convolutions
+    "cfg3_pool": dict(params="cfg3", packing="hw", batch=1, image=(3, 32, 32), crop=(8, 16), sum_after_dense=True,
+                      layers=[dict(kind="conv", out=32, k=3, stride=1, pad=0, bound=31, features=True, square=True),
+                              dict(kind="pool", k=2, stride=2),
+                              dict(kind="conv", out=64, k=3, stride=1, pad=0, bound=31, features=True, square=True,
+                                   sum=True),
+                              dict(kind="dense", out=10, bound=31, square=False)]),
+    "cfg3_pool_small": dict(params="t2k3", packing="hw", batch=1, image=(3, 32, 32), crop=(8, 16),
+                            sum_after_dense=True,
+                            layers=[dict(kind="conv", out=3, k=3, stride=1, pad=0, bound=31, features=True,
+                                         square=True),
+                                    dict(kind="pool", k=2, stride=2),
+                                    dict(kind="conv", out=2, k=3, stride=1, pad=0, bound=31, features=True,
+                                         square=True, sum=True),
+                                    dict(kind="dense", out=3, bound=31, square=False)]),
     "cfg3_small": dict(params="t2k3", packing="hw", batch=1, image=(3, 32, 32), crop=(8, 16), sum_after_dense=True,
                        layers=[dict(kind="conv", out=3, k=3, stride=1, pad=0, bound=31, features=True, square=True),
                                dict(kind="conv", out=2, k=3, stride=2, pad=0, bound=31, features=True, square=True,
@@ -140,7 +170,12 @@ def layer_shapes(name: str):
     shapes = []
     cur = (c, h, wd)
     for lay in w["layers"]:
-        if lay["kind"] == "conv":
+        if lay["kind"] == "pool":
+            ci, hi, wi = cur
+            out = (ci, (hi - lay["k"]) // lay["stride"] + 1, (wi - lay["k"]) // lay["stride"] + 1)
+            shapes.append((cur, out))
+            cur = out
+        elif lay["kind"] == "conv":
             ci, hi, wi = cur
             oh = (hi + 2 * lay["pad"] - lay["k"]) // lay["stride"] + 1
             ow = (wi + 2 * lay["pad"] - lay["k"]) // lay["stride"] + 1
@@ -234,6 +269,10 @@ def make_inputs(name: str, seeds=SEEDS):
             plain[k] = float_weights(seeds["weights"], i, shape, ps["gain"][k] / fan ** 0.5 if fan else 0.1)
         plain["noise"] = perturbation(seeds["images"], (w["batch"], c, h, wd), w["plain"]["noise"])
     for li, lay in enumerate(w["layers"]):
+        if lay["kind"] == "pool":
+            weights.append(None)
+            feats.append(None)
+            continue
         weights.append(int_weights(seeds["weights"], li, weight_shape(name, li), lay["bound"]))
         if lay.get("features") == "plain":
             feats.append(None)

@@ -177,3 +177,16 @@ def test_cfg2_bi_full_decrypts_to_network():
     want = network.run_mod_t("cfg2_bi", g.inputs, g.ctx.t)
     assert vals.shape == (8192, 10)
     assert (vals == want).all()
+
+
+@pytest.mark.parametrize("name", ["fc_diag", "cfg3_pool"])
+def test_diag_fc_and_pooling_full_decrypt_to_network(name):
+    """At N = 16384: the diagonal-method fully connected branch (144 -> 32 -> 10, 175 and 41
+    hoisted rotations) and the CIFAR-shaped branch with a local sum-pooling layer."""
+    torch_cuda()
+    from paper_2402_01296_amd.workload import GpuSession
+    g = GpuSession(name)
+    out = g.run(g.encrypt_inputs())
+    vals = g.output_values(out)
+    want = network.run_mod_t(name, g.inputs, g.ctx.t)
+    assert (vals == want).all()

@@ -11,7 +11,8 @@ from gpu_util import torch_cuda
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("name", ["cfg1_small", "cfg2_small", "cfg3_small", "cfg3_bhw_small", "cfg2_bi_small"])
+@pytest.mark.parametrize("name", ["cfg1_small", "cfg2_small", "cfg3_small", "cfg3_bhw_small", "cfg2_bi_small",
+                                  "fc_diag_small", "cfg3_pool_small"])
 def test_program_parity(name):
     torch_cuda()
     from paper_2402_01296_amd.workload import GpuSession
@@ -45,6 +46,10 @@ def test_program_parity(name):
 def _oracle_layer(O, li, cts):
     info = O.plan["layers"][li]
     hw = O.wl["packing"] in ("hw", "bhw")
+    if info["kind"] == "pool":
+        return O.pool_hw(li, cts)
+    if info.get("method") == "diag":
+        return O.dense_diag(li, cts)
     if info["kind"] == "conv":
         return O.conv_hw(li, cts) if hw else O.conv_batch(li, cts)
     if hw and "in_slots" in info:

@@ -49,7 +49,7 @@ def test_mod_t_network_equals_exact_network(name):
     assert (np.where(2 * ex > t, ex - t, ex) == red).all()
 
 
-@pytest.mark.parametrize("name", ["cfg1_small", "cfg2_small", "cfg3_small", "cfg3_bhw_small", "cfg2_bi_small"])
+@pytest.mark.parametrize("name", ["cfg1_small", "cfg2_small", "cfg3_small", "cfg3_bhw_small", "cfg2_bi_small", "fc_diag_small", "cfg3_pool_small"])
 def test_dec_eval_equals_network(name):
     S = programs.OracleSession(name)
     out = S.run(S.encrypt_inputs())
