@@ -88,7 +88,8 @@ void bcn_eval_keys_destroy(bcn_eval_keys* ek);
 enum { BCN_KEY_RELIN = 0, BCN_KEY_ROTATION = 1 };
 /* Generates one key-switching key into ek: kind BCN_KEY_RELIN (s^2 -> s, used
  * by Mult(c1,c2)) or BCN_KEY_ROTATION for a left rotation by `step` (sigma_k(s)
- * -> s, k = 3^step mod 2N, used by Rot(c, step)).
+ * -> s, k = g^step mod 2N with g = 3 (BFV) or 5 (CKKS), used by Rot(c, step)); a
+ * negative step (> -N/2) is a right rotation and keeps its own key.
  * For digit j: b_j = -a_j s + e_j + P g_j s' mod Q P with g_j = 1 mod the
  * primes of digit j and 0 mod the rest of Q.
  * a: host uint64 [dnum][L+K][N] uniform residues over (Q primes, P primes),
@@ -269,6 +270,46 @@ int bcn_profile_enable(bcn_context* ctx, int on);
  * entries).  Returns the number of names, or an error code. */
 int bcn_profile_read(bcn_context* ctx, char* names, int names_cap, int* launches, double* total_ms, double* bytes,
                      double* ops, int cap);
+
+/* ---- CKKS: the paper's scheme (section "Experiments": CKKS with N = 2^14;
+ * appendix "CKKS Scheme") on the same RNS rings, transforms, keys and key
+ * switching.  A ciphertext [2][l][N] (same layout as above) holds N/2 real
+ * slot values at a scale Delta the caller tracks: slot i sits at the
+ * evaluation point zeta^(5^i mod 2N), zeta = exp(i pi / N).  Rot(c, r)
+ * (bcn_rotate, bcn_rotate_sum) shifts the N/2 slots left by r; keys come from
+ * bcn_keygen (relinearisation key s^2 -> s, rotation keys with k = 5^r).
+ * bcn_mac multiplies by integer scalars (the scale is unchanged);
+ * bcn_modswitch is the rescale (exact nearest division by the last prime:
+ * the scale divides by that prime).  The BFV-only calls (bcn_encode_encrypt,
+ * bcn_decrypt_decode, bcn_add_plain, bcn_mul_plain, bcn_square_relin*,
+ * bcn_layer_create) refuse a CKKS context with BCN_ERR_INVALID. */
+
+/* A CKKS context: p->t is ignored (no plaintext modulus). */
+int bcn_context_create_ckks(const bcn_params* p, int hip_device, bcn_context** out);
+/* Encoding: slots device double [n][N/2] (real) -> round(scale * m), m the real
+ * polynomial with m(zeta^(5^i)) = z_i, as residues over Q_level: out device
+ * [n][level][N], coefficient form, or transformed (bcn_ntt order) when
+ * ntt_domain != 0.  Requires scale in (0, 2^52) and |scale * m_k| < 2^52. */
+int bcn_ckks_encode(bcn_context* ctx, const double* slots, int n, int level, double scale, int ntt_domain,
+                    double* out, bcn_stream stream);
+/* E: encodes host slots [n][N/2] at `scale` and encrypts at `level`:
+ * c = (-a s + e + m, a); a: host uint64 [n][level][N], e: host int8 [n][N]. */
+int bcn_ckks_encode_encrypt(bcn_context* ctx, const bcn_secret_key* sk, const double* slots, double scale,
+                            const uint64_t* a, const int8_t* e, int n, int level, double* ct_out, bcn_stream stream);
+/* D: m = lift_c([c0 + c1 s]_Q), decoded: slots_out host double [n][N/2] = m(zeta^(5^i)) / scale (real parts). */
+int bcn_ckks_decrypt_decode(bcn_context* ctx, const bcn_secret_key* sk, const double* ct, int n, int level,
+                            double scale, double* slots_out, bcn_stream stream);
+/* Add(c, u): c0 += pt for each ciphertext, pt device [n][level][N] coefficient residues
+ * (bcn_ckks_encode at the ciphertext's scale). */
+int bcn_ckks_add_plain(bcn_context* ctx, double* ct, int n, int level, const double* pt, bcn_stream stream);
+/* Mult(c, u): out = in * pt, pt device [level][N] transformed (bcn_ckks_encode with
+ * ntt_domain), shared by the n ciphertexts; the scales multiply. */
+int bcn_ckks_mul_plain(bcn_context* ctx, const double* in, double* out, int n, int level, const double* pt_ntt,
+                       bcn_stream stream);
+/* Mult(c, c): the exact tensor mod Q_level, relinearised, then rescaled by q_level:
+ * in [n][2][level][N] at scale D -> out [n][2][level-1][N] at scale D^2 / q_level. */
+int bcn_ckks_square_relin_rescale(bcn_context* ctx, const bcn_eval_keys* ek, const double* in, double* out, int n,
+                                  int level, bcn_stream stream);
 
 /* ---- scratch arena ----
  * Each context owns a grow-only device scratch arena used by every call.  When

@@ -81,6 +81,13 @@ _SIGS = {
     "bcn_layer_autotune": (_I, [_VP, _VP, C.c_char_p, _I, _VP]),
     "bcn_profile_read": (_I, [_VP, C.c_char_p, _I, _VP, _VP, _VP, _VP, _I]),
     "bcn_square_relin_noalloc": (_I, [_VP, _VP, _VP, _VP, _I, _I, _I, _VP]),
+    "bcn_context_create_ckks": (_I, [_VP, _I, _VP]),
+    "bcn_ckks_encode": (_I, [_VP, _VP, _I, _I, C.c_double, _I, _VP, _VP]),
+    "bcn_ckks_encode_encrypt": (_I, [_VP, _VP, _VP, C.c_double, _VP, _VP, _I, _I, _VP, _VP]),
+    "bcn_ckks_decrypt_decode": (_I, [_VP, _VP, _VP, _I, _I, C.c_double, _VP, _VP]),
+    "bcn_ckks_add_plain": (_I, [_VP, _VP, _I, _I, _VP, _VP]),
+    "bcn_ckks_mul_plain": (_I, [_VP, _VP, _VP, _I, _I, _VP, _VP]),
+    "bcn_ckks_square_relin_rescale": (_I, [_VP, _VP, _VP, _VP, _I, _I, _VP]),
     "bcn_scratch_info": (_I, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "bcn_scratch_release": (_I, [_VP]),
 }
@@ -125,17 +132,20 @@ def _dptr(t):
 
 
 class Context:
-    def __init__(self, n, q_bits, L, K, alpha, t, device=0):
-        self.p = Params(n, q_bits, L, K, alpha, t)
+    def __init__(self, n, q_bits, L, K, alpha, t, device=0, ckks=False):
+        """A BFV context, or with ckks=True a CKKS context (t ignored)."""
+        self.ckks = ckks
+        self.p = Params(n, q_bits, L, K, alpha, 0 if ckks else t)
         h = C.c_void_p()
-        _check(lib().bcn_context_create(C.byref(self.p), device, C.byref(h)))
+        create = lib().bcn_context_create_ckks if ckks else lib().bcn_context_create
+        _check(create(C.byref(self.p), device, C.byref(h)))
         self.h = h
         self.n, self.L, self.K, self.alpha, self.t = n, L, K, alpha, t
         buf = np.zeros(64, dtype=np.uint64)
         nq, np_, nb = C.c_int(), C.c_int(), C.c_int()
         _check(lib().bcn_context_primes(h, buf.ctypes.data_as(C.c_void_p), 64, C.byref(nq), C.byref(np_),
                                         C.byref(nb)))
-        self.primes = [int(x) for x in buf[:nq.value + np_.value + nb.value + 1]]
+        self.primes = [int(x) for x in buf[:nq.value + np_.value + nb.value + (0 if ckks else 1)]]
         self.n_q, self.n_p, self.n_aux = nq.value, np_.value, nb.value
 
     @property
@@ -307,6 +317,53 @@ class Context:
         keys = names.value.decode().split("\n")[:cnt]
         return {k: (int(la[i]), float(ms[i]), float(by[i]), float(op[i])) for i, k in enumerate(keys)}
 
+
+    # ------------------------------------------------------------ CKKS
+    def ckks_encrypt(self, sk, slots, scale, a, e, level=None):
+        """Encode host slots [n][N/2] at `scale` and encrypt: device [n][2][level][N]."""
+        level = self.L if level is None else level
+        slots, sp = _np_ptr(slots, np.float64)
+        a, ap = _np_ptr(a, np.uint64)
+        e, ep = _np_ptr(e, np.int8)
+        n = slots.shape[0]
+        ct = self.empty_ct(n, level)
+        _check(lib().bcn_ckks_encode_encrypt(self.h, sk.h, sp, C.c_double(scale), ap, ep, n, level, _dptr(ct),
+                                             _stream()))
+        return ct
+
+    def ckks_decrypt(self, sk, ct, scale):
+        """Decrypted, decoded slots (real parts), host [n][N/2]."""
+        n, _, level, _ = ct.shape
+        out = np.zeros((n, self.n // 2), dtype=np.float64)
+        _check(lib().bcn_ckks_decrypt_decode(self.h, sk.h, _dptr(ct), n, level, C.c_double(scale),
+                                             out.ctypes.data_as(C.c_void_p), _stream()))
+        return out
+
+    def ckks_encode(self, slots, level, scale, ntt=False):
+        """Device slots [n][N/2] (float64) -> device residues [n][level][N]."""
+        import torch
+        slots = slots.contiguous()
+        n = slots.shape[0]
+        out = torch.empty((n, level, self.n), dtype=torch.float64, device="cuda")
+        _check(lib().bcn_ckks_encode(self.h, _dptr(slots), n, level, C.c_double(scale), 1 if ntt else 0, _dptr(out),
+                                     _stream()))
+        return out
+
+    def ckks_add_plain(self, ct, pt):
+        n, _, level, _ = ct.shape
+        _check(lib().bcn_ckks_add_plain(self.h, _dptr(ct), n, level, _dptr(pt), _stream()))
+
+    def ckks_mul_plain(self, ct, pt_ntt):
+        n, _, level, _ = ct.shape
+        out = self.empty_ct(n, level)
+        _check(lib().bcn_ckks_mul_plain(self.h, _dptr(ct), _dptr(out), n, level, _dptr(pt_ntt), _stream()))
+        return out
+
+    def ckks_square_relin_rescale(self, ek, ct):
+        n, _, level, _ = ct.shape
+        out = self.empty_ct(n, level - 1)
+        _check(lib().bcn_ckks_square_relin_rescale(self.h, ek.h, _dptr(ct), _dptr(out), n, level, _stream()))
+        return out
 
     # ------------------------------------------------------------ scratch arena
     def scratch_info(self):

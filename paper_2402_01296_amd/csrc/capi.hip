@@ -12,7 +12,8 @@ struct bcn_eval_keys { bcn::EvalKeys* k; };
 struct bcn_layer { bcn::Layer* l; };
 
 namespace bcn {
-Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uint32_t alpha, uint64_t t, int device);
+Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uint32_t alpha, uint64_t t, int device,
+                        bool ckks);
 void destroy_context(Context* c);
 }  // namespace bcn
 
@@ -55,6 +56,12 @@ void check_n(int n) {
 void check_ptr(const void* p, const char* what) {
   if (!p) throw bcn::Error(BCN_ERR_INVALID, std::string("null pointer: ") + what);
 }
+
+void need_scheme(const bcn::Context& c, int scheme) {
+  if (c.scheme != scheme)
+    throw bcn::Error(BCN_ERR_INVALID, scheme ? "a CKKS operation needs a CKKS context"
+                                             : "a BFV operation needs a BFV context (this one is CKKS)");
+}
 }  // namespace
 
 extern "C" {
@@ -67,7 +74,7 @@ int bcn_context_create(const bcn_params* p, int hip_device, bcn_context** out) {
     check_ptr(out, "out");
     auto* h = new bcn_context{nullptr};
     try {
-      h->c = bcn::create_context(p->n, p->q_bits, p->L, p->K, p->alpha, p->t, hip_device);
+      h->c = bcn::create_context(p->n, p->q_bits, p->L, p->K, p->alpha, p->t, hip_device, false);
     } catch (...) {
       delete h;
       throw;
@@ -134,8 +141,8 @@ int bcn_keygen(bcn_context* ctx, const bcn_secret_key* sk, bcn_eval_keys* ek, in
     check_ptr(a, "a");
     check_ptr(e, "e");
     if (kind != BCN_KEY_RELIN && kind != BCN_KEY_ROTATION) throw bcn::Error(BCN_ERR_INVALID, "bad key kind");
-    if (kind == BCN_KEY_ROTATION && (step <= 0 || step >= c.n / 2))
-      throw bcn::Error(BCN_ERR_INVALID, "rotation step must be in [1, N/2)");
+    if (kind == BCN_KEY_ROTATION && (step == 0 || step <= -c.n / 2 || step >= c.n / 2))
+      throw bcn::Error(BCN_ERR_INVALID, "rotation step must be nonzero in (-N/2, N/2)");
     bcn::keygen(c, *sk->k, *ek->k, kind, step, a, e, (hipStream_t)stream);
   });
 }
@@ -165,6 +172,7 @@ int bcn_encode_encrypt(bcn_context* ctx, const bcn_secret_key* sk, const int64_t
                        const int8_t* e, int n, int level, double* ct_out, bcn_stream stream) {
   return guard([&] {
     bcn::Context& c = ctxof(ctx);
+    need_scheme(c, 0);
     check_level(c, level);
     check_n(n);
     check_ptr(sk, "secret key");
@@ -181,6 +189,7 @@ int bcn_decrypt_decode(bcn_context* ctx, const bcn_secret_key* sk, const double*
                        int64_t* slots_out, bcn_stream stream) {
   return guard([&] {
     bcn::Context& c = ctxof(ctx);
+    need_scheme(c, 0);
     check_level(c, level);
     check_n(n);
     check_ptr(sk, "secret key");
@@ -285,6 +294,7 @@ int bcn_mac(bcn_context* ctx, const double* in, int n_in, double* out, int n_out
 int bcn_add_plain(bcn_context* ctx, double* ct, int n, int level, const int64_t* slots, bcn_stream stream) {
   return guard([&] {
     bcn::Context& c = ctxof(ctx);
+    need_scheme(c, 0);
     check_level(c, level);
     check_n(n);
     if (n == 0) return;
@@ -304,6 +314,7 @@ int bcn_mul_plain(bcn_context* ctx, const double* in, double* out, int n, int le
                   bcn_stream stream) {
   return guard([&] {
     bcn::Context& c = ctxof(ctx);
+    need_scheme(c, 0);
     check_level(c, level);
     check_n(n);
     if (n == 0) return;
@@ -328,6 +339,7 @@ int bcn_square_relin(bcn_context* ctx, const bcn_eval_keys* ek, const double* in
                      int modswitch, bcn_stream stream) {
   return guard([&] {
     bcn::Context& c = ctxof(ctx);
+    need_scheme(c, 0);
     check_level(c, level);
     check_n(n);
     check_ptr(ek, "eval keys");
@@ -344,6 +356,7 @@ int bcn_square_relin_noalloc(bcn_context* ctx, const bcn_eval_keys* ek, const do
     // no arena reset here: resetting may move the arena to a new block (an allocation)
     if (!ctx || !ctx->c) throw bcn::Error(BCN_ERR_INVALID, "null context");
     bcn::Context& c = *ctx->c;
+    need_scheme(c, 0);
     BCN_HIP(hipSetDevice(c.device));
     check_level(c, level);
     check_n(n);
@@ -468,6 +481,7 @@ int bcn_profile_read(bcn_context* ctx, char* names, int names_cap, int* launches
 int bcn_layer_create(bcn_context* ctx, const bcn_layer_desc* desc, int level, bcn_layer** out) {
   return guard([&] {
     bcn::Context& c = ctxof(ctx);
+    need_scheme(c, 0);
     check_ptr(desc, "desc");
     check_ptr(out, "out");
     *out = new bcn_layer{bcn::layer_create(c, *desc, level)};
@@ -542,6 +556,119 @@ int bcn_scratch_release(bcn_context* ctx) {
     if (!ctx || !ctx->c) throw bcn::Error(BCN_ERR_INVALID, "null context");
     BCN_HIP(hipSetDevice(ctx->c->device));
     ctx->c->arena->release_retired();
+  });
+}
+
+// ---- CKKS
+
+int bcn_context_create_ckks(const bcn_params* p, int hip_device, bcn_context** out) {
+  return guard([&] {
+    check_ptr(p, "params");
+    check_ptr(out, "out");
+    auto* h = new bcn_context{nullptr};
+    try {
+      h->c = bcn::create_context(p->n, p->q_bits, p->L, p->K, p->alpha, 0, hip_device, true);
+    } catch (...) {
+      delete h;
+      throw;
+    }
+    *out = h;
+  });
+}
+
+int bcn_ckks_encode(bcn_context* ctx, const double* slots, int n, int level, double scale, int ntt_domain, double* out,
+                    bcn_stream stream) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    need_scheme(c, 1);
+    check_level(c, level);
+    check_n(n);
+    if (n == 0) return;
+    check_ptr(slots, "slots");
+    check_ptr(out, "out");
+    bcn::ckks_encode(c, slots, n, level, scale, ntt_domain != 0, out, (hipStream_t)stream);
+  });
+}
+
+int bcn_ckks_encode_encrypt(bcn_context* ctx, const bcn_secret_key* sk, const double* slots, double scale,
+                            const uint64_t* a, const int8_t* e, int n, int level, double* ct_out, bcn_stream stream) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    need_scheme(c, 1);
+    check_level(c, level);
+    check_n(n);
+    check_ptr(sk, "secret key");
+    if (n == 0) return;
+    check_ptr(slots, "slots");
+    check_ptr(a, "a");
+    check_ptr(e, "e");
+    check_ptr(ct_out, "ct_out");
+    bcn::ckks_encrypt(c, *sk->k, slots, scale, a, e, n, level, ct_out, (hipStream_t)stream);
+  });
+}
+
+int bcn_ckks_decrypt_decode(bcn_context* ctx, const bcn_secret_key* sk, const double* ct, int n, int level,
+                            double scale, double* slots_out, bcn_stream stream) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    need_scheme(c, 1);
+    check_level(c, level);
+    check_n(n);
+    check_ptr(sk, "secret key");
+    if (n == 0) return;
+    check_ptr(ct, "ct");
+    check_ptr(slots_out, "slots_out");
+    if (!(scale > 0.0)) throw bcn::Error(BCN_ERR_INVALID, "scale must be positive");
+    bcn::ckks_decrypt(c, *sk->k, ct, n, level, scale, slots_out, (hipStream_t)stream);
+  });
+}
+
+int bcn_ckks_add_plain(bcn_context* ctx, double* ct, int n, int level, const double* pt, bcn_stream stream) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    need_scheme(c, 1);
+    check_level(c, level);
+    check_n(n);
+    if (n == 0) return;
+    check_ptr(ct, "ct");
+    check_ptr(pt, "pt");
+    bcn::ckks_add_plain(c, ct, n, level, pt, (hipStream_t)stream);
+  });
+}
+
+int bcn_ckks_mul_plain(bcn_context* ctx, const double* in, double* out, int n, int level, const double* pt_ntt,
+                       bcn_stream stream) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    need_scheme(c, 1);
+    check_level(c, level);
+    check_n(n);
+    if (n == 0) return;
+    check_ptr(in, "in");
+    check_ptr(out, "out");
+    check_ptr(pt_ntt, "pt");
+    const size_t words = (size_t)n * 2 * level * c.n;
+    double* A = c.arena->take(words);
+    bcn::copy_rows(in, 0, A, 0, words, 1, (hipStream_t)stream);
+    bcn::ntt_forward(c, A, 2 * n, c.basis_Q(level), (hipStream_t)stream);
+    bcn::mul_plain_ntt(c, A, A, n, level, pt_ntt, false, (hipStream_t)stream);
+    bcn::ntt_inverse(c, A, 2 * n, c.basis_Q(level), (hipStream_t)stream);
+    bcn::copy_rows(A, 0, out, 0, words, 1, (hipStream_t)stream);
+  });
+}
+
+int bcn_ckks_square_relin_rescale(bcn_context* ctx, const bcn_eval_keys* ek, const double* in, double* out, int n,
+                                  int level, bcn_stream stream) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    need_scheme(c, 1);
+    check_level(c, level);
+    check_n(n);
+    check_ptr(ek, "eval keys");
+    if (n == 0) return;
+    check_ptr(in, "in");
+    check_ptr(out, "out");
+    bcn::ckks_square_relin_rescale(c, *ek->k, in, out, n, level, (hipStream_t)stream);
   });
 }
 

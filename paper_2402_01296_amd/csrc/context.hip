@@ -204,7 +204,8 @@ void release_convs(const Context& c) {
   }
 }
 
-Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uint32_t alpha, uint64_t t, int device) {
+Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uint32_t alpha, uint64_t t, int device,
+                        bool ckks) {
   int logn = 0;
   while ((1u << logn) < n) ++logn;
   if ((1u << logn) != n || logn < 10 || logn > 14) throw Error(-1, "N must be a power of two in [1024, 16384]");
@@ -212,9 +213,13 @@ Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uin
   if (L < 1 || L > 8) throw Error(-1, "number of ciphertext primes must be 1..8");
   if (K < 1 || K > 3) throw Error(-1, "number of special primes must be 1..3");
   if (alpha < 1 || alpha > 8) throw Error(-1, "digit size must be 1..8");
-  if (t < 3 || t >= (1ull << 21) || !host::is_prime(t) || (t - 1) % (2ull * n) != 0)
-    throw Error(-1, "t must be a prime below 2^21 with t = 1 mod 2N");
-  if (t >= (1ull << (q_bits - 2))) throw Error(-1, "t too large for the ciphertext primes");
+  if (ckks) {
+    t = 0;
+  } else {
+    if (t < 3 || t >= (1ull << 21) || !host::is_prime(t) || (t - 1) % (2ull * n) != 0)
+      throw Error(-1, "t must be a prime below 2^21 with t = 1 mod 2N");
+    if (t >= (1ull << (q_bits - 2))) throw Error(-1, "t too large for the ciphertext primes");
+  }
   // special primes must cover one digit: P > Q_j keeps the key-switching noise small
   if (K < alpha && false) throw Error(-1, "unreachable");
 
@@ -227,6 +232,8 @@ Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uin
   c->K = (int)K;
   c->alpha = (int)alpha;
   c->t = t;
+  c->scheme = ckks ? 1 : 0;
+  c->gen = ckks ? 5 : 3;
   // Q and P: the largest q_bits-bit primes = 1 mod 2N, then aux primes B with
   // B > 2 N Q so that the square's exact tensor lives in Q*B.
   std::vector<uint64_t> qp = host::ntt_primes((int)q_bits, 2ull * n, (int)(L + K), {t});
@@ -244,8 +251,12 @@ Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uin
   c->m = m;
   c->primes.assign(qp.begin(), qp.end());
   for (int i = 0; i < m; ++i) c->primes.push_back(more[L + K + i]);
-  c->primes.push_back(t);
-  c->id_t = (int)c->primes.size() - 1;
+  if (!ckks) {
+    c->primes.push_back(t);
+    c->id_t = (int)c->primes.size() - 1;
+  } else {
+    c->id_t = -1;
+  }
   const int np = (int)c->primes.size();
   for (uint64_t q : c->primes) c->hmods.push_back(Mod{(double)q, 1.0 / (double)q});
 
@@ -292,6 +303,7 @@ Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uin
   c->tab.mods = dm;
   c->tab.logn = logn;
 
+  if (!ckks) {
   // slot s -> position of its evaluation point in the transform of R_t
   std::vector<uint32_t> pos(N);
   const uint64_t two_n = 2ull * N;
@@ -310,6 +322,7 @@ Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uin
     if (slot_of[i] == 0xffffffffu) throw Error(-1, "slot map is not a permutation");
   BCN_HIP(hipMalloc(&c->d_slot_of_word, N * sizeof(uint32_t)));
   BCN_HIP(hipMemcpy(c->d_slot_of_word, slot_of.data(), N * sizeof(uint32_t), hipMemcpyHostToDevice));
+  }
   c->arena = std::make_unique<Arena>();
   // default transform shape (bcn_autotune may replace it by a measured choice)
   c->ntt_loge = logn >= 14 ? 5 : 4;
@@ -358,6 +371,7 @@ Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uin
   preload_conversions(*c);
   preload_ks_digits(*c);
   fixed_scratch_setup(*c);
+  if (ckks) ckks_setup(*c);
   return c.release();
 }
 
@@ -375,6 +389,7 @@ void destroy_context(Context* c) {
   if (c->d_tables) (void)hipFree(c->d_tables);
   if (c->d_slot_pos) (void)hipFree(c->d_slot_pos);
   if (c->d_slot_of_word) (void)hipFree(c->d_slot_of_word);
+  if (c->ckks_tab) (void)hipFree(c->ckks_tab);
   delete c;
 }
 

@@ -136,7 +136,10 @@ struct Context {
   hipEvent_t get_event() const;
   int n = 0, logn = 0;
   int L = 0, K = 0, alpha = 0, m = 0;   // Q primes, P primes, digit size, aux primes
-  uint64_t t = 0;
+  uint64_t t = 0;                        // BFV plaintext modulus (0 for CKKS)
+  int scheme = 0;                        // 0 BFV, 1 CKKS
+  int gen = 3;                           // slot rotation generator: Rot(c, r) = sigma_{gen^r}
+  double* ckks_tab = nullptr;            // CKKS encoder tables (ckks.hip)
   std::vector<uint64_t> primes;          // ids: Q [0,L), P [L,L+K), B [L+K,L+K+m), t last
   std::vector<Mod> hmods;
   int id_t = 0;

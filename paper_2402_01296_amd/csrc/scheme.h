@@ -53,6 +53,22 @@ size_t square_relin_scratch_doubles(const Context& c, int n, int level);
 void square_relin_noalloc(Context& c, const EvalKeys& ek, const double* in, double* out, int n, int level, bool modsw,
                           hipStream_t s);
 void fixed_scratch_setup(Context& c);
+
+// ---- CKKS (ckks.hip): the paper's scheme on the same rings, keys and key switching
+void ckks_setup(Context& c);
+// slots z (device, real, [n][N/2]) -> round(scale * m) as residues over Q_level ([n][level][N],
+// coefficient form; with ntt_domain, transformed)
+void ckks_encode(const Context& c, const double* z, int n, int level, double scale, bool ntt_domain, double* out,
+                 hipStream_t s);
+void ckks_encrypt(Context& c, const SecretKey& sk, const double* z_host, double scale, const uint64_t* a_host,
+                  const int8_t* e_host, int n, int level, double* ct, hipStream_t s);
+void ckks_decrypt(Context& c, const SecretKey& sk, const double* ct, int n, int level, double scale, double* z_host,
+                  hipStream_t s);
+// c0 += pt (coefficient residues [n][level][N], one per ciphertext)
+void ckks_add_plain(const Context& c, double* ct, int n, int level, const double* pt, hipStream_t s);
+// Mult(c1, c2) with c1 = c2, relinearised, then rescaled by q_level: [n][2][level][N] -> [n][2][level-1][N]
+void ckks_square_relin_rescale(Context& c, const EvalKeys& ek, const double* in, double* out, int n, int level,
+                               hipStream_t s);
 // the same from x [n][2][level+m][N] whose Q limbs hold the input; x's B limbs are filled in place
 void square_relin_qb(Context& c, const EvalKeys& ek, double* x, double* out, int n, int level, bool modsw,
                      hipStream_t s);

@@ -51,7 +51,7 @@ const double* EvalKeys::rot_key(int step) const {
 int galois_element(const Context& c, int step) {
   const uint64_t half = (uint64_t)c.n / 2, two_n = 2ull * c.n;
   const uint64_t r = (uint64_t)(((int64_t)step % (int64_t)half + (int64_t)half) % (int64_t)half);
-  return (int)host::powmod(3, r, two_n);
+  return (int)host::powmod((uint64_t)c.gen, r, two_n);
 }
 
 int galois_inverse(const Context& c, int k) { return (int)host::inv_pow2((uint64_t)k, c.logn + 1); }

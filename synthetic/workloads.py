@@ -141,6 +141,22 @@ WORKLOADS = {
                                     dict(kind="conv", out=2, k=3, stride=1, pad=0, bound=31, features=True,
                                          square=True, sum=True),
                                     dict(kind="dense", out=3, bound=31, square=False)]),
+    # the CIFAR-shaped branch under CKKS (the paper's scheme): real inputs (pixel / 255), real
+    # weights W / 2^wbits (W the integer weights above), real FP32 features added unquantised;
+    # inputs encrypted at scale 2^scale_bits, each mask and square followed by a rescale
+    "cfg3_ckks": dict(params="cfg3", scheme="ckks", packing="hw", batch=1, image=(3, 32, 32), crop=(8, 16),
+                      sum_after_dense=True, scale_bits=30, wbits=8,
+                      layers=[dict(kind="conv", out=32, k=3, stride=1, pad=0, bound=31, features=True, square=True),
+                              dict(kind="conv", out=64, k=3, stride=2, pad=0, bound=31, features=True, square=True,
+                                   sum=True),
+                              dict(kind="dense", out=10, bound=31, square=False)]),
+    "cfg3_ckks_small": dict(params="t2k3", scheme="ckks", packing="hw", batch=1, image=(3, 32, 32), crop=(8, 16),
+                            sum_after_dense=True, scale_bits=30, wbits=8,
+                            layers=[dict(kind="conv", out=3, k=3, stride=1, pad=0, bound=31, features=True,
+                                         square=True),
+                                    dict(kind="conv", out=2, k=3, stride=2, pad=0, bound=31, features=True,
+                                         square=True, sum=True),
+                                    dict(kind="dense", out=3, bound=31, square=False)]),
     "cfg3_small": dict(params="t2k3", packing="hw", batch=1, image=(3, 32, 32), crop=(8, 16), sum_after_dense=True,
                        layers=[dict(kind="conv", out=3, k=3, stride=1, pad=0, bound=31, features=True, square=True),
                                dict(kind="conv", out=2, k=3, stride=2, pad=0, bound=31, features=True, square=True,
