@@ -39,6 +39,14 @@ WORKLOAD_TEXT = {
 }
 
 
+def _schemes():
+    from synthetic import workloads as W
+    return {k: v.get("scheme", "bfv") for k, v in W.WORKLOADS.items()}
+
+
+W_SCHEME = _schemes()
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,8 +70,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-legs", action="store_true",
                     help="only the headline workload (no CIFAR-shaped, transform or serving legs)")
-    ap.add_argument("--legs-rates", default="200,800", help="Poisson rates of the serving leg")
-    ap.add_argument("--legs-requests", type=int, default=1000, help="requests per rate in the serving leg")
+    ap.add_argument("--legs-rates", default="50,200,800", help="Poisson rates of the serving leg")
+    ap.add_argument("--legs-requests", type=int, default=600, help="requests per rate in the serving leg")
     return ap.parse_args()
 
 
@@ -185,6 +193,12 @@ def mix_bench(args):
         outg = m.run_batched(graphs=True)
     t_graph = (time.perf_counter() - t0) / args.steps
     same = all(bool((alone[r] == m.request_output(outg, r)).all()) for r in range(len(m.names)))
+    # the transform phase of the whole mix: one persistent launch over the uneven (N, limbs) work
+    # list against per-group launches on their streams (the autotuner keeps the faster)
+    tp_multi = m.transform_phase(multi=True)
+    tp_streams = m.transform_phase(multi=False)
+    print("bench: transform phase multi %.3f ms, per-group streams %.3f ms" % (tp_multi, tp_streams),
+          file=sys.stderr, flush=True)
     n = len(m.names)
     print(json.dumps({
         "metric": "encrypted inferences/sec (batched uneven mix)",
@@ -198,6 +212,10 @@ def mix_bench(args):
         "speedup_vs_per_request": round(t_alone / t_graph, 2),
         "per_group": per_group,
         "bit_identical_alone_vs_batched": same,
+        "transform_phase": {"work": "forward + inverse transform of every request's input ciphertexts",
+                            "one_persistent_launch_ms": round(tp_multi, 3),
+                            "per_group_streams_ms": round(tp_streams, 3),
+                            "chosen": "one persistent launch" if tp_multi < tp_streams else "per-group streams"},
     }), flush=True)
 
 
@@ -488,6 +506,58 @@ def run_workload(name: str, steps: int, warmup: int, autotune: bool = True, grap
     return res
 
 
+def run_ckks_workload(name: str, steps: int, warmup: int, autotune: bool = True, verify: bool = True):
+    """The CIFAR-shaped branch under CKKS (the paper's scheme): requests/s of one image, the
+    per-kernel split, and the decrypted outputs against the FP64 real-valued network."""
+    import numpy as np
+    import torch
+
+    from paper_2402_01296_amd.ckks_workload import CkksSession
+    g = CkksSession(name)
+    tuning = g.ctx.autotune() if autotune else None
+    ct_in = g.encrypt_inputs()
+    for _ in range(max(2, warmup)):
+        out, scale = g.run(ct_in)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out, scale = g.run(ct_in)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    print("bench: %s timed %d steps, %.3f ms/step" % (name, steps, total * 1e3 / steps), file=sys.stderr, flush=True)
+    g.ctx.profile(True)
+    for _ in range(steps):
+        g.run(ct_in)
+    torch.cuda.synchronize()
+    g.ctx.profile(False)
+    kern = {}
+    for k, (la, ms, by, ops) in g.ctx.profile_read().items():
+        sec = ms * 1e-3
+        kern[k] = dict(launches=la, ms=ms, bytes=by, ops=ops,
+                       gbs=by / sec / 1e9 if sec > 0 else 0.0, tops=ops / sec / 1e12 if sec > 0 else 0.0)
+    dom = max(kern, key=lambda k: kern[k]["ms"])
+    err = None
+    if verify:
+        from oracle import ckks_network   # test-only check of this run's outputs
+        want = ckks_network.run(name, g.inputs)
+        got = g.output_values(out, scale)
+        err = float(np.abs(got - want).max() / np.abs(want).max())
+    res = {"workload": "CIFAR-shaped branch under CKKS (the paper's scheme): N=16384, 6x40-bit primes, dnum=3, "
+                       "one 32x32x3 image, inputs at scale 2^30, real weights W/2^8, real features",
+           "name": name, "ms_per_step": round(total * 1e3 / steps, 3), "requests_per_s": round(steps / total, 3),
+           "roofline": roofline(kern[dom], dom, name),
+           "kernels": {k: {"ms_per_step": round(v["ms"] / steps, 3), "launches": v["launches"],
+                           "gbs": round(v["gbs"], 1), "fp64_tops": round(v["tops"], 3)}
+                       for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])},
+           "autotune": [ln for ln in (tuning or "").splitlines() if "chosen" in ln],
+           "max_error_vs_real_network": err,
+           "error_bound": 1e-6}
+    del g, ct_in, out
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return res
+
+
 def roofline(d: dict, kernel: str, workload: str):
     """The kernel's bound is the larger of its two floors: algorithmic bytes at the HBM peak and
     algorithmic FP64 operations at the vector peak; achieved = algorithmic units / launch time."""
@@ -597,6 +667,10 @@ def main():
     if args.serve:
         serve_bench(args)
         return
+    if W_SCHEME.get(args.workload) == "ckks":
+        print(json.dumps(run_ckks_workload(args.workload, args.steps, args.warmup, not args.no_autotune,
+                                           not args.no_verify)), flush=True)
+        return
     # the oracle baseline runs first, before anything touches the GPU (its pool forks)
     cpu = None
     if not args.no_cpu_baseline and args.workload == "cfg2":
@@ -616,6 +690,8 @@ def main():
                                         autotune=not args.no_autotune, verify=not args.no_verify)
         legs["cfg2_bi"] = run_workload("cfg2_bi", max(5, args.steps // 2), args.warmup,
                                        autotune=not args.no_autotune, verify=not args.no_verify)
+        legs["cfg3_ckks"] = run_ckks_workload("cfg3_ckks", max(5, args.steps // 2), args.warmup,
+                                              autotune=not args.no_autotune, verify=not args.no_verify)
         legs["ntt_" + args.workload] = ntt_leg(args.workload, max(5, args.steps // 2), not args.no_autotune)
         rows, info = serving_leg([float(r) for r in args.legs_rates.split(",")], args.legs_requests,
                                  autotune=not args.no_autotune)

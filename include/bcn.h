@@ -125,6 +125,19 @@ int bcn_ct_import(bcn_context* ctx, const uint64_t* host_in, int n, int level, d
 int bcn_ntt(bcn_context* ctx, double* data, int n_polys, int n_limbs, int first_prime, int inverse,
             bcn_stream stream);
 
+/* Batching across parameter sets: one persistent launch transforms the limbs of
+ * several contexts (N = 4096, 8192 or 16384; each with its own primes), e.g.
+ * requests of uneven ring degree and prime count.  Item i: data device
+ * [n_polys][n_limbs][N] of context ctx, limb j with prime id first_prime + j;
+ * the result is exactly bcn_ntt of each item.  At most 16 items, all contexts
+ * on one device; calls on overlapping data race. */
+typedef struct {
+  bcn_context* ctx;
+  double* data;
+  int32_t n_polys, n_limbs, first_prime;
+} bcn_ntt_item;
+int bcn_ntt_multi(const bcn_ntt_item* items, int n_items, int inverse, bcn_stream stream);
+
 /* out[o] = sum_j w[o][j] in[j] (Mult(c,u) by scalars, Add(c1,c2)); w host int32 [n_out][n_in].
  * The environment variable BCN_MAC_TILE (a power of two, 1..64) pins the number of
  * outputs per tile; results are the same for every tile size. */

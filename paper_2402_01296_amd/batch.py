@@ -151,6 +151,39 @@ class Mix:
                 grp.capture((chunks or {}).get(name))
         torch.cuda.synchronize()
 
+    def transform_phase(self, multi: bool, reps: int = 5) -> float:
+        """Forward then inverse transforms of every request's input ciphertexts (all limbs) across
+        the parameter sets: one persistent launch per direction over the uneven (N, limbs) work
+        list (multi), or each group's own launches on its stream.  Returns ms per phase."""
+        torch = self.torch
+        from . import bcn
+        if not hasattr(self, "_tp"):
+            self._tp = {name: grp.ct.clone().reshape(-1, grp.ct.shape[2], grp.ct.shape[3])
+                        for name, grp in self.groups.items()}
+        items = [(self.sessions[name].ctx, buf, 0) for name, buf in self._tp.items()]
+        cur = torch.cuda.current_stream()
+
+        def once():
+            if multi:
+                bcn.ntt_multi(items)
+                bcn.ntt_multi(items, inverse=True)
+                return
+            for name, buf in self._tp.items():
+                st = self.streams[name]
+                st.wait_stream(cur)
+                with torch.cuda.stream(st):
+                    self.sessions[name].ctx.ntt(buf, 0)
+                    self.sessions[name].ctx.ntt(buf, 0, inverse=True)
+            for st in self.streams.values():
+                cur.wait_stream(st)
+        once()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            once()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
     def request_output(self, outs_batched, rid: int):
         """Output ciphertexts of request rid from a batched result."""
         name = self.names[rid]

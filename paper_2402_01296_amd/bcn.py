@@ -43,6 +43,23 @@ class LayerDesc(C.Structure):
                 ("method", C.c_int32)]
 
 
+class NttItem(C.Structure):
+    _fields_ = [("ctx", C.c_void_p), ("data", C.c_void_p), ("n_polys", C.c_int32), ("n_limbs", C.c_int32),
+                ("first_prime", C.c_int32)]
+
+
+def ntt_multi(items, inverse=False):
+    """One persistent launch transforming several contexts' limbs: items of
+    (context, data [n_polys][n_limbs][N] device tensor, first_prime)."""
+    arr = (NttItem * len(items))()
+    for i, (ctx, data, first) in enumerate(items):
+        arr[i].ctx = ctx.h
+        arr[i].data = data.data_ptr()
+        arr[i].n_polys, arr[i].n_limbs = data.shape[0], data.shape[1]
+        arr[i].first_prime = first
+    _check(lib().bcn_ntt_multi(arr, len(items), 1 if inverse else 0, _stream()))
+
+
 _lib = None
 
 _VP, _I, _U64P, _I64P, _I32P, _I8P = C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p
@@ -82,6 +99,7 @@ _SIGS = {
     "bcn_profile_read": (_I, [_VP, C.c_char_p, _I, _VP, _VP, _VP, _VP, _I]),
     "bcn_square_relin_noalloc": (_I, [_VP, _VP, _VP, _VP, _I, _I, _I, _VP]),
     "bcn_context_create_ckks": (_I, [_VP, _I, _VP]),
+    "bcn_ntt_multi": (_I, [_VP, _I, _I, _VP]),
     "bcn_ckks_encode": (_I, [_VP, _VP, _I, _I, C.c_double, _I, _VP, _VP]),
     "bcn_ckks_encode_encrypt": (_I, [_VP, _VP, _VP, C.c_double, _VP, _VP, _I, _I, _VP, _VP]),
     "bcn_ckks_decrypt_decode": (_I, [_VP, _VP, _VP, _I, _I, C.c_double, _VP, _VP]),

@@ -559,6 +559,30 @@ int bcn_scratch_release(bcn_context* ctx) {
   });
 }
 
+int bcn_ntt_multi(const bcn_ntt_item* items, int n_items, int inverse, bcn_stream stream) {
+  return guard([&] {
+    if (n_items < 0 || n_items > bcn::kMaxMultiItems) throw bcn::Error(BCN_ERR_INVALID, "1..16 items per launch");
+    if (n_items == 0) return;
+    check_ptr(items, "items");
+    std::vector<bcn::MultiNttItem> v;
+    int device = -1;
+    for (int i = 0; i < n_items; ++i) {
+      const bcn_ntt_item& it = items[i];
+      if (!it.ctx || !it.ctx->c) throw bcn::Error(BCN_ERR_INVALID, "null context in a transform item");
+      const bcn::Context& c = *it.ctx->c;
+      if (device < 0) device = c.device;
+      if (c.device != device) throw bcn::Error(BCN_ERR_INVALID, "transform items on different devices");
+      if (it.n_polys < 0 || it.n_limbs < 1 || it.first_prime < 0 ||
+          it.first_prime + it.n_limbs > (int)c.primes.size())
+        throw bcn::Error(BCN_ERR_INVALID, "bad transform item shape");
+      if (it.n_polys > 0) check_ptr(it.data, "item data");
+      v.push_back({it.data, c.tab, c.logn, it.n_limbs, it.first_prime, it.n_polys * it.n_limbs});
+    }
+    BCN_HIP(hipSetDevice(device));
+    bcn::ntt_multi(v, inverse != 0, (hipStream_t)stream);
+  });
+}
+
 // ---- CKKS
 
 int bcn_context_create_ckks(const bcn_params* p, int hip_device, bcn_context** out) {

@@ -192,6 +192,19 @@ class ProfScope {
 };
 
 // ---- transforms (ntt.hip)
+// one item of a multi-context transform launch: limbs [n_polys][n_limbs][N] of one context,
+// limb i with prime id first_prime + i
+constexpr int kMaxMultiItems = 16;
+struct MultiNttItem {
+  double* data;
+  Tables tb;
+  int logn, n_limbs, first_prime, units;
+};
+struct MultiNttWork {
+  MultiNttItem it[kMaxMultiItems];
+  int n_items, total;
+};
+void ntt_multi(const std::vector<MultiNttItem>& items, bool inverse, hipStream_t s);
 // data: [n_polys][basis.n][N]; each limb transformed in place with its prime.
 void ntt_forward(const Context& c, double* data, int n_polys, const Basis& b, hipStream_t s);
 void ntt_inverse(const Context& c, double* data, int n_polys, const Basis& b, hipStream_t s);

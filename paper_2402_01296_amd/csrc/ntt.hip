@@ -426,6 +426,44 @@ k_square_fused(const double* __restrict__ in, double* __restrict__ out, Basis ba
   run_pass<LOGN, LOGE, true, 0, true, false>(x1, lds, nullptr, d2, iw, post, m, tid);
 }
 
+// One persistent launch over transform work of several contexts: ring degrees 4096, 8192
+// and 16384 with each context's own prime tables.  The work list holds items, each a batch of
+// limbs of one context; every workgroup walks the units blockIdx.x, blockIdx.x + gridDim.x, ...
+// of the concatenated list (whole limbs), so one grid sized to the device serves requests of
+// uneven ring degree and prime count.  All three degrees run with 512 threads (2^(logn-9)
+// residues per thread) and the LDS holds the largest degree of the list.
+template <bool INV>
+__global__ void __launch_bounds__(512) k_ntt_multi(MultiNttWork w) {
+  extern __shared__ double lds[];
+  for (int u = blockIdx.x; u < w.total; u += gridDim.x) {
+    int k = 0, base = 0;
+    while (k + 1 < w.n_items && u >= base + w.it[k].units) {
+      base += w.it[k].units;
+      ++k;
+    }
+    const int logn = w.it[k].logn, nl = w.it[k].n_limbs;
+    const int local = u - base, limb = local % nl, poly = local / nl;
+    const Tables tb = w.it[k].tb;
+    const int pid = w.it[k].first_prime + limb;
+    const Mod m = tb.mods[pid];
+    const size_t N = (size_t)1 << logn;
+    double* a = w.it[k].data + ((size_t)poly * nl + limb) * N;
+    const double* tw = INV ? tb.inv + (size_t)pid * N : tb.fwd + (size_t)pid * N;
+    const double* post = tb.post + (size_t)pid * N;
+    if (logn == 12) {
+      double x[8];
+      run_pass<12, 3, INV, 0>(x, lds, a, a, tw, post, m, threadIdx.x);
+    } else if (logn == 13) {
+      double x[16];
+      run_pass<13, 4, INV, 0>(x, lds, a, a, tw, post, m, threadIdx.x);
+    } else {
+      double x[32];
+      run_pass<14, 5, INV, 0>(x, lds, a, a, tw, post, m, threadIdx.x);
+    }
+    __syncthreads();   // the next unit reuses the LDS
+  }
+}
+
 template <int LOGN, int LOGE, bool INV>
 void launch(const Context& c, double* data, int n_polys, const Basis& b, hipStream_t s) {
   constexpr int N = 1 << LOGN;
@@ -805,6 +843,39 @@ std::vector<int> Context::ntt_loge_options() const {
     case 14: return {4, 5};
     default: return {};
   }
+}
+
+void ntt_multi(const std::vector<MultiNttItem>& items, bool inverse, hipStream_t s) {
+  if (items.empty()) return;
+  if ((int)items.size() > kMaxMultiItems) throw Error(-1, "too many items in one transform launch");
+  MultiNttWork w{};
+  int maxlog = 0;
+  for (size_t i = 0; i < items.size(); ++i) {
+    if (items[i].logn < 12 || items[i].logn > 14) throw Error(-1, "multi-context transform: N must be 4096..16384");
+    w.it[i] = items[i];
+    w.total += items[i].units;
+    maxlog = std::max(maxlog, items[i].logn);
+  }
+  w.n_items = (int)items.size();
+  if (w.total == 0) return;
+  static bool attr = false;
+  if (!attr) {
+    BCN_HIP(hipFuncSetAttribute((const void*)k_ntt_multi<false>, hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
+    BCN_HIP(hipFuncSetAttribute((const void*)k_ntt_multi<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
+    attr = true;
+  }
+  int dev = 0;
+  BCN_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  BCN_HIP(hipGetDeviceProperties(&prop, dev));
+  const size_t lds = ((size_t)1 << maxlog) * sizeof(double);
+  const int per_cu = std::max(1, (int)(prop.maxSharedMemoryPerMultiProcessor / lds));
+  const int grid = std::min(w.total, prop.multiProcessorCount * per_cu);
+  if (inverse)
+    hipLaunchKernelGGL(k_ntt_multi<true>, dim3(grid), dim3(512), lds, s, w);
+  else
+    hipLaunchKernelGGL(k_ntt_multi<false>, dim3(grid), dim3(512), lds, s, w);
+  BCN_HIP(hipGetLastError());
 }
 
 void ntt_setup(const Context& c) {
