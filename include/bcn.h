@@ -157,7 +157,7 @@ int bcn_square_relin(bcn_context* ctx, const bcn_eval_keys* ek, const double* in
  * the same arguments, semantics and bit-identical results, but no allocation,
  * free or allocating library call of any kind.  Its scratch is a fixed 64 MiB
  * array of device memory per GPU, held by the library until the process ends.
- * A call whose scratch would exceed it (about 12 ciphertexts at N = 8192 with
+ * A call whose scratch would exceed it (about 13 ciphertexts at N = 8192 with
  * four primes, 4 at N = 16384 with six) returns BCN_ERR_INVALID before
  * launching anything.  Every call on one GPU, from any context, stream or host
  * thread, uses that one array, so calls that overlap in time on one GPU race:

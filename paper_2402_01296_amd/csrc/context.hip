@@ -235,22 +235,28 @@ Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uin
   c->scheme = ckks ? 1 : 0;
   c->gen = ckks ? 5 : 3;
   // Q and P: the largest q_bits-bit primes = 1 mod 2N, then aux primes B with
-  // B > 2 N Q so that the square's exact tensor lives in Q*B.
+  // B > 2 N Q so that the square's exact tensor lives in Q*B.  B takes the largest 41-bit
+  // primes (the widest the exact FP64 residue arithmetic allows), so it needs as few limbs as
+  // possible whatever the size of the ciphertext primes: every B limb is five more transforms
+  // per ciphertext in the square.
   std::vector<uint64_t> qp = host::ntt_primes((int)q_bits, 2ull * n, (int)(L + K), {t});
   double log_q = 0;
   for (uint32_t i = 0; i < L; ++i) log_q += std::log2((double)qp[i]);
   const double need = log_q + logn + 2.0;
-  std::vector<uint64_t> more = host::ntt_primes((int)q_bits, 2ull * n, (int)(L + K) + 16, {t});
+  std::vector<uint64_t> skip(qp.begin(), qp.end());
+  skip.push_back(t);
+  std::vector<uint64_t> more = host::ntt_primes(41, 2ull * n, 16, skip);
   double log_b = 0;
   int m = 0;
   while (log_b <= need) {
-    log_b += std::log2((double)more[L + K + m]);
+    if (m == (int)more.size()) throw Error(-1, "auxiliary basis too large");
+    log_b += std::log2((double)more[m]);
     ++m;
   }
   if ((int)L + m > 16) throw Error(-1, "auxiliary basis too large");
   c->m = m;
   c->primes.assign(qp.begin(), qp.end());
-  for (int i = 0; i < m; ++i) c->primes.push_back(more[L + K + i]);
+  for (int i = 0; i < m; ++i) c->primes.push_back(more[i]);
   if (!ckks) {
     c->primes.push_back(t);
     c->id_t = (int)c->primes.size() - 1;

@@ -43,8 +43,8 @@ def test_noalloc_refuses_oversize_calls():
     from paper_2402_01296_amd import bcn
     prm, ctx, ek = _setup("cfg2", 52)
     level = prm.L
-    x = torch.zeros((13, 2, level, prm.n), dtype=torch.float64, device="cuda")
-    out = ctx.empty_ct(13, level)
+    x = torch.zeros((40, 2, level, prm.n), dtype=torch.float64, device="cuda")
+    out = ctx.empty_ct(40, level)
     with pytest.raises(bcn.BcnError) as ei:
         ctx.square_relin_noalloc(ek, x, out)
     assert ei.value.code == bcn.BCN_ERR_INVALID
