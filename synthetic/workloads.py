@@ -40,7 +40,7 @@ SEEDS = dict(keys=1, enc=2, weights=3, images=4, features=5)
 PARAMS = {
     # the three workloads
     "cfg1": dict(n=4096, bits=30, L=2, K=1, alpha=1, t=65537),
-    "cfg2": dict(n=8192, bits=36, L=4, K=1, alpha=1, t=1032193),
+    "cfg2": dict(n=8192, bits=36, L=4, K=2, alpha=2, t=1032193),
     "cfg3": dict(n=16384, bits=40, L=6, K=2, alpha=2, t=65537),
     # workload 1 with five primes so that its output still decrypts (insecure)
     "cfg1d": dict(n=4096, bits=30, L=5, K=1, alpha=1, t=65537, insecure=True),
