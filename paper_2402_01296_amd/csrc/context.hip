@@ -372,6 +372,7 @@ Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uin
     const size_t lds = (size_t)n * sizeof(double);
     const int per_cu = std::max(1, (int)(prop.maxSharedMemoryPerMultiProcessor / lds));
     c->persist_blocks = prop.multiProcessorCount * per_cu;
+    c->n_cus = prop.multiProcessorCount;
   }
   ntt_setup(*c);
   preload_conversions(*c);

@@ -160,6 +160,7 @@ struct Context {
   bool ntt_persist = false;              // persistent, prefetching transform kernel
   bool ntt_prefetch = false;             // transform loads the next pass's twiddles before each exchange
   int persist_blocks = 512;              // its grid: workgroups resident at once
+  int n_cus = 256;                       // compute units of the device
   int ks_mode = 2;                       // key switching: 0 ModUp + NTT + inner product + INTT (four kernels),
                                          // 1 one fused kernel, 2 digits+NTT and inner product+INTT (two kernels)
   int ks_mode_rot = 2;                   // the same for hoisted rotations (0 or 2)

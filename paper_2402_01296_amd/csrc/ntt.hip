@@ -664,8 +664,10 @@ k_ntt_digits(const double* __restrict__ src, size_t src_stride, int dnum, KsDigi
 // transform-domain Galois permutation of output o's key, none for
 // relinearisation) while gathering the inverse transform's first pass, then
 // inverse-transforms both accumulators into u[o][k][limb] (coefficient form).
-// Output o reads the digits of source o / d_div.
-template <int LOGN, int LOGE>
+// Output o reads the digits of source o / d_div.  SPLIT: a block computes only one of the two
+// parts (twice the blocks, each with half the inner product and one inverse transform), for
+// launches too small to fill the device, whose time is the latency of one block.
+template <int LOGN, int LOGE, bool SPLIT>
 __global__ void __launch_bounds__(1 << (LOGN - LOGE))
 k_ks_intt(const double* __restrict__ D, int d_div, KeySel ka, int level, int dnum, int L, Basis qp, Tables tb,
           double* __restrict__ u) {
@@ -674,10 +676,12 @@ k_ks_intt(const double* __restrict__ D, int d_div, KeySel ka, int level, int dnu
   constexpr int C0 = Sched<LOGN, LOGE, true>::c(0);
   constexpr int SZ0 = 1 << C0, G0 = E >> C0;
   extern __shared__ double lds[];
-  const int nb = qp.n, nout = gridDim.x / nb;
+  const int nb = qp.n, nout = gridDim.x / (nb * (SPLIT ? 2 : 1));
   // limb-major: the blocks of one XCD share one or two target limbs, so that limb's key
   // parts (2 dnum limbs, read by every output) stay in that XCD's L2
-  const int w = xcd_order(blockIdx.x, gridDim.x);
+  const int wx = xcd_order(blockIdx.x, gridDim.x);
+  const int part = SPLIT ? (wx & 1) : 0;
+  const int w = SPLIT ? (wx >> 1) : wx;
   const int limb = w / nout, o = w - limb * nout;
   const int pid = qp.id[limb];
   const Mod m = tb.mods[pid];
@@ -708,33 +712,34 @@ k_ks_intt(const double* __restrict__ D, int d_div, KeySel ka, int level, int dnu
     for (int e = 0; e < CH; ++e) a0[e] = a1[e] = 0.0;
     for (int j = 0; j < dnum; ++j) {
       const double* dj = dd + (size_t)j * nb * N;
-      const double* k0 = key + ((size_t)(j * 2) * KL + klimb) * N;
+      const double* k0 = key + ((size_t)(j * 2 + part) * KL + klimb) * N;
       const double* k1 = key + ((size_t)(j * 2 + 1) * KL + klimb) * N;
       double dv[CH], kv0[CH], kv1[CH];
 #pragma unroll
       for (int e = 0; e < CH; ++e) {
         dv[e] = dj[srcw[e]];
         kv0[e] = k0[pos[e]];
-        kv1[e] = k1[pos[e]];
+        if (!SPLIT) kv1[e] = k1[pos[e]];
       }
 #pragma unroll
       for (int e = 0; e < CH; ++e) {
         a0[e] += mul_lazy(dv[e], kv0[e], m);
-        a1[e] += mul_lazy(dv[e], kv1[e], m);
+        if (!SPLIT) a1[e] += mul_lazy(dv[e], kv1[e], m);
       }
     }
 #pragma unroll
     for (int e = 0; e < CH; ++e) {
       x[c0 + e] = reduce(a0[e], m);
-      acc1[c0 + e] = reduce(a1[e], m);
+      if (!SPLIT) acc1[c0 + e] = reduce(a1[e], m);
     }
   }
   const double* iw = tb.inv + (size_t)pid * N;
   const double* post = tb.post + (size_t)pid * N;
-  run_pass<LOGN, LOGE, true, 0, true, false>(x, lds, nullptr, u + ((size_t)(o * 2) * nb + limb) * N, iw, post, m,
-                                             tid);
-  run_pass<LOGN, LOGE, true, 0, true, false>(acc1, lds, nullptr, u + ((size_t)(o * 2 + 1) * nb + limb) * N, iw, post,
+  run_pass<LOGN, LOGE, true, 0, true, false>(x, lds, nullptr, u + ((size_t)(o * 2 + part) * nb + limb) * N, iw, post,
                                              m, tid);
+  if (!SPLIT)
+    run_pass<LOGN, LOGE, true, 0, true, false>(acc1, lds, nullptr, u + ((size_t)(o * 2 + 1) * nb + limb) * N, iw,
+                                               post, m, tid);
 }
 
 template <int LOGN, int LOGE>
@@ -755,9 +760,13 @@ void launch_ks_split(const Context& c, int part, const double* src, size_t strid
     BCN_HIP(hipGetLastError());
   }
   const unsigned b2 = part == 2 ? (unsigned)n_out * qp.n : 0u;
-  if (b2 > 0) {
-    hipLaunchKernelGGL((k_ks_intt<LOGN, LOGE>), dim3(b2), dim3(N >> LOGE), lds, s, D, d_div, ks, level, dnum, c.L, qp,
-                       c.tab, u);
+  if (b2 > 0 && (int)b2 < c.n_cus) {
+    // too few blocks to fill the device: one block per part halves each block's latency
+    hipLaunchKernelGGL((k_ks_intt<LOGN, LOGE, true>), dim3(2 * b2), dim3(N >> LOGE), lds, s, D, d_div, ks, level, dnum,
+                       c.L, qp, c.tab, u);
+  } else if (b2 > 0) {
+    hipLaunchKernelGGL((k_ks_intt<LOGN, LOGE, false>), dim3(b2), dim3(N >> LOGE), lds, s, D, d_div, ks, level, dnum,
+                       c.L, qp, c.tab, u);
     BCN_HIP(hipGetLastError());
   }
 }
@@ -785,7 +794,10 @@ void set_attr() {
                               lds));
   BCN_HIP(hipFuncSetAttribute((const void*)k_ntt_digits<LOGN, LOGE, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
   BCN_HIP(hipFuncSetAttribute((const void*)k_ntt_digits<LOGN, LOGE, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-  BCN_HIP(hipFuncSetAttribute((const void*)k_ks_intt<LOGN, LOGE>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+  BCN_HIP(hipFuncSetAttribute((const void*)k_ks_intt<LOGN, LOGE, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              lds));
+  BCN_HIP(hipFuncSetAttribute((const void*)k_ks_intt<LOGN, LOGE, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              lds));
 }
 
 template <int LOGN, int LOGE>
