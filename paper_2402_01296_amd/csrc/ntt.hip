@@ -698,6 +698,49 @@ k_ks_intt(const double* __restrict__ D, int d_div, KeySel ka, int level, int dnu
   // round trip per digit instead of one per element and digit.
   constexpr int CH = 4;
   double x[E], acc1[E];
+  if (gal != 1) {
+    // Rotations: the Galois permutation scatters the digit reads over the whole limb.  Each
+    // digit limb is staged in LDS with coalesced loads and the permuted reads come from LDS;
+    // the key words are read in storage order (coalesced) as before.
+#pragma unroll
+    for (int e = 0; e < E; ++e) x[e] = acc1[e] = 0.0;
+    for (int j = 0; j < dnum; ++j) {
+      const double* dj = dd + (size_t)j * nb * N;
+      __syncthreads();                       // the previous digit's reads are done
+#pragma unroll 4
+      for (int p = tid; p < N; p += T) lds[p] = dj[p];
+      __syncthreads();
+      const double* k0 = key + ((size_t)(j * 2 + part) * KL + klimb) * N;
+      const double* k1 = key + ((size_t)(j * 2 + 1) * KL + klimb) * N;
+#pragma unroll
+      for (int c0 = 0; c0 < E; c0 += CH) {
+        int pos[CH];
+        double dv[CH], kv0[CH], kv1[CH];
+#pragma unroll
+        for (int e = 0; e < CH; ++e) {
+          const int gi = ((c0 + e) / SZ0 * T + tid) * SZ0 + (c0 + e) % SZ0;
+          pos[e] = ntt_store(gi, LOGN);
+          dv[e] = lds[ntt_store(ntt_perm(gi, gal, LOGN), LOGN)];
+        }
+#pragma unroll
+        for (int e = 0; e < CH; ++e) {
+          kv0[e] = k0[pos[e]];
+          if (!SPLIT) kv1[e] = k1[pos[e]];
+        }
+#pragma unroll
+        for (int e = 0; e < CH; ++e) {
+          x[c0 + e] += mul_lazy(dv[e], kv0[e], m);
+          if (!SPLIT) acc1[c0 + e] += mul_lazy(dv[e], kv1[e], m);
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      x[e] = reduce(x[e], m);
+      if (!SPLIT) acc1[e] = reduce(acc1[e], m);
+    }
+    __syncthreads();                         // the transform's exchanges reuse the LDS
+  } else {
 #pragma unroll
   for (int c0 = 0; c0 < E; c0 += CH) {
     int pos[CH], srcw[CH];
@@ -705,7 +748,7 @@ k_ks_intt(const double* __restrict__ D, int d_div, KeySel ka, int level, int dnu
     for (int e = 0; e < CH; ++e) {
       const int gi = ((c0 + e) / SZ0 * T + tid) * SZ0 + (c0 + e) % SZ0;
       pos[e] = ntt_store(gi, LOGN);
-      srcw[e] = gal == 1 ? pos[e] : ntt_store(ntt_perm(gi, gal, LOGN), LOGN);
+      srcw[e] = pos[e];
     }
     double a0[CH], a1[CH];
 #pragma unroll
@@ -732,6 +775,7 @@ k_ks_intt(const double* __restrict__ D, int d_div, KeySel ka, int level, int dnu
       x[c0 + e] = reduce(a0[e], m);
       if (!SPLIT) acc1[c0 + e] = reduce(a1[e], m);
     }
+  }
   }
   const double* iw = tb.inv + (size_t)pid * N;
   const double* post = tb.post + (size_t)pid * N;
