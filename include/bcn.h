@@ -110,6 +110,51 @@ int bcn_encode_encrypt(bcn_context* ctx, const bcn_secret_key* sk, const int64_t
 int bcn_decrypt_decode(bcn_context* ctx, const bcn_secret_key* sk, const double* ct, int n, int level,
                        int64_t* slots_out, bcn_stream stream);
 
+/* ---- client side: seeded randomness ----
+ * The paper leaves the randomness of keys and encryptions to the scheme
+ * (appendix "CKKS Scheme": a uniform, s and e small).  These calls draw it
+ * from ChaCha20 keystreams (the block function of RFC 8439, section 2.3) so
+ * that a seed fixes every key and ciphertext bit for bit.  Stream
+ * (seed, purpose, index): key = seed as 8 little-endian bytes then 24 zero
+ * bytes; nonce = the 32-bit words (purpose, index >> 32, index & 0xffffffff);
+ * block counter from 0; each 64-bit value is two consecutive little-endian
+ * keystream words, low word first.  Samplers (fixed consumption):
+ *   ternary   (u mod 3) - 1
+ *   uniform q (u_hi 2^64 + u_lo) mod q from two consecutive values
+ *   Gaussian  sigma = 3.2 on [-19, 19] by a cumulative table:
+ *             T_k = floor(2^64 CDF(k)), k = -19..18; e = -19 + #{k : u >= T_k}
+ * Host-only; the result depends on nothing but the arguments. */
+enum { BCN_SAMPLE_TERNARY = 0, BCN_SAMPLE_UNIFORM = 1, BCN_SAMPLE_GAUSSIAN = 2 };
+enum {
+  BCN_PURPOSE_SECRET = 1, /* index 0: the secret key s */
+  BCN_PURPOSE_KSK_A = 2,  /* index (key << 32) | (digit (L+K) + prime): a of a key-switching key */
+  BCN_PURPOSE_KSK_E = 3,  /* index (key << 32) | digit: its error; key = 0 (relin) or the Galois element k */
+  BCN_PURPOSE_ENC_A = 4,  /* index (ct << 32) | prime: a of encryption number ct, residues mod q_prime */
+  BCN_PURPOSE_ENC_E = 5   /* index ct << 32: its error */
+};
+/* Writes n samples of `kind` from stream (seed, purpose, index) to out (host int64 [n]);
+ * q is the modulus of BCN_SAMPLE_UNIFORM (2 .. 2^62), ignored otherwise. */
+int bcn_sample(int kind, uint64_t seed, uint32_t purpose, uint64_t index, uint64_t q, int n, int64_t* out);
+/* The 38 Gaussian thresholds T_k (host uint64 out[38]). */
+int bcn_gaussian_table(uint64_t* out);
+/* s = ternary from stream (seed, BCN_PURPOSE_SECRET, 0); same object as bcn_secret_key_create. */
+int bcn_secret_key_generate(bcn_context* ctx, uint64_t seed, bcn_secret_key** out);
+/* bcn_keygen with a_j (residue over prime i of Q then P) uniform from stream
+ * (seed, BCN_PURPOSE_KSK_A, (key << 32) | (j (L+K) + i)) and e_j Gaussian from
+ * (seed, BCN_PURPOSE_KSK_E, (key << 32) | j); key = 0 for BCN_KEY_RELIN, else
+ * the Galois element of `step`.  The host buffers are the library's own. */
+int bcn_keygen_seeded(bcn_context* ctx, const bcn_secret_key* sk, bcn_eval_keys* ek, int kind, int step,
+                      uint64_t seed, bcn_stream stream);
+/* bcn_encode_encrypt (BFV context) or bcn_ckks_encode_encrypt (CKKS context; slots
+ * host double [n][N/2] at `scale`) with the randomness of ciphertext r taken from
+ * index ct = first + r: a over q_1..q_level uniform from (seed, BCN_PURPOSE_ENC_A,
+ * (ct << 32) | i), e Gaussian from (seed, BCN_PURPOSE_ENC_E, ct << 32); first + n
+ * must not exceed 2^32. */
+int bcn_encrypt_seeded(bcn_context* ctx, const bcn_secret_key* sk, const int64_t* slots, uint64_t seed,
+                       uint64_t first, int n, int level, double* ct_out, bcn_stream stream);
+int bcn_ckks_encrypt_seeded(bcn_context* ctx, const bcn_secret_key* sk, const double* slots, double scale,
+                            uint64_t seed, uint64_t first, int n, int level, double* ct_out, bcn_stream stream);
+
 /* Coefficient-form transfer: host uint64 [n][2][level][N] <-> device ciphertexts. */
 int bcn_ct_export(bcn_context* ctx, const double* ct, int n, int level, uint64_t* host_out, bcn_stream stream);
 int bcn_ct_import(bcn_context* ctx, const uint64_t* host_in, int n, int level, double* ct, bcn_stream stream);

@@ -110,3 +110,30 @@ def gaussian(st: Stream, n: int, table=None) -> list[int]:
         u = st.next()
         out.append(-BOUND + sum(1 for x in t if u >= x))
     return out
+
+
+# --------------------------------------------------------------- scheme randomness
+# Stream indices: a key-switching key is numbered 0 (relinearisation) or by its Galois
+# element k; digit j, prime position i over (Q primes, P primes) of width w = L + K.
+# Encryption number r: prime position i over q_1..q_level.
+
+def secret(seed: int, n: int) -> list[int]:
+    """The ternary secret key s."""
+    return ternary(Stream(seed, P_SECRET, 0), n)
+
+
+def ksk_randomness(seed: int, key: int, moduli, dnum: int, n: int):
+    """(a, e) of one key-switching key: a[j][i] uniform mod moduli[i], e[j] Gaussian."""
+    w = len(moduli)
+    a = [[uniform(Stream(seed, P_KSK_A, (key << 32) | (j * w + i)), q, n) for i, q in enumerate(moduli)]
+         for j in range(dnum)]
+    table = cdt_thresholds()
+    e = [gaussian(Stream(seed, P_KSK_E, (key << 32) | j), n, table) for j in range(dnum)]
+    return a, e
+
+
+def enc_randomness(seed: int, index: int, moduli, n: int):
+    """(a, e) of encryption number `index`: a[i] uniform mod moduli[i] (q_1..q_level), e Gaussian."""
+    a = [uniform(Stream(seed, P_ENC_A, (index << 32) | i), q, n) for i, q in enumerate(moduli)]
+    e = gaussian(Stream(seed, P_ENC_E, index << 32), n)
+    return a, e

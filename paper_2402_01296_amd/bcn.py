@@ -19,6 +19,8 @@ BCN_KEY_RELIN, BCN_KEY_ROTATION = 0, 1
 BCN_CONV2D, BCN_DENSE, BCN_POOL = 0, 1, 2
 BCN_DENSE_WEIGHT_VECTORS, BCN_DENSE_DIAGONAL = 0, 1
 BCN_PACK_BATCH, BCN_PACK_HW = 0, 1
+BCN_SAMPLE_TERNARY, BCN_SAMPLE_UNIFORM, BCN_SAMPLE_GAUSSIAN = 0, 1, 2
+BCN_PURPOSE_SECRET, BCN_PURPOSE_KSK_A, BCN_PURPOSE_KSK_E, BCN_PURPOSE_ENC_A, BCN_PURPOSE_ENC_E = 1, 2, 3, 4, 5
 BCN_OK, BCN_ERR_INVALID, BCN_ERR_LEVEL, BCN_ERR_KEY, BCN_ERR_NOMEM, BCN_ERR_HIP, BCN_ERR_INTERNAL = 0, -1, -2, -3, -4, -5, -6
 
 
@@ -108,6 +110,12 @@ _SIGS = {
     "bcn_ckks_square_relin_rescale": (_I, [_VP, _VP, _VP, _VP, _I, _I, _VP]),
     "bcn_scratch_info": (_I, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "bcn_scratch_release": (_I, [_VP]),
+    "bcn_sample": (_I, [_I, C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64, _I, _I64P]),
+    "bcn_gaussian_table": (_I, [_U64P]),
+    "bcn_secret_key_generate": (_I, [_VP, C.c_uint64, C.POINTER(_VP)]),
+    "bcn_keygen_seeded": (_I, [_VP, _VP, _VP, _I, _I, C.c_uint64, _VP]),
+    "bcn_encrypt_seeded": (_I, [_VP, _VP, _I64P, C.c_uint64, C.c_uint64, _I, _I, _VP, _VP]),
+    "bcn_ckks_encrypt_seeded": (_I, [_VP, _VP, _VP, C.c_double, C.c_uint64, C.c_uint64, _I, _I, _VP, _VP]),
 }
 
 
@@ -147,6 +155,19 @@ def _stream():
 
 def _dptr(t):
     return C.c_void_p(t.data_ptr())
+
+
+def sample(kind, seed, purpose, index, n, q=0):
+    """n samples of `kind` (BCN_SAMPLE_*) from the ChaCha20 stream (seed, purpose, index)."""
+    out = np.zeros(n, dtype=np.uint64 if kind == BCN_SAMPLE_UNIFORM else np.int64)
+    _check(lib().bcn_sample(kind, seed, purpose, index, q, n, out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def gaussian_table():
+    out = np.zeros(38, dtype=np.uint64)
+    _check(lib().bcn_gaussian_table(out.ctypes.data_as(C.c_void_p)))
+    return [int(x) for x in out]
 
 
 class Context:
@@ -200,6 +221,31 @@ class Context:
         h = C.c_void_p()
         _check(lib().bcn_secret_key_create(self.h, p, C.byref(h)))
         return SecretKey(self, h)
+
+    def secret_key_seeded(self, seed):
+        h = C.c_void_p()
+        _check(lib().bcn_secret_key_generate(self.h, seed, C.byref(h)))
+        return SecretKey(self, h)
+
+    def keygen_seeded(self, sk, ek, kind, step, seed):
+        _check(lib().bcn_keygen_seeded(self.h, sk.h, ek.h, kind, step, seed, _stream()))
+
+    def encrypt_seeded(self, sk, slots, seed, first=0, level=None):
+        level = self.L if level is None else level
+        slots, sp = _np_ptr(slots, np.int64)
+        n = slots.shape[0]
+        ct = self.empty_ct(n, level)
+        _check(lib().bcn_encrypt_seeded(self.h, sk.h, sp, seed, first, n, level, _dptr(ct), _stream()))
+        return ct
+
+    def ckks_encrypt_seeded(self, sk, slots, scale, seed, first=0, level=None):
+        level = self.L if level is None else level
+        slots, sp = _np_ptr(slots, np.float64)
+        n = slots.shape[0]
+        ct = self.empty_ct(n, level)
+        _check(lib().bcn_ckks_encrypt_seeded(self.h, sk.h, sp, C.c_double(scale), seed, first, n, level,
+                                             _dptr(ct), _stream()))
+        return ct
 
     def eval_keys(self):
         h = C.c_void_p()

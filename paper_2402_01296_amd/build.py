@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libbcn.so")
-SOURCES = ["ntt.hip", "kernels.hip", "context.hip", "scheme.hip", "layers.hip", "tune.hip", "noalloc.hip", "ckks.hip", "capi.hip"]
+SOURCES = ["ntt.hip", "kernels.hip", "context.hip", "scheme.hip", "layers.hip", "tune.hip", "noalloc.hip", "ckks.hip", "sampler.hip", "capi.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -5,6 +5,7 @@
 
 #include "../../include/bcn.h"
 #include "layers.h"
+#include "sampler.h"
 
 struct bcn_context { bcn::Context* c; };
 struct bcn_secret_key { bcn::SecretKey* k; };
@@ -61,6 +62,24 @@ void need_scheme(const bcn::Context& c, int scheme) {
   if (c.scheme != scheme)
     throw bcn::Error(BCN_ERR_INVALID, scheme ? "a CKKS operation needs a CKKS context"
                                              : "a BFV operation needs a BFV context (this one is CKKS)");
+}
+// a [n][level][N] and e [n][N] of encryptions first .. first + n - 1
+void encryption_randomness(const bcn::Context& c, uint64_t seed, uint64_t first, int n, int level,
+                           std::vector<uint64_t>& a, std::vector<int8_t>& e) {
+  if (first + (uint64_t)n > (1ull << 32)) throw bcn::Error(BCN_ERR_INVALID, "encryption index beyond 2^32");
+  a.resize((size_t)n * level * c.n);
+  e.resize((size_t)n * c.n);
+  std::vector<int64_t> tmp(c.n);
+  for (int r = 0; r < n; ++r) {
+    const uint64_t id = (first + (uint64_t)r) << 32;
+    for (int i = 0; i < level; ++i) {
+      bcn::Stream st(seed, bcn::kPurposeEncA, id | (uint64_t)i);
+      bcn::sample_uniform(st, c.primes[i], c.n, a.data() + ((size_t)r * level + i) * c.n);
+    }
+    bcn::Stream st(seed, bcn::kPurposeEncE, id);
+    bcn::sample_gaussian(st, c.n, tmp.data());
+    for (int k = 0; k < c.n; ++k) e[(size_t)r * c.n + k] = (int8_t)tmp[k];
+  }
 }
 }  // namespace
 
@@ -197,6 +216,109 @@ int bcn_decrypt_decode(bcn_context* ctx, const bcn_secret_key* sk, const double*
     check_ptr(ct, "ct");
     check_ptr(slots_out, "slots_out");
     bcn::decrypt(c, *sk->k, ct, n, level, slots_out, (hipStream_t)stream);
+  });
+}
+
+int bcn_sample(int kind, uint64_t seed, uint32_t purpose, uint64_t index, uint64_t q, int n, int64_t* out) {
+  return guard([&] {
+    check_n(n);
+    if (n == 0) return;
+    check_ptr(out, "out");
+    bcn::Stream st(seed, purpose, index);
+    if (kind == BCN_SAMPLE_TERNARY) {
+      bcn::sample_ternary(st, n, out);
+    } else if (kind == BCN_SAMPLE_GAUSSIAN) {
+      bcn::sample_gaussian(st, n, out);
+    } else if (kind == BCN_SAMPLE_UNIFORM) {
+      if (q < 2 || q > (1ull << 62)) throw bcn::Error(BCN_ERR_INVALID, "uniform modulus must be in [2, 2^62]");
+      bcn::sample_uniform(st, q, n, reinterpret_cast<uint64_t*>(out));
+    } else {
+      throw bcn::Error(BCN_ERR_INVALID, "bad sample kind");
+    }
+  });
+}
+
+int bcn_gaussian_table(uint64_t* out) {
+  return guard([&] {
+    check_ptr(out, "out");
+    const std::vector<uint64_t>& t = bcn::cdt_table();
+    std::memcpy(out, t.data(), t.size() * sizeof(uint64_t));
+  });
+}
+
+int bcn_secret_key_generate(bcn_context* ctx, uint64_t seed, bcn_secret_key** out) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    check_ptr(out, "out");
+    std::vector<int64_t> v(c.n);
+    bcn::Stream st(seed, bcn::kPurposeSecret, 0);
+    bcn::sample_ternary(st, c.n, v.data());
+    std::vector<int8_t> s(v.begin(), v.end());
+    *out = new bcn_secret_key{bcn::secret_key_create(c, s.data())};
+  });
+}
+
+int bcn_keygen_seeded(bcn_context* ctx, const bcn_secret_key* sk, bcn_eval_keys* ek, int kind, int step,
+                      uint64_t seed, bcn_stream stream) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    check_ptr(sk, "secret key");
+    check_ptr(ek, "eval keys");
+    if (kind != BCN_KEY_RELIN && kind != BCN_KEY_ROTATION) throw bcn::Error(BCN_ERR_INVALID, "bad key kind");
+    if (kind == BCN_KEY_ROTATION && (step == 0 || step <= -c.n / 2 || step >= c.n / 2))
+      throw bcn::Error(BCN_ERR_INVALID, "rotation step must be nonzero in (-N/2, N/2)");
+    const uint64_t key = kind == BCN_KEY_RELIN ? 0 : (uint64_t)bcn::galois_element(c, step);
+    const int dnum = c.dnum(c.L), width = c.L + c.K;
+    std::vector<uint64_t> a((size_t)dnum * width * c.n);
+    std::vector<int8_t> e((size_t)dnum * c.n);
+    std::vector<int64_t> tmp(c.n);
+    for (int j = 0; j < dnum; ++j) {
+      for (int i = 0; i < width; ++i) {
+        bcn::Stream st(seed, bcn::kPurposeKskA, (key << 32) | (uint64_t)(j * width + i));
+        bcn::sample_uniform(st, c.primes[i], c.n, a.data() + ((size_t)j * width + i) * c.n);
+      }
+      bcn::Stream st(seed, bcn::kPurposeKskE, (key << 32) | (uint64_t)j);
+      bcn::sample_gaussian(st, c.n, tmp.data());
+      for (int k = 0; k < c.n; ++k) e[(size_t)j * c.n + k] = (int8_t)tmp[k];
+    }
+    bcn::keygen(c, *sk->k, *ek->k, kind, step, a.data(), e.data(), (hipStream_t)stream);
+  });
+}
+
+
+int bcn_encrypt_seeded(bcn_context* ctx, const bcn_secret_key* sk, const int64_t* slots, uint64_t seed,
+                       uint64_t first, int n, int level, double* ct_out, bcn_stream stream) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    need_scheme(c, 0);
+    check_level(c, level);
+    check_n(n);
+    check_ptr(sk, "secret key");
+    if (n == 0) return;
+    check_ptr(slots, "slots");
+    check_ptr(ct_out, "ct_out");
+    std::vector<uint64_t> a;
+    std::vector<int8_t> e;
+    encryption_randomness(c, seed, first, n, level, a, e);
+    bcn::encrypt(c, *sk->k, slots, a.data(), e.data(), n, level, ct_out, (hipStream_t)stream);
+  });
+}
+
+int bcn_ckks_encrypt_seeded(bcn_context* ctx, const bcn_secret_key* sk, const double* slots, double scale,
+                            uint64_t seed, uint64_t first, int n, int level, double* ct_out, bcn_stream stream) {
+  return guard([&] {
+    bcn::Context& c = ctxof(ctx);
+    need_scheme(c, 1);
+    check_level(c, level);
+    check_n(n);
+    check_ptr(sk, "secret key");
+    if (n == 0) return;
+    check_ptr(slots, "slots");
+    check_ptr(ct_out, "ct_out");
+    std::vector<uint64_t> a;
+    std::vector<int8_t> e;
+    encryption_randomness(c, seed, first, n, level, a, e);
+    bcn::ckks_encrypt(c, *sk->k, slots, scale, a.data(), e.data(), n, level, ct_out, (hipStream_t)stream);
   });
 }
 
