@@ -234,18 +234,28 @@ def key_switch(prm: Params, x, key: KSKey, level: int):
 
 
 def _ks_inner(prm: Params, digits, key: KSKey, level: int):
-    Q = prm.Q(level)
-    P = prm.P
-    QP = Q * P
+    u0, u1 = ks_extended(prm, digits, key, level)
+    return mod_down(prm, u0, level), mod_down(prm, u1, level)
+
+
+def ks_extended(prm: Params, digits, key: KSKey, level: int):
+    """The key switch before its division by P: u_k = sum_j D_j * key_j[k] mod Q_l P."""
+    QP = prm.Q(level) * prm.P
     out = []
     for part in (0, 1):
         u = [0] * prm.n
         for j, D in enumerate(digits):
             k = [v % QP for v in key.parts[j][part]]
             u = [x + y for x, y in zip(u, ring.negacyclic_mul(D, k))]
-        u = [x % QP for x in u]
-        out.append([((x - nt.centered(x, P)) // P) % Q for x in u])
+        out.append([x % QP for x in u])
     return out[0], out[1]
+
+
+def mod_down(prm: Params, x, level: int) -> list[int]:
+    """ModDown: the nearest integer to x / P, mod Q_l, for x in [0, Q_l P)
+    (x minus its centred residue mod P is divisible by P)."""
+    Q, P = prm.Q(level), prm.P
+    return [((v - nt.centered(v, P)) // P) % Q for v in x]
 
 
 def relinearize(prm: Params, d, rk: KSKey, level: int) -> Ct:
@@ -299,6 +309,69 @@ def rotate_hoisted(prm: Params, a: Ct, rs, gks) -> list[Ct]:
         c0 = ring.reduce(ring.automorphism(a.c0, k), Q)
         out.append(Ct(ring.add(c0, k0, Q), k1, a.level))
     return out
+
+
+# ---------------------------------------------------------------- rotations with deferred ModDown
+#
+# A weighted sum of rotations (a convolution's taps) needs the division by P of the key
+# switch only once, after the sum: each rotation is kept over Q_l P scaled by P,
+#   Rot~(c, r) = (P sigma_k(c0) + u0, u1),  u = sum_j sigma_k(D_j) key_j  mod Q_l P,
+#   Rot~(c, 0) = (P c0, P c1),
+# which decrypts under s to P Rot(c, r) plus the key-switching error, and the sum (times
+# any plaintext) is brought back to Q_l by one ModDown.  The P-multiples pass through the
+# rounding exactly, so only the key-switching terms are rounded, once.
+
+def _digits(prm: Params, x, level: int):
+    out = []
+    for j in range(prm.dnum(level)):
+        Qj = 1
+        for qq in prm.digit_primes(j, level):
+            Qj *= qq
+        out.append(ring.lift_c(x, Qj))
+    return out
+
+
+def rotations_extended(prm: Params, a: Ct, rs, gks) -> list:
+    """[(e0, e1)] over Q_l P for each step r (0 = the ciphertext itself; its key is unused),
+    from one digit decomposition of c1."""
+    level = a.level
+    QP = prm.Q(level) * prm.P
+    P = prm.P
+    digits = _digits(prm, a.c1, level)
+    out = []
+    for r, gk in zip(rs, gks):
+        if r == 0:
+            out.append(([(P * v) % QP for v in a.c0], [(P * v) % QP for v in a.c1]))
+            continue
+        k = galois_element(prm, r)
+        u0, u1 = ks_extended(prm, [ring.automorphism(D, k) for D in digits], gk, level)
+        c0 = ring.automorphism(a.c0, k)
+        out.append(([(P * x + y) % QP for x, y in zip(c0, u0)], u1))
+    return out
+
+
+def mac_extended(prm: Params, exts, weights, level: int):
+    """sum_j w_j * ext_j mod Q_l P (small signed integer weights)."""
+    QP = prm.Q(level) * prm.P
+    acc = [[0] * prm.n, [0] * prm.n]
+    for ext, w in zip(exts, weights):
+        w = int(w)
+        if w == 0:
+            continue
+        for part in (0, 1):
+            acc[part] = [x + w * y for x, y in zip(acc[part], ext[part])]
+    return tuple([x % QP for x in a] for a in acc)
+
+
+def mul_plain_extended(prm: Params, ext, m, level: int):
+    """Both parts times the centred lift of the plaintext m (coefficients mod t), mod Q_l P."""
+    QP = prm.Q(level) * prm.P
+    ml = ring.lift_c(m, prm.t)
+    return tuple(ring.reduce(ring.negacyclic_mul(part, ml), QP) for part in ext)
+
+
+def mod_down_ct(prm: Params, ext, level: int) -> Ct:
+    return Ct(mod_down(prm, ext[0], level), mod_down(prm, ext[1], level), level)
 
 
 # ---------------------------------------------------------------- modulus switching

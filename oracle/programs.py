@@ -277,7 +277,8 @@ class OracleSession:
         return res
 
     def rotated_input(self, li: int, ct):
-        """One input channel of HW conv layer li rotated by every kernel offset (hoisted)."""
+        """One input channel of layer li rotated by every kernel offset (hoisted), each
+        rotation complete (brought back to Q_l)."""
         offs = self.plan["layers"][li]["offsets"]
         nz = [o for o in offs if o]
         rots = bfv.rotate_hoisted(self.prm, ct, nz, [self.gk[o] for o in nz])
@@ -285,26 +286,38 @@ class OracleSession:
         table[0] = ct
         return [table[o] for o in offs]
 
-    def conv_hw(self, li: int, cts: dict, outputs=None, rot=None) -> dict:
-        """HW conv layer li for output maps ``outputs``; ``rot`` may carry the inputs already
-        rotated by rotated_input (channel -> list over the kernel offsets)."""
+    def extended_input(self, li: int, ct):
+        """One input channel of HW conv / pooling layer li at every kernel offset, kept over
+        Q_l P before ModDown (hoisted digits; the offset 0 tap is P times the input)."""
+        offs = self.plan["layers"][li]["offsets"]
+        nz = [o for o in offs if o]
+        ext = bfv.rotations_extended(self.prm, ct, [0] + nz, [None] + [self.gk[o] for o in nz])
+        table = dict(zip([0] + nz, ext))
+        return [table[o] for o in offs]
+
+    def conv_hw(self, li: int, cts: dict, outputs=None, ext=None) -> dict:
+        """HW conv layer li for output maps ``outputs``: the taps of every input channel over
+        Q_l P (``ext`` may carry them, channel -> list over the kernel offsets, as made by
+        extended_input), summed with the weights, times the output mask, then one ModDown;
+        then the features and the activation."""
         prm, info = self.prm, self.plan["layers"][li]
         w = self.inputs["weights"][li]
         O, cin, k, _ = w.shape
-        if rot is None:
-            rot = {c: self.rotated_input(li, cts[c]) for c in range(cin)}
+        level = cts[0].level
+        if ext is None:
+            ext = {c: self.extended_input(li, cts[c]) for c in range(cin)}
         mask = self.enc.encode(self.mask_slots(li))
         outputs = range(O) if outputs is None else outputs
         res = {}
         for o in outputs:
             terms, ws = [], []
             for c in range(cin):
-                for t_i, ct in enumerate(rot[c]):
+                for t_i, e in enumerate(ext[c]):
                     di, dj = divmod(t_i, k)
-                    terms.append(ct)
+                    terms.append(e)
                     ws.append(int(w[o, c, di, dj]))
-            ct = bfv.mac(prm, terms, ws)
-            ct = bfv.mul_plain(prm, ct, mask)
+            acc = bfv.mac_extended(prm, terms, ws, level)
+            ct = bfv.mod_down_ct(prm, bfv.mul_plain_extended(prm, acc, mask, level), level)
             if info.get("features"):
                 ct = bfv.add_plain(prm, ct, self.enc.encode(self.feature_slots(li, o)))
             ct = self._activation(ct, info)
@@ -314,15 +327,17 @@ class OracleSession:
         return res
 
     def pool_hw(self, li: int, cts: dict) -> dict:
-        """Local sum pooling, channel by channel: rotations by the window offsets, summed,
-        then the mask of the strided outputs (appendix "Implementation Details", pooling
-        layer: a convolution without weights)."""
+        """Local sum pooling, channel by channel: the window offsets' taps over Q_l P, summed,
+        times the mask of the strided outputs, then one ModDown (appendix "Implementation
+        Details", pooling layer: a convolution without weights)."""
         prm, info = self.prm, self.plan["layers"][li]
         mask = self.enc.encode(self.mask_slots(li))
         res = {}
         for c in sorted(cts):
-            taps = self.rotated_input(li, cts[c])
-            res[c] = bfv.mul_plain(prm, bfv.mac(prm, taps, [1] * len(taps)), mask)
+            level = cts[c].level
+            taps = self.extended_input(li, cts[c])
+            acc = bfv.mac_extended(prm, taps, [1] * len(taps), level)
+            res[c] = bfv.mod_down_ct(prm, bfv.mul_plain_extended(prm, acc, mask, level), level)
         return res
 
     def dense_diag(self, li: int, cts: dict) -> dict:

@@ -260,15 +260,18 @@ struct MacPlan {
 // requests > 1: independent requests at in + r*in_req, out + r*out_req (doubles)
 // out_ct, out_part (doubles): output row r's part k starts at out + r * out_ct + k * out_part
 // (0: contiguous [rows][2][level][N]); e.g. the Q limbs of a [rows][2][level+m][N] buffer
+// basis: the limbs of each part when they are not Q_level (e.g. Q_level then P); then
+// `level` only selects the delta constants and delta_msg must be null.
 void mac(const Context& c, const MacPlan& p, const double* in, double* out, int level, hipStream_t s, int requests = 1,
          size_t in_req = 0, size_t out_req = 0, const double* delta_msg = nullptr, size_t out_ct = 0,
-         size_t out_part = 0);
+         size_t out_part = 0, const Basis* basis = nullptr);
 
 // c0 of each ciphertext += Delta(m_i), m_i in [0, t) coefficient form, [n][N]
 void add_delta(const Context& c, double* ct, int n, int level, const double* m, hipStream_t s);
 // out[k] = in[k] (.) pt  (NTT domain); pt [level][N] shared, or [n][level][N] when per_ct
+// (basis: the limbs when they are not Q_level)
 void mul_plain_ntt(const Context& c, const double* in, double* out, int n, int level, const double* pt,
-                   bool per_ct, hipStream_t s);
+                   bool per_ct, hipStream_t s, const Basis* basis = nullptr);
 // out[k] = sum_c in[c] (.) pt[k][c]  (NTT domain); pt [n_out][n_in][level][N]
 void ptvec_mac_ntt(const Context& c, const double* in, int n_in, double* out, int n_out, int level,
                    const double* pt, hipStream_t s, int requests = 1);
@@ -307,6 +310,24 @@ void ks_inner(const Context& c, const double* D, int d_div, const KeySel& ks, in
 // the transform-domain permutation, and ks must then carry none (galois 1).
 void ks_split(const Context& c, const double* src, size_t src_stride, int n_src, int level, const KeySel& ks,
               int n_out, int d_div, double* D, double* u, hipStream_t s, int src_galois = 1);
+// Rotations kept over Q_l P before ModDown (the taps of a convolution whose weighted sum
+// is divided by P once): output o = P sigma(c0) + sum_j sigma(D_j) key_j[0] on the Q limbs
+// (the key term alone on the P limbs) and sum_j sigma(D_j) key_j[1], in the transform
+// domain, written at u + (o / out_div) * out_outer + (o % out_div) * 2 (level + K) N.
+// c0hat: the sources' part 0 transformed over Q_level, source i at c0hat + i * c0_stride.
+struct KsExt {
+  const double* c0hat = nullptr;
+  size_t c0_stride = 0;
+  int out_div = 1;
+  size_t out_outer = 0;
+  double pm[kMaxBasis] = {};   // P mod q_i, i < level
+};
+void ks_extended(const Context& c, const double* src, size_t src_stride, int n_src, int level, const KeySel& ks,
+                 int n_out, int d_div, double* D, double* u, const KsExt& ext, hipStream_t s);
+// Tap 0 of ks_extended's layout: P c^ on the Q limbs and 0 on the P limbs of each part, for
+// n sources c^ ([n][2][level][N], transform domain) into X + i * out_outer ([2][level + K][N]).
+void ext_tap0(const Context& c, const double* chat, int n, int level, const KsExt& ext, double* X, size_t out_outer,
+              hipStream_t s);
 // exact round(u/P) of u [n][2][level+K][N] (coeff) -> [n][2][level][N], plus an addend:
 // add_mode 0: none; 1: add [n][2][level][N]; 2: add sigma_k(add) to part 0 only (add [n][2][level][N]);
 // 3: add add itself and sigma_k of its part 0 (rotate-and-add; out must not alias add).
@@ -334,7 +355,8 @@ void modswitch(const Context& c, const double* in, double* out, int n, int level
 void automorphism_coeff(const Context& c, const double* in, double* out, int n, const Basis& b, int k,
                         hipStream_t s);
 // m [n][N] in [0, t): residues of lift_c(m) on each limb of Q_level -> [n][level][N]
-void lift_plain(const Context& c, const double* m, double* out, int n, int level, hipStream_t s);
+void lift_plain(const Context& c, const double* m, double* out, int n, int level, hipStream_t s,
+                const Basis* basis = nullptr);
 // slot values (int64, any representative) -> transform-domain vector mod t at the slot positions
 void slots_to_tdomain(const Context& c, const int64_t* slots, double* out, int n, hipStream_t s);
 // slot-batched FP32 features [requests][batch][stride_b] -> quantised plaintexts in the

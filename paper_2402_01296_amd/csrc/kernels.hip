@@ -138,6 +138,22 @@ __global__ void k_mul_plain(const double* __restrict__ in, double* __restrict__ 
   out[idx] = mul_mod(in[idx], p, m);
 }
 
+// P c^ on the Q limbs, 0 on the P limbs (tap 0 of the extended taps)
+__global__ void k_ext_tap0(const double* __restrict__ chat, int n, int level, int nb, int logn, KsExt ext, Basis b,
+                           const Mod* __restrict__ mods, double* __restrict__ X, size_t out_outer) {
+  const size_t N = (size_t)1 << logn;
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx >= (size_t)n * 2 * nb * N) return;
+  const size_t i = idx / (2 * nb * N);
+  const size_t r = idx % (2 * nb * N);
+  const int part = (int)(r / (nb * N));
+  const int limb = (int)((r >> logn) % nb);
+  const size_t k = idx & (N - 1);
+  double v = 0.0;
+  if (limb < level) v = mul_mod(chat[(i * 2 + part) * level * N + (size_t)limb * N + k], ext.pm[limb], mods[b.id[limb]]);
+  X[i * out_outer + r] = v;
+}
+
 __global__ void k_ptvec_mac(const double* __restrict__ in, int n_in, double* __restrict__ out, int n_out,
                             int level, int logn, const double* __restrict__ pt, Basis b,
                             const Mod* __restrict__ mods, int requests) {
@@ -664,11 +680,14 @@ void delta_consts(const Context& c, int level, double* qmodt_out, double* neg) {
 }  // namespace
 
 void mac(const Context& c, const MacPlan& p, const double* in, double* out, int level, hipStream_t s, int requests,
-         size_t in_req, size_t out_req, const double* delta_msg, size_t out_ct, size_t out_part) {
-  const int words = 2 * level * c.n;
+         size_t in_req, size_t out_req, const double* delta_msg, size_t out_ct, size_t out_part, const Basis* basis) {
+  if (basis && delta_msg) throw Error(-1, "the delta add needs the Q_level basis");
+  const Basis b = basis ? *basis : c.basis_Q(level);
+  const int nl = b.n;
+  const int words = 2 * nl * c.n;
   if (out_ct == 0) {
     out_ct = (size_t)words;
-    out_part = (size_t)level * c.n;
+    out_part = (size_t)nl * c.n;
   }
   if (p.n_out == 0 || requests == 0) return;
   DeltaAdd da;
@@ -681,15 +700,14 @@ void mac(const Context& c, const MacPlan& p, const double* in, double* out, int 
   // algorithmic work: one FMA per word for each nonzero (output, input) weight
   ProfScope ps(c, "mac", s, 8.0 * words * ((double)p.n_in + p.n_out) * requests, (double)words * p.nnz * requests);
   dim3 grid(nblocks(words), p.n_tiles, requests);
-  const Basis b = c.basis_Q(level);
   switch (p.tile) {
 #define BCN_MAC_CASE(TO)                                                                                  \
   case TO:                                                                                                \
     if (p.centre)                                                                                         \
-      hipLaunchKernelGGL((k_mac<TO, true>), grid, dim3(TPB), 0, s, in, out, words, c.logn, level, p.W, p.rows, \
+      hipLaunchKernelGGL((k_mac<TO, true>), grid, dim3(TPB), 0, s, in, out, words, c.logn, nl, p.W, p.rows, \
                          p.tile_ptr, p.tile_cols, p.chunk, b, c.tab.mods, in_req, out_req, out_ct, out_part, da); \
     else                                                                                                  \
-      hipLaunchKernelGGL((k_mac<TO, false>), grid, dim3(TPB), 0, s, in, out, words, c.logn, level, p.W,    \
+      hipLaunchKernelGGL((k_mac<TO, false>), grid, dim3(TPB), 0, s, in, out, words, c.logn, nl, p.W,       \
                          p.rows, p.tile_ptr, p.tile_cols, p.chunk, b, c.tab.mods, in_req, out_req, out_ct,   \
                          out_part, da);                                                                       \
     break;
@@ -698,6 +716,17 @@ void mac(const Context& c, const MacPlan& p, const double* in, double* out, int 
 #undef BCN_MAC_CASE
     default: throw Error(-1, "bad MAC tile");
   }
+  BCN_HIP(hipGetLastError());
+}
+
+void ext_tap0(const Context& c, const double* chat, int n, int level, const KsExt& ext, double* X, size_t out_outer,
+              hipStream_t s) {
+  if (n == 0) return;
+  const Basis b = c.basis_QP(level);
+  const size_t work = (size_t)n * 2 * b.n * c.n;
+  ProfScope ps(c, "ext_tap0", s, 8.0 * (double)n * 2 * c.n * (level + b.n));
+  hipLaunchKernelGGL(k_ext_tap0, dim3(nblocks(work)), dim3(TPB), 0, s, chat, n, level, b.n, c.logn, ext, b, c.tab.mods,
+                     X, out_outer);
   BCN_HIP(hipGetLastError());
 }
 
@@ -713,10 +742,11 @@ void add_delta(const Context& c, double* ct, int n, int level, const double* m, 
 }
 
 void mul_plain_ntt(const Context& c, const double* in, double* out, int n, int level, const double* pt, bool per_ct,
-                   hipStream_t s) {
+                   hipStream_t s, const Basis* basis) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_mul_plain, dim3(nblocks((size_t)n * 2 * level * c.n)), dim3(TPB), 0, s, in, out, n, level,
-                     c.logn, pt, per_ct ? 1 : 0, c.basis_Q(level), c.tab.mods);
+  const Basis b = basis ? *basis : c.basis_Q(level);
+  hipLaunchKernelGGL(k_mul_plain, dim3(nblocks((size_t)n * 2 * b.n * c.n)), dim3(TPB), 0, s, in, out, n, b.n,
+                     c.logn, pt, per_ct ? 1 : 0, b, c.tab.mods);
   BCN_HIP(hipGetLastError());
 }
 
@@ -931,10 +961,11 @@ void automorphism_coeff(const Context& c, const double* in, double* out, int n, 
   BCN_HIP(hipGetLastError());
 }
 
-void lift_plain(const Context& c, const double* m, double* out, int n, int level, hipStream_t s) {
+void lift_plain(const Context& c, const double* m, double* out, int n, int level, hipStream_t s, const Basis* basis) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_lift_plain, dim3(nblocks((size_t)n * level * c.n)), dim3(TPB), 0, s, m, out, n, level, c.logn,
-                     (double)c.t, c.basis_Q(level), c.tab.mods);
+  const Basis b = basis ? *basis : c.basis_Q(level);
+  hipLaunchKernelGGL(k_lift_plain, dim3(nblocks((size_t)n * b.n * c.n)), dim3(TPB), 0, s, m, out, n, b.n, c.logn,
+                     (double)c.t, b, c.tab.mods);
   BCN_HIP(hipGetLastError());
 }
 

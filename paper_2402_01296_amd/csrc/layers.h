@@ -22,7 +22,7 @@ struct Layer {
   std::vector<int> mac_order;
   std::vector<int> steps;        // HW conv: nonzero tap offsets, tap index = position + 1
   std::vector<int> all_steps;    // every Galois step the layer needs
-  double* mask_hat = nullptr;    // [level][N]
+  double* mask_hat_qp = nullptr; // [level + K][N]: the conv mask over Q_level then P
   double* ptv_hat = nullptr;     // [n_out][n_in][level][N]
   int* slot_of = nullptr;        // [per] output slot of each output position (HW)
   int per = 0;

@@ -12,7 +12,7 @@ namespace bcn {
 
 Layer::~Layer() {
   free_mac_plan(mac);
-  if (mask_hat) (void)hipFree(mask_hat);
+  if (mask_hat_qp) (void)hipFree(mask_hat_qp);
   if (ptv_hat) (void)hipFree(ptv_hat);
   if (slot_of) (void)hipFree(slot_of);
 }
@@ -166,9 +166,9 @@ Layer* layer_create(Context& c, const bcn_layer_desc& d, int level) {
     std::vector<int64_t> mask(N, 0);
     for (int b : bases)
       for (int v : so) mask[b + v] = 1;
-    BCN_HIP(hipMalloc(&L->mask_hat, (size_t)level * N * sizeof(double)));
+    BCN_HIP(hipMalloc(&L->mask_hat_qp, (size_t)(level + c.K) * N * sizeof(double)));
     c.arena->reset();
-    encode_plain_ntt(c, mask.data(), 1, level, L->mask_hat, nullptr);
+    encode_plain_ntt(c, mask.data(), 1, level, L->mask_hat_qp, nullptr, true);
     // feature slots of one output map: images in order, positions in (i, j) order
     std::vector<int> fo;
     for (int b : bases)
@@ -283,14 +283,20 @@ void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, doub
     ptvec_mac_ntt(c, taps, L.n_in * L.k2, A, 1, level, L.ptv_hat, s, R);
     ntt_inverse(c, A, 2 * nout, c.basis_Q(level), s);
   } else if (L.kind == BCN_CONV2D) {
-    // taps [R*n_in][k2]: tap 0 = the input, taps 1.. = hoisted rotations
-    double* taps = ar.take((size_t)nin * L.k2 * ctw);
-    copy_rows(in, ctw, taps, L.k2 * ctw, ctw, nin, s);
-    rotate_hoisted(c, ek, in, nin, level, L.steps, taps + ctw, s, (int)L.steps.size(), L.k2 * ctw);
-    mac(c, L.mac, taps, A, level, s, R, (size_t)L.n_in * L.k2 * ctw, (size_t)L.n_out * ctw);
-    ntt_forward(c, A, 2 * nout, c.basis_Q(level), s);
-    mul_plain_ntt(c, A, A, nout, level, L.mask_hat, false, s);
-    ntt_inverse(c, A, 2 * nout, c.basis_Q(level), s);
+    // taps [R*n_in][k2] over Q_level P in the transform domain (tap 0 = P * the input, taps 1.. =
+    // hoisted rotations before their ModDown), weighted sum, mask, then one ModDown per output
+    const Basis qp = c.basis_QP(level);
+    const size_t ctx = (size_t)2 * qp.n * N;
+    double* H = ar.take((size_t)nin * ctw);
+    copy_rows(in, 0, H, 0, (size_t)nin * ctw, 1, s);
+    ntt_forward(c, H, 2 * nin, c.basis_Q(level), s);
+    double* X = ar.take((size_t)nin * L.k2 * ctx);
+    taps_extended(c, ek, in, H, nin, level, L.steps, X, s);
+    double* U = ar.take((size_t)nout * ctx);
+    mac(c, L.mac, X, U, level, s, R, (size_t)L.n_in * L.k2 * ctx, (size_t)L.n_out * ctx, nullptr, 0, 0, &qp);
+    mul_plain_ntt(c, U, U, nout, level, L.mask_hat_qp, false, s, &qp);
+    ntt_inverse(c, U, 2 * nout, qp, s);
+    moddown(c, U, nout, level, nullptr, 1, 0, 0, KeySel(), false, A, s);
   } else {
     double* H = ar.take((size_t)nin * ctw);
     copy_rows(in, 0, H, 0, (size_t)nin * ctw, 1, s);

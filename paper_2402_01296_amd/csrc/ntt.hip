@@ -667,10 +667,15 @@ k_ntt_digits(const double* __restrict__ src, size_t src_stride, int dnum, KsDigi
 // Output o reads the digits of source o / d_div.  SPLIT: a block computes only one of the two
 // parts (twice the blocks, each with half the inner product and one inverse transform), for
 // launches too small to fill the device, whose time is the latency of one block.
-template <int LOGN, int LOGE, bool SPLIT>
+//
+// EXT: no inverse transform (the taps of a convolution kept over Q_l P, see ks_extended).
+// The block adds P sigma(c0^) on the Q limbs of part 0 (the source's transformed part 0,
+// staged in LDS like a digit limb) and stores both parts in the transform domain at
+// u + (o / out_div) out_outer + (o % out_div) 2 (level + K) N.
+template <int LOGN, int LOGE, bool SPLIT, bool EXT = false>
 __global__ void __launch_bounds__(1 << (LOGN - LOGE))
 k_ks_intt(const double* __restrict__ D, int d_div, KeySel ka, int level, int dnum, int L, Basis qp, Tables tb,
-          double* __restrict__ u) {
+          double* __restrict__ u, KsExt ext) {
   using S = Shape<LOGN, LOGE>;
   constexpr int N = S::N, E = S::E, T = S::T;
   constexpr int C0 = Sched<LOGN, LOGE, true>::c(0);
@@ -777,6 +782,32 @@ k_ks_intt(const double* __restrict__ D, int d_div, KeySel ka, int level, int dnu
     }
   }
   }
+  if constexpr (EXT) {
+    if (limb < level && part == 0) {
+      // P sigma(c0^): the source's part 0 limb staged in LDS, read through the permutation
+      const double* c0 = ext.c0hat + (size_t)(o / d_div) * ext.c0_stride + (size_t)limb * N;
+      __syncthreads();
+#pragma unroll 4
+      for (int p = tid; p < N; p += T) lds[p] = c0[p];
+      __syncthreads();
+      const double pm = ext.pm[limb];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int gi = (e / SZ0 * T + tid) * SZ0 + e % SZ0;
+        const double v = lds[gal == 1 ? ntt_store(gi, LOGN) : ntt_store(ntt_perm(gi, gal, LOGN), LOGN)];
+        x[e] = reduce(x[e] + mul_lazy(v, pm, m), m);
+      }
+    }
+    double* dst = u + (size_t)(o / ext.out_div) * ext.out_outer + (size_t)(o % ext.out_div) * 2 * nb * N +
+                  (size_t)limb * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int pos = ntt_store((e / SZ0 * T + tid) * SZ0 + e % SZ0, LOGN);
+      dst[(size_t)part * nb * N + pos] = x[e];
+      if (!SPLIT) dst[(size_t)nb * N + pos] = acc1[e];
+    }
+    return;
+  }
   const double* iw = tb.inv + (size_t)pid * N;
   const double* post = tb.post + (size_t)pid * N;
   run_pass<LOGN, LOGE, true, 0, true, false>(x, lds, nullptr, u + ((size_t)(o * 2 + part) * nb + limb) * N, iw, post,
@@ -807,12 +838,30 @@ void launch_ks_split(const Context& c, int part, const double* src, size_t strid
   if (b2 > 0 && (int)b2 < c.n_cus) {
     // too few blocks to fill the device: one block per part halves each block's latency
     hipLaunchKernelGGL((k_ks_intt<LOGN, LOGE, true>), dim3(2 * b2), dim3(N >> LOGE), lds, s, D, d_div, ks, level, dnum,
-                       c.L, qp, c.tab, u);
+                       c.L, qp, c.tab, u, KsExt());
   } else if (b2 > 0) {
     hipLaunchKernelGGL((k_ks_intt<LOGN, LOGE, false>), dim3(b2), dim3(N >> LOGE), lds, s, D, d_div, ks, level, dnum,
-                       c.L, qp, c.tab, u);
+                       c.L, qp, c.tab, u, KsExt());
     BCN_HIP(hipGetLastError());
   }
+}
+
+// the extended inner product (no inverse transform) of n_out outputs
+template <int LOGN, int LOGE>
+void launch_ks_ext(const Context& c, int level, const double* D, const KeySel& ks, int n_out, int d_div, double* u,
+                   const Basis& qp, const KsExt& ext, hipStream_t s) {
+  constexpr int N = 1 << LOGN;
+  const size_t lds = (size_t)N * sizeof(double);
+  const int dnum = c.dnum(level);
+  const unsigned b2 = (unsigned)n_out * qp.n;
+  if (b2 == 0) return;
+  if ((int)b2 < c.n_cus)
+    hipLaunchKernelGGL((k_ks_intt<LOGN, LOGE, true, true>), dim3(2 * b2), dim3(N >> LOGE), lds, s, D, d_div, ks, level,
+                       dnum, c.L, qp, c.tab, u, ext);
+  else
+    hipLaunchKernelGGL((k_ks_intt<LOGN, LOGE, false, true>), dim3(b2), dim3(N >> LOGE), lds, s, D, d_div, ks, level,
+                       dnum, c.L, qp, c.tab, u, ext);
+  BCN_HIP(hipGetLastError());
 }
 
 template <int LOGN, int LOGE>
@@ -842,6 +891,10 @@ void set_attr() {
                               lds));
   BCN_HIP(hipFuncSetAttribute((const void*)k_ks_intt<LOGN, LOGE, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               lds));
+  BCN_HIP(hipFuncSetAttribute((const void*)k_ks_intt<LOGN, LOGE, false, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+  BCN_HIP(hipFuncSetAttribute((const void*)k_ks_intt<LOGN, LOGE, true, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds));
 }
 
 template <int LOGN, int LOGE>
@@ -987,6 +1040,15 @@ KsDigits ks_digits(const Context& c, int level, const Basis& qp) {
 }
 }  // namespace
 
+namespace {
+// the first kernel of ks_split alone: digits of the sources into D
+void ks_split_digits_only(const Context& c, const double* src, size_t src_stride, int n_src, int level, double* D,
+                          hipStream_t s) {
+  KeySel none;
+  ks_split(c, src, src_stride, n_src, level, none, 0, 1, D, nullptr, s);
+}
+}  // namespace
+
 void ks_split(const Context& c, const double* src, size_t src_stride, int n_src, int level, const KeySel& ks,
               int n_out, int d_div, double* D, double* u, hipStream_t s, int src_galois) {
   const Basis qp = c.basis_QP(level);
@@ -995,7 +1057,7 @@ void ks_split(const Context& c, const double* src, size_t src_stride, int n_src,
   const double tr = 8.0 * (c.n / 2) * c.logn + 4.0 * c.n;        // FP64 ops of one limb transform
   const int key = c.logn * 16 + c.ks_loge;
   const int store_gal = src_galois == 1 ? 1 : (int)host::inv_pow2((uint64_t)src_galois, c.logn + 1);
-  for (int part = 1; part <= 2; ++part) {
+  for (int part = 1; part <= (n_out > 0 ? 2 : 1); ++part) {
     // digits: source limbs once, digits out, dnum * (level + K) forward transforms per source;
     // inner product: digits and two key parts in, two parts out, two inverse transforms per output limb
     const double u1 = (double)n_src * dnum * qp.n, u2 = (double)n_out * qp.n;
@@ -1014,6 +1076,29 @@ void ks_split(const Context& c, const double* src, size_t src_stride, int n_src,
 #undef BCN_KSS_CASE
       default: throw Error(-1, "unsupported ring degree / transform shape");
     }
+  }
+}
+
+void ks_extended(const Context& c, const double* src, size_t src_stride, int n_src, int level, const KeySel& ks,
+                 int n_out, int d_div, double* D, double* u, const KsExt& ext, hipStream_t s) {
+  // the digits as for a complete key switch, then the inner products with no inverse transform
+  ks_split_digits_only(c, src, src_stride, n_src, level, D, s);
+  const Basis qp = c.basis_QP(level);
+  const int dnum = c.dnum(level);
+  const double u2 = (double)n_out * qp.n;
+  // digits and two key parts in (the source's part 0 on the Q limbs), two parts out
+  ProfScope ps(c, "ks_ext", s, 8.0 * c.n * u2 * (dnum + 2.0 * dnum + 2.0), u2 * dnum * 2.0 * 7.0 * c.n);
+  const int key = c.logn * 16 + c.ks_loge;
+  switch (key) {
+#define BCN_KSE_CASE(LN, LE) \
+  case LN * 16 + LE: launch_ks_ext<LN, LE>(c, level, D, ks, n_out, d_div, u, qp, ext, s); break;
+    BCN_KSE_CASE(10, 3) BCN_KSE_CASE(10, 4)
+    BCN_KSE_CASE(11, 3) BCN_KSE_CASE(11, 4)
+    BCN_KSE_CASE(12, 4) BCN_KSE_CASE(12, 5)
+    BCN_KSE_CASE(13, 4) BCN_KSE_CASE(13, 5)
+    BCN_KSE_CASE(14, 4) BCN_KSE_CASE(14, 5)
+#undef BCN_KSE_CASE
+    default: throw Error(-1, "unsupported ring degree / transform shape");
   }
 }
 

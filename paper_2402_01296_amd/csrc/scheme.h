@@ -43,7 +43,9 @@ void decrypt(Context& c, const SecretKey& sk, const double* ct, int n, int level
 // m [n][N] in [0, t) from slot vectors already on the device (int64 [n][N])
 void encode_device(Context& c, const int64_t* slots_dev, double* m, int n, hipStream_t s);
 // NTT over Q_level of lift_c(encode(slots)) for host slot vectors [n][N] -> out [n][level][N]
-void encode_plain_ntt(Context& c, const int64_t* slots_host, int n, int level, double* out, hipStream_t s);
+// over_qp: the transform over Q_level then P ([n][level + K][N])
+void encode_plain_ntt(Context& c, const int64_t* slots_host, int n, int level, double* out, hipStream_t s,
+                      bool over_qp = false);
 
 void square_relin(Context& c, const EvalKeys& ek, const double* in, double* out, int n, int level, bool modsw,
                   hipStream_t s);
@@ -76,6 +78,11 @@ void square_relin_qb(Context& c, const EvalKeys& ek, double* x, double* out, int
 void rotate_hoisted(Context& c, EvalKeys& ek, const double* in, int n_in, int level, const std::vector<int>& steps,
                     double* out, hipStream_t s, int out_div = 0, size_t out_outer = 0);
 void rotate_sum(Context& c, const EvalKeys& ek, double* ct, int n, int level, int span, hipStream_t s);
+// The k2 taps of each of n_in inputs kept over Q_level P before ModDown, in the transform
+// domain: X [n_in][k2][2][level + K][N], tap 0 = P * input, tap 1 + r = Rot~(input, steps[r]).
+// in: the inputs (coefficient form), in_hat: the same transformed over Q_level.
+void taps_extended(Context& c, EvalKeys& ek, const double* in, const double* in_hat, int n_in, int level,
+                   const std::vector<int>& steps, double* X, hipStream_t s);
 
 // w: [n_out][n_in]; order: output rows in tiling order (empty = natural); tile: outputs per
 // tile (power of two <= 64, 0 = automatic)

@@ -167,13 +167,15 @@ void encode_device(Context& c, const int64_t* slots_dev, double* m, int n, hipSt
   ntt_inverse(c, m, n, basis_t(c), s);
 }
 
-void encode_plain_ntt(Context& c, const int64_t* slots_host, int n, int level, double* out, hipStream_t s) {
+void encode_plain_ntt(Context& c, const int64_t* slots_host, int n, int level, double* out, hipStream_t s,
+                      bool over_qp) {
   Arena& ar = *c.arena;
   const int64_t* sd = dev_upload(slots_host, (size_t)n * c.n, s, ar);
   double* m = ar.take((size_t)n * c.n);
   encode_device(c, sd, m, n, s);
-  lift_plain(c, m, out, n, level, s);
-  ntt_forward(c, out, n, c.basis_Q(level), s);
+  const Basis b = over_qp ? c.basis_QP(level) : c.basis_Q(level);
+  lift_plain(c, m, out, n, b.n, s, &b);
+  ntt_forward(c, out, n, b, s);
   BCN_HIP(hipStreamSynchronize(s));
 }
 
@@ -329,6 +331,37 @@ void rotate_hoisted(Context& c, EvalKeys& ek, const double* in, int n_in, int le
     ntt_inverse(c, U, 2 * n_in * ns, qp, s);
   }
   moddown(c, U, n_in * ns, level, in, ns, (size_t)2 * level * N, 2, ks, false, out, s, out_div, out_outer);
+}
+
+void taps_extended(Context& c, EvalKeys& ek, const double* in, const double* in_hat, int n_in, int level,
+                   const std::vector<int>& steps, double* X, hipStream_t s) {
+  if (n_in == 0) return;
+  Arena& ar = *c.arena;
+  const size_t N = c.n;
+  const Basis qp = c.basis_QP(level);
+  const int ns = (int)steps.size(), k2 = ns + 1;
+  const size_t ctx = (size_t)2 * qp.n * N;
+  KsExt ext;
+  ext.c0hat = in_hat;
+  ext.c0_stride = (size_t)2 * level * N;
+  ext.out_div = ns > 0 ? ns : 1;
+  ext.out_outer = (size_t)k2 * ctx;
+  for (int d = 0; d < level; ++d) {
+    const uint64_t q = c.primes[d];
+    uint64_t pm = 1;
+    for (int i = 0; i < c.K; ++i) pm = host::mulmod(pm, c.primes[c.idP(i)] % q, q);
+    ext.pm[d] = (double)pm;
+  }
+  ext_tap0(c, in_hat, n_in, level, ext, X, ext.out_outer, s);
+  if (ns == 0) return;
+  const KeyTable& tb = ek.table(steps);
+  double* D = ar.take((size_t)n_in * c.dnum(level) * qp.n * N);
+  KeySel ks;
+  ks.keys = tb.keys;
+  ks.galois = tb.galois;
+  ks.kinv = tb.kinv;
+  ks.nk = tb.nk;
+  ks_extended(c, in + level * N, (size_t)2 * level * N, n_in, level, ks, n_in * ns, ns, D, X + ctx, ext, s);
 }
 
 void rotate_sum(Context& c, const EvalKeys& ek, double* ct, int n, int level, int span, hipStream_t s) {

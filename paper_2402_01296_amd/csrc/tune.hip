@@ -238,7 +238,11 @@ std::string autotune_ntt(Context& c, hipStream_t s) {
 
 std::string autotune_layer_mac(Context& c, Layer& L, hipStream_t s) {
   if (L.mac_weights.empty()) return "";
-  const size_t ctw = (size_t)2 * L.level * c.n;
+  // a HW convolution's MAC runs over the taps kept over Q_level then P
+  const bool ext = L.packing != BCN_PACK_BATCH && L.kind == BCN_CONV2D && !L.diag;
+  const Basis qp = c.basis_QP(L.level);
+  const Basis* basis = ext ? &qp : nullptr;
+  const size_t ctw = (size_t)2 * (ext ? qp.n : L.level) * c.n;
   const int n_in_mac = L.mac.n_in;
   double* in = c.arena->take((size_t)n_in_mac * ctw);
   double* out = c.arena->take((size_t)L.mac.n_out * ctw);
@@ -255,7 +259,7 @@ std::string autotune_layer_mac(Context& c, Layer& L, hipStream_t s) {
     MacPlan p = make_mac_plan(c, L.mac_weights, L.mac.n_out, n_in_mac, L.mac_order, tile);
     float ms = 0;
     try {
-      ms = time_ms_cold(s, 5, flush, kFlush, [&] { mac(c, p, in, out, L.level, s); });
+      ms = time_ms_cold(s, 5, flush, kFlush, [&] { mac(c, p, in, out, L.level, s, 1, 0, 0, nullptr, 0, 0, basis); });
     } catch (...) {
       free_mac_plan(p);
       throw;

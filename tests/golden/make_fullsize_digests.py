@@ -35,15 +35,15 @@ def _encrypt(i):
     return i, O.encrypt_slots(_S["slots"][i], i)
 
 
-def _rotate(c):
+def _extend(c):
     O = _S["O"]
-    return c, O.rotated_input(_S["li"], _S["cts"][c])
+    return c, O.extended_input(_S["li"], _S["cts"][c])
 
 
 def _layer_output(o):
     O, li, kind = _S["O"], _S["li"], _S["kind"]
     if kind == "conv_hw":
-        return o, O.conv_hw(li, _S["cts"], outputs=[o], rot=_S["rot"])[o]
+        return o, O.conv_hw(li, _S["cts"], outputs=[o], ext=_S["ext"])[o]
     if kind == "conv_batch":
         return o, O.conv_batch(li, _S["cts"], outputs=[o])[o]
     if kind == "dense_hw":
@@ -76,7 +76,7 @@ def main():
         if info["kind"] == "conv":
             n_out = info["out_shape"][0] if hw else int(np.prod(info["out_shape"]))
             if hw:
-                _S["rot"] = _pool_map(_rotate, sorted(cts), workers)
+                _S["ext"] = _pool_map(_extend, sorted(cts), workers)
                 _S["kind"] = "conv_hw"
                 if info.get("sum"):
                     spatial = False
@@ -88,7 +88,7 @@ def main():
         else:
             n_out, _S["kind"] = info["out"], "dense_scalar"
         cts = _pool_map(_layer_output, list(range(n_out)), workers)
-        _S.pop("rot", None)
+        _S.pop("ext", None)
         level = cts[0].level
         out["layers"].append({"what": "outputs of layer %d (%s)" % (li + 1, _S["kind"]), "level": level,
                               "digests": [digest(prm, cts[o]) for o in range(n_out)]})

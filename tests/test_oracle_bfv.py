@@ -404,3 +404,82 @@ def test_modswitch_known_answer_every_coefficient():
     ql, Qn = prm.q[2], prm.Q(2)
     assert list(got.c0) == [_nearest(v, ql) % Qn for v in c0]
     assert list(got.c1) == [_nearest(v, ql) % Qn for v in c1]
+
+
+def _sigma_signed(a, k):
+    n = len(a)
+    out = [0] * n
+    for i, v in enumerate(a):
+        e = i * k
+        out[e % n] += -v if (e // n) % 2 else v
+    return out
+
+
+@pytest.mark.parametrize("level", [3, 2])
+def test_deferred_moddown_conv_known_answer(level):
+    # A weighted sum of rotations kept over Q_l P, times a plaintext, then one ModDown:
+    #   tap(c, 0) = (P c0, P c1);  tap(c, r) = (P sigma_k(c0) + u0, u1),
+    #   u_k = sum_j D_j(sigma_k(c1)) * key_r,j[k]  (D_j centred mod Q_j, schoolbook over Z);
+    #   out = nearest((lift_c(m) * sum w tap) / P) mod Q_l, every coefficient of both parts.
+    prm = params.make("dh", 8, 30, 3, 2, 2, 17, insecure=True)
+    Q, P = prm.Q(level), prm.P
+    QP = Q * P
+    keys = {1: _tiny_key(prm, 41), 3: _tiny_key(prm, 43)}
+    cts = []
+    for c in range(2):
+        c0 = [(i * 0x2545F4914F6CDD1D + 17 + 101 * c) % Q for i in range(8)]
+        c1 = [(i * 0x9E3779B97F4A7C15 + 5 + 37 * c) % Q for i in range(8)]
+        cts.append(bfv.Ct(c0, c1, level))
+    steps = [0, 1, 3]
+    w = {(0, 0): 3, (0, 1): -2, (0, 3): 5, (1, 0): -7, (1, 1): 4, (1, 3): 1}
+    m = [1, 0, 16, 3, 0, 9, 1, 15]
+
+    def tap(ct, r):
+        if r == 0:
+            return [(P * v) % QP for v in ct.c0], [(P * v) % QP for v in ct.c1]
+        k = pow(3, r, 16)
+        s0, s1 = _sigma_signed(ct.c0, k), [v % Q for v in _sigma_signed(ct.c1, k)]
+        u = []
+        for part in (0, 1):
+            acc = [0] * 8
+            for j in range(prm.dnum(level)):
+                Qj = 1
+                for q in prm.q[j * prm.alpha:min((j + 1) * prm.alpha, level)]:
+                    Qj *= q
+                D = [_centred(v, Qj) for v in s1]
+                acc = [a + b for a, b in zip(acc, _schoolbook(D, [v % QP for v in keys[r].parts[j][part]]))]
+            u.append(acc)
+        return [(P * a + b) % QP for a, b in zip(s0, u[0])], [v % QP for v in u[1]]
+
+    A = [[0] * 8, [0] * 8]
+    for c in range(2):
+        for r in steps:
+            t0, t1 = tap(cts[c], r)
+            A[0] = [a + w[(c, r)] * b for a, b in zip(A[0], t0)]
+            A[1] = [a + w[(c, r)] * b for a, b in zip(A[1], t1)]
+    lifted = [v - 17 if 2 * v > 17 else v for v in m]
+    want = [[_nearest(v % QP, P) % Q for v in _schoolbook([a % QP for a in part], lifted)] for part in A]
+
+    exts = {c: bfv.rotations_extended(prm, cts[c], steps, [None, keys[1], keys[3]]) for c in range(2)}
+    terms = [exts[c][i] for c in range(2) for i in range(3)]
+    ws = [w[(c, r)] for c in range(2) for r in steps]
+    acc = bfv.mac_extended(prm, terms, ws, level)
+    got = bfv.mod_down_ct(prm, bfv.mul_plain_extended(prm, acc, m, level), level)
+    assert list(got.c0) == want[0] and list(got.c1) == want[1]
+    # the single rounding is visible: ModDown per rotation before the sum gives another result
+    per = []
+    for c in range(2):
+        rots = bfv.rotate_hoisted(prm, cts[c], [1, 3], [keys[1], keys[3]])
+        per += [cts[c]] + rots
+    alt = bfv.mul_plain(prm, bfv.mac(prm, per, ws), m)
+    assert list(alt.c0) != want[0] or list(alt.c1) != want[1]
+
+
+def test_mod_down_is_exact_on_multiples_of_p():
+    prm = params.make("md", 8, 30, 3, 2, 1, 17, insecure=True)
+    Q, P = prm.Q(3), prm.P
+    x = [(i * 0x9E3779B97F4A7C15 + 3) % Q for i in range(8)]
+    assert bfv.mod_down(prm, [(P * v) % (Q * P) for v in x], 3) == x
+    # and rounds to nearest: P x + y with |y| < P/2 maps to x
+    ys = [P // 2 - 1, -(P // 2) + 1, 1, -1, 0, 5, P // 3, -(P // 3)]
+    assert bfv.mod_down(prm, [(P * v + y) % (Q * P) for v, y in zip(x, ys)], 3) == x
