@@ -415,6 +415,7 @@ def run_workload(name: str, steps: int, warmup: int, autotune: bool = True, grap
         eager_out = step()
     torch.cuda.synchronize()
     eager_ms = (time.perf_counter() - t0) * 1000.0 / steps
+    eager_step = step
     graph_ok = None
     if graph:
         # the whole step captured once as a hipGraph and replayed, checked against the eager result
@@ -453,7 +454,7 @@ def run_workload(name: str, steps: int, warmup: int, autotune: bool = True, grap
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        step()
+        eager_step()
     torch.cuda.synchronize()
     inst_ms = (time.perf_counter() - t0) * 1000.0 / steps
     g.ctx.profile(False)

@@ -266,6 +266,13 @@ void mac(const Context& c, const MacPlan& p, const double* in, double* out, int 
          size_t in_req = 0, size_t out_req = 0, const double* delta_msg = nullptr, size_t out_ct = 0,
          size_t out_part = 0, const Basis* basis = nullptr);
 
+// The MAC of a slot-batched layer feeding a square, writing out rows [2][level + m][N] over
+// Q_level then B (the extension fused into the MAC's stores); out_ct, out_part as for mac.
+// Returns false (and does nothing) when the plan's tile or centring is not supported.
+bool mac_qb_supported(const MacPlan& p, int level);
+bool mac_qb(const Context& c, const MacPlan& p, const double* in, double* out, int level, hipStream_t s, int requests,
+            size_t in_req, size_t out_req, const double* delta_msg, size_t out_ct, size_t out_part);
+
 // c0 of each ciphertext += Delta(m_i), m_i in [0, t) coefficient form, [n][N]
 void add_delta(const Context& c, double* ct, int n, int level, const double* m, hipStream_t s);
 // out[k] = in[k] (.) pt  (NTT domain); pt [level][N] shared, or [n][level][N] when per_ct

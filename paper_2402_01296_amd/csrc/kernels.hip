@@ -104,6 +104,93 @@ k_mac(const double* __restrict__ in, double* __restrict__ out, int words, int lo
   }
 }
 
+// The same MAC feeding a square (slot batching): thread (part, coefficient k) accumulates all
+// NQ limbs of the tile's TO outputs, so after the reduction (and the feature add on part 0) it
+// holds every residue of the coefficient and writes the B limbs of its centred lift too (the
+// steps of k_extend_qb): out row r is [2][NQ + m][N] over Q_level then B.  Uncentred plans only.
+template <int TO, int NQ>
+__global__ void __launch_bounds__(TPB)
+k_mac_qb(const double* __restrict__ in, double* __restrict__ out, int logn, const double* __restrict__ Wp,
+         const int* __restrict__ rows, const int* __restrict__ tptr, const int* __restrict__ tcols, Basis b,
+         const Mod* __restrict__ mods, size_t in_req, size_t out_req, size_t out_ct, size_t out_part, DeltaAdd da,
+         const Conv* __restrict__ cvp) {
+  const size_t N = (size_t)1 << logn;
+  const size_t w = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (w >= 2 * N) return;
+  in += blockIdx.z * in_req;
+  out += blockIdx.z * out_req;
+  const int tile = blockIdx.y;
+  const int part = (int)(w >> logn);
+  const size_t k = w & (N - 1);
+  const size_t words = 2 * NQ * N;
+  double acc[TO][NQ];
+#pragma unroll
+  for (int o = 0; o < TO; ++o)
+#pragma unroll
+    for (int l = 0; l < NQ; ++l) acc[o][l] = 0.0;
+  const double* __restrict__ xin = in + (size_t)part * NQ * N + k;
+  const int beg = tptr[tile], end = tptr[tile + 1];
+  int e = beg;
+  for (; e + 2 <= end; e += 2) {
+    double x[2][NQ];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int l = 0; l < NQ; ++l) x[u][l] = xin[(size_t)tcols[e + u] * words + (size_t)l * N];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const double* __restrict__ wr = Wp + (size_t)(e + u) * TO;
+#pragma unroll
+      for (int o = 0; o < TO; ++o)
+#pragma unroll
+        for (int l = 0; l < NQ; ++l) acc[o][l] = fma(wr[o], x[u][l], acc[o][l]);
+    }
+  }
+  for (; e < end; ++e) {
+    double x[NQ];
+#pragma unroll
+    for (int l = 0; l < NQ; ++l) x[l] = xin[(size_t)tcols[e] * words + (size_t)l * N];
+    const double* __restrict__ wr = Wp + (size_t)e * TO;
+#pragma unroll
+    for (int o = 0; o < TO; ++o)
+#pragma unroll
+      for (int l = 0; l < NQ; ++l) acc[o][l] = fma(wr[o], x[l], acc[o][l]);
+  }
+  const Conv& cv = *cvp;
+  const bool add = da.msg != nullptr && part == 0;
+#pragma unroll
+  for (int o = 0; o < TO; ++o) {
+    const int row = rows[tile * TO + o];
+    if (row < 0) continue;
+    double r[NQ], v[NQ];
+    double rt = 0.0;
+    if (add) rt = mul_mod(da.qmodt, da.msg[blockIdx.z * da.msg_req + ((size_t)row << logn) + k], da.mt);  // [Q m]_t
+    double* dst = out + (size_t)row * out_ct + (size_t)part * out_part + k;
+#pragma unroll
+    for (int l = 0; l < NQ; ++l) {
+      const Mod m = mods[b.id[l]];
+      double x = reduce(acc[o][l], m);
+      if (add) {
+        double d = norm(mul_lazy(rt, da.negtinv[l], m), m);           // floor(Q m / t) mod q
+        if (2.0 * rt > da.mt.q) d = add_mod(d, 1.0, m);                // nearest, never a tie (t odd)
+        x = add_mod(x, d, m);
+      }
+      r[l] = x;
+      dst[(size_t)l * N] = x;
+    }
+    garner<NQ>(r, v, cv, mods);
+    const bool neg = above_half<NQ>(v, NQ, cv, mods);
+    for (int d = 0; d < cv.nd; ++d) {
+      const Mod md = mods[cv.dst[d]];
+      double a = v[NQ - 1];
+#pragma unroll
+      for (int kk = NQ - 2; kk >= 0; --kk) a = mul_lazy(a, cv.pm[d][kk], md) + v[kk];
+      if (neg) a -= cv.Mmod[d];
+      dst[(size_t)(NQ + d) * N] = reduce(a, md);
+    }
+  }
+}
+
 // ------------------------------------------------------------------ plaintext ops
 
 struct LimbConsts {
@@ -728,6 +815,61 @@ void ext_tap0(const Context& c, const double* chat, int n, int level, const KsEx
   hipLaunchKernelGGL(k_ext_tap0, dim3(nblocks(work)), dim3(TPB), 0, s, chat, n, level, b.n, c.logn, ext, b, c.tab.mods,
                      X, out_outer);
   BCN_HIP(hipGetLastError());
+}
+
+static const Conv* extend_conv(const Context& c, int level);
+
+bool mac_qb_supported(const MacPlan& p, int level) {
+  return !p.centre && level >= 2 && level <= 6 && (p.tile == 2 || p.tile == 4 || p.tile == 8 || p.tile == 16) &&
+         p.tile * level <= 64;
+}
+
+bool mac_qb(const Context& c, const MacPlan& p, const double* in, double* out, int level, hipStream_t s, int requests,
+            size_t in_req, size_t out_req, const double* delta_msg, size_t out_ct, size_t out_part) {
+  if (!mac_qb_supported(p, level)) return false;
+  if (p.n_out == 0 || requests == 0) return true;
+  DeltaAdd da;
+  if (delta_msg) {
+    da.msg = delta_msg;
+    da.msg_req = (size_t)p.n_out * c.n;
+    da.mt = c.mod(c.id_t);
+    delta_consts(c, level, &da.qmodt, da.negtinv);
+  }
+  const Conv* cv = extend_conv(c, level);
+  const double words = 2.0 * level * c.n;
+  // inputs and the Q limbs out as for the MAC, plus the B limbs the extension would have written
+  ProfScope ps(c, "mac", s, 8.0 * requests * (words * ((double)p.n_in + p.n_out) + 2.0 * c.m * c.n * p.n_out),
+               words * p.nnz * requests);
+  dim3 grid(nblocks((size_t)2 * c.n), p.n_tiles, requests);
+  const Basis b = c.basis_Q(level);
+#define BCN_MQB(TO, NQ)                                                                                            \
+  hipLaunchKernelGGL((k_mac_qb<TO, NQ>), grid, dim3(TPB), 0, s, in, out, c.logn, p.W, p.rows, p.tile_ptr, p.tile_cols, \
+                     b, c.tab.mods, in_req, out_req, out_ct, out_part, da, cv)
+#define BCN_MQB_T(NQ)                                    \
+  switch (p.tile) {                                      \
+    case 2: BCN_MQB(2, NQ); break;                       \
+    case 4: BCN_MQB(4, NQ); break;                       \
+    case 8: BCN_MQB(8, NQ); break;                       \
+  }
+#define BCN_MQB_T16(NQ)                                  \
+  if (p.tile == 16) {                                    \
+    BCN_MQB(16, NQ);                                     \
+  } else {                                               \
+    BCN_MQB_T(NQ)                                        \
+  }
+  // accumulators: tile * level <= 64
+  switch (level) {
+    case 2: BCN_MQB_T16(2) break;
+    case 3: BCN_MQB_T16(3) break;
+    case 4: BCN_MQB_T16(4) break;
+    case 5: BCN_MQB_T(5) break;
+    case 6: BCN_MQB_T(6) break;
+  }
+#undef BCN_MQB_T16
+#undef BCN_MQB_T
+#undef BCN_MQB
+  BCN_HIP(hipGetLastError());
+  return true;
 }
 
 void add_delta(const Context& c, double* ct, int n, int level, const double* m, hipStream_t s) {

@@ -18,6 +18,7 @@ struct Layer {
   int fclamp = 127;
   int batch = 0, stride_b = 0;
   MacPlan mac;
+  bool mac_ext = true;           // slot-batched square layer: the MAC writes the B limbs too (when supported)
   std::vector<int32_t> mac_weights;  // host copy of the MAC matrix (for retuning)
   std::vector<int> mac_order;
   std::vector<int> steps;        // HW conv: nonzero tap offsets, tap index = position + 1

@@ -3,6 +3,7 @@
 // global sum epilogues (appendix "Implementation Details"; features enter as
 // in section "The unidirectional connections").
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 
 #include "../../include/bcn.h"
@@ -18,6 +19,16 @@ Layer::~Layer() {
 }
 
 namespace {
+// BCN_MAC_TILE pins a slot-batched layer's MAC tile (a power of two in 1..64) until an autotune;
+// BCN_MAC_EXT=0 keeps the extension to Q+B out of the MAC
+int env_mac_tile(int dflt) {
+  const char* e = std::getenv("BCN_MAC_TILE");
+  if (!e) return dflt;
+  const int t = std::atoi(e);
+  if (t < 1 || t > 64 || (t & (t - 1))) throw Error(-1, "BCN_MAC_TILE must be a power of two in 1..64");
+  return t;
+}
+
 int next_pow2(int x) {
   int s = 1;
   while (s < x) s *= 2;
@@ -50,6 +61,7 @@ Layer* layer_create(Context& c, const bcn_layer_desc& d, int level) {
   auto L = std::make_unique<Layer>();
   L->kind = d.kind;
   L->packing = d.packing;
+  if (const char* e = std::getenv("BCN_MAC_EXT")) L->mac_ext = std::atoi(e) != 0;
   L->level = level;
   L->square = d.square != 0;
   L->modsw = d.square && d.modswitch && level >= 2;
@@ -89,14 +101,14 @@ Layer* layer_create(Context& c, const bcn_layer_desc& d, int level) {
       for (int i = 0; i < L->oh; ++i)
         for (int j = 0; j < L->ow; ++j)
           for (int o = 0; o < d.out_c; ++o) order.push_back((o * L->oh + i) * L->ow + j);
-      L->mac = make_mac_plan(c, W, L->n_out, L->n_in, order, 16);
+      L->mac = make_mac_plan(c, W, L->n_out, L->n_in, order, env_mac_tile(16));
       L->mac_weights = W;
       L->mac_order = order;
     } else {
       L->n_in = d.in_c * d.in_h * d.in_w;
       L->n_out = d.out_c;
       std::vector<int32_t> W(d.weights, d.weights + (size_t)L->n_out * L->n_in);
-      L->mac = make_mac_plan(c, W, L->n_out, L->n_in);
+      L->mac = make_mac_plan(c, W, L->n_out, L->n_in, {}, env_mac_tile(0));
       L->mac_weights = W;
     }
     L->stride_b = L->n_out;
@@ -258,6 +270,7 @@ void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, doub
   const bool qb = L.packing == BCN_PACK_BATCH && L.square;
   const size_t ctq = (size_t)2 * (level + c.m) * N;
   double* A = direct ? out : ar.take((size_t)nout * (qb ? ctq : ctw));
+  bool b_filled = false;        // the MAC wrote the B limbs of the square's Q+B input
   if (L.packing == BCN_PACK_BATCH) {
     // slot batching: the features are quantised straight into the transform domain of R_t,
     // encoded (inverse transform mod t) and added by the MAC's own stores
@@ -270,9 +283,11 @@ void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, doub
       bt.id[0] = c.id_t;
       ntt_inverse(c, fm, nout, bt, s);
     }
-    if (qb)
-      mac(c, L.mac, in, A, level, s, R, (size_t)L.n_in * ctw, (size_t)L.n_out * ctq, fm, ctq, ctq / 2);
-    else
+    if (qb) {
+      b_filled = L.mac_ext &&
+                 mac_qb(c, L.mac, in, A, level, s, R, (size_t)L.n_in * ctw, (size_t)L.n_out * ctq, fm, ctq, ctq / 2);
+      if (!b_filled) mac(c, L.mac, in, A, level, s, R, (size_t)L.n_in * ctw, (size_t)L.n_out * ctq, fm, ctq, ctq / 2);
+    } else
       mac(c, L.mac, in, A, level, s, R, (size_t)L.n_in * ctw, (size_t)L.n_out * ctw, fm);
   } else if (L.diag) {
     // taps [R*n_in][k2] as for a convolution, then all taps times their weight vectors, summed
@@ -326,7 +341,7 @@ void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, doub
     return;
   }
   if (qb) {
-    square_relin_qb(c, ek, A, out, nout, level, L.modsw, s);
+    square_relin_qb(c, ek, A, out, nout, level, L.modsw, s, b_filled);
   } else if (L.square) {
     square_relin(c, ek, A, out, nout, level, L.modsw, s);
   } else {

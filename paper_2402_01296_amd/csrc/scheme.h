@@ -73,7 +73,7 @@ void ckks_square_relin_rescale(Context& c, const EvalKeys& ek, const double* in,
                                hipStream_t s);
 // the same from x [n][2][level+m][N] whose Q limbs hold the input; x's B limbs are filled in place
 void square_relin_qb(Context& c, const EvalKeys& ek, double* x, double* out, int n, int level, bool modsw,
-                     hipStream_t s);
+                     hipStream_t s, bool b_filled = false);
 // out placement as in moddown (out_div = 0: contiguous [n_in][n_steps])
 void rotate_hoisted(Context& c, EvalKeys& ek, const double* in, int n_in, int level, const std::vector<int>& steps,
                     double* out, hipStream_t s, int out_div = 0, size_t out_outer = 0);

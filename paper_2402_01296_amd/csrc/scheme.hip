@@ -298,11 +298,11 @@ void square_relin(Context& c, const EvalKeys& ek, const double* in, double* out,
 }
 
 void square_relin_qb(Context& c, const EvalKeys& ek, double* x, double* out, int n, int level, bool modsw,
-                     hipStream_t s) {
+                     hipStream_t s, bool b_filled) {
   if (!ek.relin) throw Error(-3, "missing relinearisation key");
   if (modsw && level < 2) throw Error(-2, "modulus switch needs two primes");
   if (n == 0) return;
-  extend_qb(c, x, x, n, level, s);
+  if (!b_filled) extend_qb(c, x, x, n, level, s);
   square_relin_tail(c, ek, x, out, n, level, modsw, s);
 }
 

@@ -243,9 +243,13 @@ std::string autotune_layer_mac(Context& c, Layer& L, hipStream_t s) {
   const Basis qp = c.basis_QP(L.level);
   const Basis* basis = ext ? &qp : nullptr;
   const size_t ctw = (size_t)2 * (ext ? qp.n : L.level) * c.n;
+  // a slot-batched square layer's MAC writes the square's Q+B input: timed with the extension,
+  // either fused into the MAC or as the separate kernel
+  const bool qb = L.packing == BCN_PACK_BATCH && L.square;
+  const size_t ctq = (size_t)2 * (L.level + c.m) * c.n;
   const int n_in_mac = L.mac.n_in;
   double* in = c.arena->take((size_t)n_in_mac * ctw);
-  double* out = c.arena->take((size_t)L.mac.n_out * ctw);
+  double* out = c.arena->take((size_t)L.mac.n_out * (qb ? ctq : ctw));
   BCN_HIP(hipMemsetAsync(in, 0, (size_t)n_in_mac * ctw * sizeof(double), s));
   // the MAC streams inputs another kernel wrote long before, so candidates are timed cold
   constexpr size_t kFlush = (size_t)1 << 26;   // 512 MiB, twice the last-level cache
@@ -253,32 +257,49 @@ std::string autotune_layer_mac(Context& c, Layer& L, hipStream_t s) {
   std::string report;
   float best_ms = 1e30f;
   int best_tile = L.mac.tile;
+  bool best_ext = false;
   for (int tile : {1, 2, 4, 8, 16, 32, 64}) {
     if (tile / 2 >= L.mac.n_out && tile > 8) break;
     if (tile < 8 && L.mac.n_out > 64) continue;   // narrow tiles only pay off for narrow layers
     MacPlan p = make_mac_plan(c, L.mac_weights, L.mac.n_out, n_in_mac, L.mac_order, tile);
-    float ms = 0;
-    try {
-      ms = time_ms_cold(s, 5, flush, kFlush, [&] { mac(c, p, in, out, L.level, s, 1, 0, 0, nullptr, 0, 0, basis); });
-    } catch (...) {
-      free_mac_plan(p);
-      throw;
+    for (int fused = 0; fused <= (qb ? 1 : 0); ++fused) {
+      if (fused && !mac_qb_supported(p, L.level)) continue;
+      float ms = 0;
+      try {
+        ms = time_ms_cold(s, 5, flush, kFlush, [&] {
+          if (!qb) {
+            mac(c, p, in, out, L.level, s, 1, 0, 0, nullptr, 0, 0, basis);
+          } else if (fused) {
+            mac_qb(c, p, in, out, L.level, s, 1, 0, 0, nullptr, ctq, ctq / 2);
+          } else {
+            mac(c, p, in, out, L.level, s, 1, 0, 0, nullptr, ctq, ctq / 2);
+            extend_qb(c, out, out, L.mac.n_out, L.level, s);
+          }
+        });
+      } catch (...) {
+        free_mac_plan(p);
+        throw;
+      }
+      char line[160];
+      std::snprintf(line, sizeof line, "mac %dx%d tile=%d%s: %.3f ms\n", L.mac.n_out, n_in_mac, tile,
+                    qb ? (fused ? " extension fused" : " + extension") : "", ms);
+      report += line;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_tile = tile;
+        best_ext = fused != 0;
+      }
     }
     free_mac_plan(p);
-    char line[128];
-    std::snprintf(line, sizeof line, "mac %dx%d tile=%d: %.3f ms\n", L.mac.n_out, n_in_mac, tile, ms);
-    report += line;
-    if (ms < best_ms) {
-      best_ms = ms;
-      best_tile = tile;
-    }
   }
+  L.mac_ext = best_ext;
   if (best_tile != L.mac.tile) {
     BCN_HIP(hipStreamSynchronize(s));
     free_mac_plan(L.mac);
     L.mac = make_mac_plan(c, L.mac_weights, L.mac.n_out, n_in_mac, L.mac_order, best_tile);
   }
-  report += "mac chosen tile=" + std::to_string(best_tile) + "\n";
+  report += "mac chosen tile=" + std::to_string(best_tile) + (qb ? (best_ext ? " extension fused" : " + extension") : "") +
+            "\n";
   return report;
 }
 

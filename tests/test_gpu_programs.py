@@ -82,3 +82,25 @@ def test_bi_model_overlapped_equals_serial_and_network():
     vals = g.output_values(over)
     want = network.run_mod_t(name, g.inputs, g.ctx.t)
     assert (vals == want).all()
+
+
+@pytest.mark.parametrize("tile", [2, 4, 8, 16])
+@pytest.mark.parametrize("fused", [1, 0])
+def test_batch_square_layer_mac_tiles(tile, fused, monkeypatch):
+    """A slot-batched square layer's MAC at each tile, with the extension to Q+B fused into its
+    stores or run as its own kernel: the layer's outputs bit-equal to the oracle's."""
+    torch_cuda()
+    monkeypatch.setenv("BCN_MAC_TILE", str(tile))
+    monkeypatch.setenv("BCN_MAC_EXT", str(fused))
+    from paper_2402_01296_amd.workload import GpuSession
+    name = "cfg2_small"
+    g = GpuSession(name)
+    O = programs.OracleSession(name)
+    ct = g.encrypt_inputs()
+    cur_o = O.encrypt_inputs()
+    for li in range(2):
+        ct = g.layers[li](g.ek, ct, g.features[li])
+        cur_o = _oracle_layer(O, li, cur_o)
+        got = g.ctx.export(ct)
+        for k in range(len(cur_o)):
+            assert (got[k] == bfv.ct_to_rns(O.prm, cur_o[k])).all(), "layer %d output %d" % (li, k)
