@@ -214,10 +214,17 @@ int bcn_square_relin_noalloc(bcn_context* ctx, const bcn_eval_keys* ek, const do
  * (hoisting; bit-identical to one-at-a-time).  out device [n_in][n_steps][2][level][N]. */
 int bcn_rotate(bcn_context* ctx, const bcn_eval_keys* ek, const double* in, int n_in, int level,
                const int32_t* steps, int n_steps, double* out, bcn_stream stream);
-/* In place: c <- c + Rot(c, r) for r = span/2, ..., 2, 1 (span a power of two):
- * slot 0 of each row receives the sum of its first span slots. */
+/* In place: c <- sum of Rot(c, r) over r = 0 .. span-1 (span = 2^k >= 2): slot 0 of each
+ * row receives the sum of its first span slots (the global sum pooling of appendix
+ * "Implementation Details").  Two rounds, each a set of hoisted rotations kept over Q_l P,
+ * summed and divided by P once: baby steps 1 .. b-1, then giant steps b, 2b, .., (g-1) b of
+ * the first round's result, b = 2^ceil(k/2), g = span / b.  Every step needs its rotation
+ * key (bcn_rotate_sum_steps lists them); BCN_ERR_KEY if one is missing. */
 int bcn_rotate_sum(bcn_context* ctx, const bcn_eval_keys* ek, double* ct, int n, int level, int span,
                    bcn_stream stream);
+/* The rotation steps bcn_rotate_sum(span) uses: writes up to cap of them to steps (may be
+ * NULL) and returns their count, or BCN_ERR_INVALID for a span that is not a power of two >= 2. */
+int bcn_rotate_sum_steps(int span, int32_t* steps, int cap);
 /* Exact modulus switch: c' = (c - lift_c([c]_{q_l})) / q_l mod Q_{l-1}. */
 int bcn_modswitch(bcn_context* ctx, const double* in, double* out, int n, int level, bcn_stream stream);
 
@@ -280,6 +287,11 @@ typedef struct {
   int32_t block;         /* HW: 0 (one image at base 0), or the slot distance between the blocks of
                             `batch` images packed in one ciphertext (BHW packing) */
   int32_t method;        /* HW DENSE: BCN_DENSE_WEIGHT_VECTORS (default) or BCN_DENSE_DIAGONAL */
+  int32_t defer_relin;   /* BATCH with square: 1 = leave the square unrelinearised, out rows are
+                            [3][level_out][N] (d0, d1, d2: decrypts as d0 + d1 s + d2 s^2) */
+  int32_t in_parts;      /* BATCH: 2 (0 = 2), or 3 when the inputs are such unrelinearised products:
+                            the layer's weighted sums run over the three parts and each output is
+                            relinearised once before the rest of the layer */
 } bcn_layer_desc;
 
 /* Prepares a layer for inputs at `level`: uploads weights, encodes masks and
@@ -291,12 +303,16 @@ void bcn_layer_destroy(bcn_layer* layer);
 int bcn_layer_rotation_steps(const bcn_layer* layer, int32_t* steps, int cap);
 /* Input/output ciphertext counts and the output level. */
 int bcn_layer_shape(const bcn_layer* layer, int* n_in, int* n_out, int* level_out);
-/* Evaluates the layer: in device [n_in][2][level][N] -> out device [n_out][2][level_out][N];
+/* Parts per input and per output row: 2, or 3 for unrelinearised products (desc in_parts,
+ * defer_relin). */
+int bcn_layer_parts(const bcn_layer* layer, int* in_parts, int* out_parts);
+/* Evaluates the layer: in device [n_in][in_parts][level][N] -> out device
+ * [n_out][out_parts][level_out][N] (parts 2 unless deferred relinearisation is asked for);
  * features: device float or NULL when the layer has none. */
 int bcn_layer_eval(bcn_context* ctx, const bcn_eval_keys* ek, const bcn_layer* layer, const double* in,
                    double* out, const float* features, bcn_stream stream);
 /* The same layer over n_requests independent requests in one set of launches:
- * in [n_requests][n_in][2][level][N], out [n_requests][n_out][2][level_out][N],
+ * in [n_requests][n_in][in_parts][level][N], out [n_requests][n_out][out_parts][level_out][N],
  * features [n_requests][...] in the per-request layout above.  Request r's
  * results are bit-identical to evaluating it alone.  From the second call of
  * a shape on it issues no host synchronisation, allocation or memset, so it

@@ -38,6 +38,15 @@ class Ct:
 
 
 @dataclass
+class Ct3:
+    """An unrelinearised product (d0, d1, d2): decrypts as d0 + d1 s + d2 s^2."""
+    c0: list
+    c1: list
+    c2: list
+    level: int
+
+
+@dataclass
 class KSKey:
     """Key-switching key: parts[j] = (b_j, a_j) with coefficients in [0, Q_L * P)."""
     parts: list
@@ -274,6 +283,48 @@ def square(prm: Params, a: Ct, rk: KSKey) -> Ct:
     return multiply(prm, a, a, rk)
 
 
+# ---------------------------------------------------------------- deferred relinearisation
+# Relinearisation is linear, so a square followed by a linear layer may relinearise the
+# linear layer's outputs instead of its inputs: the layer's weighted sums run over the three
+# parts (d0, d1, d2) and each output is key-switched once.
+
+def square_unrelinearised(prm: Params, a: Ct) -> Ct3:
+    d0, d1, d2 = tensor(prm, a, a)
+    return Ct3(d0, d1, d2, a.level)
+
+
+def modswitch3(prm: Params, a: Ct3) -> Ct3:
+    """Drop q_l from each of the three parts (as modswitch)."""
+    level = a.level
+    assert level >= 2
+    ql = prm.q[level - 1]
+    Qn = prm.Q(level - 1)
+
+    def one(c):
+        return [((x - nt.centered(x, ql)) // ql) % Qn for x in c]
+
+    return Ct3(one(a.c0), one(a.c1), one(a.c2), level - 1)
+
+
+def mac3(prm: Params, cts, weights) -> Ct3:
+    """sum_j w_j * ct_j mod Q over three-part products."""
+    level = cts[0].level
+    Q = prm.Q(level)
+    acc = [[0] * prm.n for _ in range(3)]
+    for ct, w in zip(cts, weights):
+        w = int(w)
+        if w == 0:
+            continue
+        assert ct.level == level
+        for p, part in enumerate((ct.c0, ct.c1, ct.c2)):
+            acc[p] = [x + w * y for x, y in zip(acc[p], part)]
+    return Ct3(*[ring.reduce(a, Q) for a in acc], level)
+
+
+def relinearize3(prm: Params, a: Ct3, rk: KSKey) -> Ct:
+    return relinearize(prm, (a.c0, a.c1, a.c2), rk, a.level)
+
+
 # ---------------------------------------------------------------- Rot(c, r)
 
 def rotate(prm: Params, a: Ct, r: int, gk: KSKey) -> Ct:
@@ -372,6 +423,27 @@ def mul_plain_extended(prm: Params, ext, m, level: int):
 
 def mod_down_ct(prm: Params, ext, level: int) -> Ct:
     return Ct(mod_down(prm, ext[0], level), mod_down(prm, ext[1], level), level)
+
+
+def rotate_sum_steps(span: int):
+    """The two rounds of rotate_sum for span = 2^k: baby steps 1 .. b-1 and giant steps
+    b, 2b, .., (g-1) b with b = 2^ceil(k/2), g = span / b."""
+    k = span.bit_length() - 1
+    assert span >= 2 and span == 1 << k
+    b = 1 << ((k + 1) // 2)
+    g = span // b
+    return [list(range(1, b)), [b * j for j in range(1, g)]]
+
+
+def rotate_sum(prm: Params, a: Ct, span: int, gks) -> Ct:
+    """sum_{r < span} Rot(a, r), in two rounds of hoisted rotations kept over Q_l P:
+    S1 = ModDown(sum_{r < b} Rot~(a, r)), then S = ModDown(sum_{j < g} Rot~(S1, j b))."""
+    for steps in rotate_sum_steps(span):
+        if not steps:
+            continue
+        ext = rotations_extended(prm, a, [0] + steps, [None] + [gks[r] for r in steps])
+        a = mod_down_ct(prm, mac_extended(prm, ext, [1] * len(ext), a.level), a.level)
+    return a
 
 
 # ---------------------------------------------------------------- modulus switching

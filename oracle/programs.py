@@ -10,14 +10,16 @@ The programs follow the appendix "Implementation Details":
     each kernel offset, multiplies by the scalar kernel weight, sums, and
     multiplies by a mask that keeps the valid output slots;
   * sum pooling ("Homomorphic pooling layer") and the HW dense layer end with
-    a rotate-and-sum S <- S + Rot(S, r), r = span/2 ... 1, leaving the sum of
-    the first ``span`` slots in slot 0;
+    a rotate-and-sum leaving the sum of the first ``span`` slots in slot 0
+    (bfv.rotate_sum: two rounds of hoisted rotations, baby and giant steps,
+    each summed over Q_l P and brought down by one ModDown);
   * plaintext-branch features are added after the convolution (and its mask)
     as encoded plaintexts (section "The unidirectional connections");
   * each square activation is followed by relinearisation and, while at least
     two primes remain, a modulus switch.
 Rotations of one ciphertext by several kernel offsets share one digit
-decomposition (hoisting), which is bit-identical to rotating one at a time.
+decomposition (hoisting); a convolution keeps them over Q_l P and divides the
+weighted, masked sum by P once per output (bfv.rotations_extended).
 """
 from __future__ import annotations
 
@@ -97,7 +99,7 @@ def plan(name: str):
                         moved_span = span
                     else:
                         info["sum_span"] = span
-                    steps.update(span >> (k + 1) for k in range(span.bit_length() - 1))
+                    steps.update(r for rs in bfv.rotate_sum_steps(span) for r in rs)
                     spatial = False
             elif moved_span:
                 info["sum_span"] = moved_span
@@ -108,8 +110,15 @@ def plan(name: str):
                 info["in_slots"] = prev["out_slots"]
                 span = _span(max(prev["out_slots"]))
                 info["sum_span"] = span
-                steps.update(span >> (k + 1) for k in range(span.bit_length() - 1))
+                steps.update(r for rs in bfv.rotate_sum_steps(span) for r in rs)
                 spatial = False
+        # a square followed by a scalar dense layer (weights per ciphertext: slot batching, or the
+        # dense layer a global sum was moved after) leaves its products unrelinearised; the dense
+        # layer's weighted sums run over the three parts and it relinearises its outputs
+        scalar = lay["kind"] == "dense" and lay.get("method") != "diag" and "in_slots" not in info
+        if layers and layers[-1].get("square") and scalar and not layers[-1].get("sum_span"):
+            layers[-1]["defer_relin"] = True
+            info["relin_in"] = True
         layers.append(info)
     if wl["packing"] == "bhw":
         n = params.get(wl["params"]).n
@@ -263,7 +272,12 @@ class OracleSession:
         outputs = range(n_out) if outputs is None else outputs
         res = {}
         for o in outputs:
-            ct = bfv.mac(prm, [cts[i] for i in range(n_in)], [int(x) for x in w[o]])
+            if info.get("relin_in"):
+                # inputs are unrelinearised products: the sum over three parts, then one key switch
+                ct = bfv.relinearize3(prm, bfv.mac3(prm, [cts[i] for i in range(n_in)], [int(x) for x in w[o]]),
+                                      self.rk)
+            else:
+                ct = bfv.mac(prm, [cts[i] for i in range(n_in)], [int(x) for x in w[o]])
             if info.get("features"):
                 # batch packing: slot b gets image b's feature of output o
                 fq = network.quantise(self.inputs["features"][li])[:, o]
@@ -387,14 +401,14 @@ class OracleSession:
         return res
 
     def rotate_sum(self, ct, span: int):
-        r = span // 2
-        while r >= 1:
-            ct = bfv.add(self.prm, ct, bfv.rotate(self.prm, ct, r, self.gk[r]))
-            r //= 2
-        return ct
+        return bfv.rotate_sum(self.prm, ct, span, self.gk)
 
     def _activation(self, ct, info):
-        if info.get("square"):
+        if info.get("square") and info.get("defer_relin"):
+            ct = bfv.square_unrelinearised(self.prm, ct)
+            if ct.level >= 2:
+                ct = bfv.modswitch3(self.prm, ct)
+        elif info.get("square"):
             ct = bfv.square(self.prm, ct, self.rk)
             if ct.level >= 2:
                 ct = bfv.modswitch(self.prm, ct)

@@ -42,7 +42,7 @@ class LayerDesc(C.Structure):
                 ("weights", C.POINTER(C.c_int32)), ("has_features", C.c_int32), ("feature_scale", C.c_float),
                 ("feature_clamp", C.c_int32), ("batch", C.c_int32), ("square", C.c_int32),
                 ("modswitch", C.c_int32), ("sum", C.c_int32), ("block", C.c_int32),
-                ("method", C.c_int32)]
+                ("method", C.c_int32), ("defer_relin", C.c_int32), ("in_parts", C.c_int32)]
 
 
 class NttItem(C.Structure):
@@ -93,6 +93,7 @@ _SIGS = {
     "bcn_layer_destroy": (None, [_VP]),
     "bcn_layer_rotation_steps": (_I, [_VP, _I32P, _I]),
     "bcn_layer_shape": (_I, [_VP, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)]),
+    "bcn_layer_parts": (_I, [_VP, C.POINTER(_I), C.POINTER(_I)]),
     "bcn_layer_eval": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "bcn_layer_eval_batch": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _I, _VP]),
     "bcn_profile_enable": (_I, [_VP, _I]),
@@ -110,6 +111,7 @@ _SIGS = {
     "bcn_ckks_square_relin_rescale": (_I, [_VP, _VP, _VP, _VP, _I, _I, _VP]),
     "bcn_scratch_info": (_I, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "bcn_scratch_release": (_I, [_VP]),
+    "bcn_rotate_sum_steps": (_I, [_I, _I32P, _I]),
     "bcn_sample": (_I, [_I, C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64, _I, _I64P]),
     "bcn_gaussian_table": (_I, [_U64P]),
     "bcn_secret_key_generate": (_I, [_VP, C.c_uint64, C.POINTER(_VP)]),
@@ -162,6 +164,16 @@ def sample(kind, seed, purpose, index, n, q=0):
     out = np.zeros(n, dtype=np.uint64 if kind == BCN_SAMPLE_UNIFORM else np.int64)
     _check(lib().bcn_sample(kind, seed, purpose, index, q, n, out.ctypes.data_as(C.c_void_p)))
     return out
+
+
+def rotate_sum_steps(span):
+    """The rotation steps bcn_rotate_sum(span) needs."""
+    n = lib().bcn_rotate_sum_steps(span, None, 0)
+    if n < 0:
+        _check(n)
+    out = np.zeros(max(n, 1), dtype=np.int32)
+    lib().bcn_rotate_sum_steps(span, out.ctypes.data_as(C.c_void_p), n)
+    return [int(x) for x in out[:n]]
 
 
 def gaussian_table():
@@ -493,6 +505,8 @@ class Layer:
         d.sum = int(desc.get("sum") or 0)
         d.block = int(desc.get("block") or 0)
         d.method = int(desc.get("method") or 0)
+        d.defer_relin = 1 if desc.get("defer_relin") else 0
+        d.in_parts = int(desc.get("in_parts") or 2)
         self.desc = d
         h = C.c_void_p()
         _check(lib().bcn_layer_create(ctx.h, C.byref(d), level, C.byref(h)))
@@ -505,19 +519,26 @@ class Layer:
         ni, no, lo = C.c_int(), C.c_int(), C.c_int()
         _check(lib().bcn_layer_shape(h, C.byref(ni), C.byref(no), C.byref(lo)))
         self.n_in, self.n_out, self.level_out = ni.value, no.value, lo.value
+        pi, po = C.c_int(), C.c_int()
+        _check(lib().bcn_layer_parts(h, C.byref(pi), C.byref(po)))
+        self.in_parts, self.out_parts = pi.value, po.value
         self.level = level
+
+    def _empty_out(self, rows):
+        import torch
+        return torch.empty((rows, self.out_parts, self.level_out, self.ctx.n), dtype=torch.float64, device="cuda")
 
     def __call__(self, ek, ct, features=None, out=None):
         if out is None:
-            out = self.ctx.empty_ct(self.n_out, self.level_out)
+            out = self._empty_out(self.n_out)
         fp = _dptr(features) if features is not None else None
         _check(lib().bcn_layer_eval(self.ctx.h, ek.h, self.h, _dptr(ct), _dptr(out), fp, _stream()))
         return out
 
     def batch(self, ek, ct, n_requests, features=None, out=None):
-        """R requests at once: ct [R*n_in][2][level][N] -> [R*n_out][2][level_out][N]."""
+        """R requests at once: ct [R*n_in][in_parts][level][N] -> [R*n_out][out_parts][level_out][N]."""
         if out is None:
-            out = self.ctx.empty_ct(n_requests * self.n_out, self.level_out)
+            out = self._empty_out(n_requests * self.n_out)
         fp = _dptr(features) if features is not None else None
         _check(lib().bcn_layer_eval_batch(self.ctx.h, ek.h, self.h, _dptr(ct), _dptr(out), fp, n_requests,
                                           _stream()))

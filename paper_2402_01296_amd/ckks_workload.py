@@ -65,7 +65,7 @@ class CkksSession:
                     moved = 1
                     while moved < last + 1:
                         moved *= 2
-                    steps.update(moved >> (k + 1) for k in range(moved.bit_length() - 1))
+                    steps.update(bcn.rotate_sum_steps(moved))
             else:
                 info["sum_span"] = moved
                 moved = 0

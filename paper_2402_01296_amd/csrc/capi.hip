@@ -515,11 +515,26 @@ int bcn_rotate_sum(bcn_context* ctx, const bcn_eval_keys* ek, double* ct, int n,
     check_n(n);
     check_ptr(ek, "eval keys");
     if (span > c.n / 2) throw bcn::Error(BCN_ERR_INVALID, "span beyond the slot row");
+    const auto rounds = bcn::rotate_sum_rounds(span);
     if (n == 0) return;
     check_ptr(ct, "ct");
-    for (int r = span / 2; r >= 1; r /= 2) ek->k->rot_key(r);
+    for (const auto& rs : rounds)
+      for (int r : rs) ek->k->rot_key(r);
     bcn::rotate_sum(c, *ek->k, ct, n, level, span, (hipStream_t)stream);
   });
+}
+
+int bcn_rotate_sum_steps(int span, int32_t* steps, int cap) {
+  int count = 0;
+  const int rc = guard([&] {
+    const auto rounds = bcn::rotate_sum_rounds(span);
+    for (const auto& rs : rounds)
+      for (int r : rs) {
+        if (steps && count < cap) steps[count] = r;
+        ++count;
+      }
+  });
+  return rc == BCN_OK ? count : rc;
 }
 
 int bcn_modswitch(bcn_context* ctx, const double* in, double* out, int n, int level, bcn_stream stream) {
@@ -637,6 +652,16 @@ int bcn_layer_shape(const bcn_layer* layer, int* n_in, int* n_out, int* level_ou
   return BCN_OK;
 }
 
+int bcn_layer_parts(const bcn_layer* layer, int* in_parts, int* out_parts) {
+  if (!layer || !layer->l) {
+    g_err = "null layer";
+    return BCN_ERR_INVALID;
+  }
+  if (in_parts) *in_parts = layer->l->in_parts;
+  if (out_parts) *out_parts = layer->l->defer ? 3 : 2;
+  return BCN_OK;
+}
+
 int bcn_layer_eval(bcn_context* ctx, const bcn_eval_keys* ek, const bcn_layer* layer, const double* in, double* out,
                    const float* features, bcn_stream stream) {
   return bcn_layer_eval_batch(ctx, ek, layer, in, out, features, 1, stream);
@@ -653,7 +678,7 @@ int bcn_layer_eval_batch(bcn_context* ctx, const bcn_eval_keys* ek, const bcn_la
     check_ptr(in, "in");
     check_ptr(out, "out");
     const bcn::Layer& L = *layer->l;
-    if (L.square && !ek->k->relin) throw bcn::Error(BCN_ERR_KEY, "missing relinearisation key");
+    if ((L.square || L.in_parts == 3) && !ek->k->relin) throw bcn::Error(BCN_ERR_KEY, "missing relinearisation key");
     for (int st : L.all_steps) ek->k->rot_key(st);
     bcn::layer_eval(c, *ek->k, L, in, out, features, (hipStream_t)stream, n_requests);
   });

@@ -262,9 +262,10 @@ struct MacPlan {
 // (0: contiguous [rows][2][level][N]); e.g. the Q limbs of a [rows][2][level+m][N] buffer
 // basis: the limbs of each part when they are not Q_level (e.g. Q_level then P); then
 // `level` only selects the delta constants and delta_msg must be null.
+// parts = 3: rows of three-part products [3][level][N] (no delta add)
 void mac(const Context& c, const MacPlan& p, const double* in, double* out, int level, hipStream_t s, int requests = 1,
          size_t in_req = 0, size_t out_req = 0, const double* delta_msg = nullptr, size_t out_ct = 0,
-         size_t out_part = 0, const Basis* basis = nullptr);
+         size_t out_part = 0, const Basis* basis = nullptr, int parts = 2);
 
 // The MAC of a slot-batched layer feeding a square, writing out rows [2][level + m][N] over
 // Q_level then B (the extension fused into the MAC's stores); out_ct, out_part as for mac.
@@ -287,9 +288,10 @@ void tensor_square(const Context& c, const double* in, double* out, int n, const
 // exact centred extension of [n][2][level][N] (coeff) into [n][2][level+m][N] over Q_level then B
 void extend_qb(const Context& c, const double* in, double* out, int n, int level, hipStream_t s);
 // round(t x / Q_level) for [n][3][level+m][N] (coeff, Q then B) -> [n][3][level][N], or with
-// only_d2 just part 2 of each ciphertext -> [n][level][N]
+// only_d2 just part 2 of each ciphertext -> [n][level][N]; modsw: then the modulus switch to
+// level - 1 limbs
 void scale_round(const Context& c, const double* in, double* out, int n, int level, hipStream_t s,
-                 bool only_d2 = false);
+                 bool only_d2 = false, bool modsw = false);
 // centred digits of x [n][level][N] (coeff) raised to Q_level+P: [n][dnum][level+K][N]
 void decompose_modup(const Context& c, const double* in, size_t in_stride, double* out, int n, int level,
                      hipStream_t s);
@@ -335,6 +337,16 @@ void ks_extended(const Context& c, const double* src, size_t src_stride, int n_s
 // n sources c^ ([n][2][level][N], transform domain) into X + i * out_outer ([2][level + K][N]).
 void ext_tap0(const Context& c, const double* chat, int n, int level, const KsExt& ext, double* X, size_t out_outer,
               hipStream_t s);
+// One rotate-and-sum round over n sources (c1 parts at src + i * src_stride, coefficient form):
+// digits into D, then u[i] = P c^ + sum over the table's steps of Rot~(c, step) over Q_level P
+// in the transform domain ([n][2][level + K][N]); chat: the sources transformed over Q_level
+// ([2][level][N] at chat + i * c_stride); ext.pm as for ks_extended.
+void ks_sum_round(const Context& c, const double* src, size_t src_stride, int n, int level, const KeySel& ks,
+                  const double* chat, size_t c_stride, const KsExt& ext, double* D, double* u, hipStream_t s);
+// out = sum of `slabs` slabs of `words` residues each (slab k at in + k * words), reduced mod the
+// basis' primes; the words are n_polys polynomials [n_polys][b.n][N]
+void sum_slabs(const Context& c, const double* in, int slabs, size_t words, int n_polys, const Basis& b, double* out,
+               hipStream_t s);
 // exact round(u/P) of u [n][2][level+K][N] (coeff) -> [n][2][level][N], plus an addend:
 // add_mode 0: none; 1: add [n][2][level][N]; 2: add sigma_k(add) to part 0 only (add [n][2][level][N]);
 // 3: add add itself and sigma_k of its part 0 (rotate-and-add; out must not alias add).

@@ -241,6 +241,16 @@ __global__ void k_ext_tap0(const double* __restrict__ chat, int n, int level, in
   X[i * out_outer + r] = v;
 }
 
+__global__ void k_sum_slabs(const double* __restrict__ in, int slabs, size_t words, int nb, int logn, Basis b,
+                            const Mod* __restrict__ mods, double* __restrict__ out) {
+  const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (idx >= words) return;
+  const Mod m = mods[b.id[(idx >> logn) % nb]];
+  double a = 0.0;                       // slabs <= 2^11 residues below 2^41: exact
+  for (int k = 0; k < slabs; ++k) a += in[(size_t)k * words + idx];
+  out[idx] = reduce(a, m);
+}
+
 __global__ void k_ptvec_mac(const double* __restrict__ in, int n_in, double* __restrict__ out, int n_out,
                             int level, int logn, const double* __restrict__ pt, Basis b,
                             const Mod* __restrict__ mods, int requests) {
@@ -358,13 +368,28 @@ __device__ __forceinline__ void scale_round_coeff(const double* __restrict__ src
 template <int NS>
 __global__ void __launch_bounds__(TPB)
 k_scale_round(const double* __restrict__ in, double* __restrict__ out, int npoly, int logn, int nq, int poly_mul,
-              int poly_add, const Conv* __restrict__ cvp, const Mod* __restrict__ mods) {
+              int poly_add, const Conv* __restrict__ cvp, const Mod* __restrict__ mods, int modsw, LimbConsts linv) {
   const size_t N = (size_t)1 << logn;
   const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
   if (idx >= (size_t)npoly * N) return;
   const size_t poly = idx >> logn, k = idx & (N - 1);
   double res[NS];
   scale_round_coeff<NS>(in + (poly * poly_mul + poly_add) * NS * N + k, N, nq, *cvp, mods, res);
+  if (modsw) {
+    // then drop q_{nq-1}: (r - lift_c([r]_{q_last})) / q_last, as the modulus switch
+    const Conv& cv = *cvp;
+    const Mod ml = mods[cv.dst[nq - 1]];
+    const double last = res[nq - 1];
+    const double lc = last > (ml.q - 1.0) * 0.5 ? last - ml.q : last;
+    double* dst = out + poly * (nq - 1) * N + k;
+#pragma unroll
+    for (int d = 0; d < NS; ++d) {
+      if (d >= nq - 1) break;
+      const Mod md = mods[cv.dst[d]];
+      dst[d * N] = norm(mul_lazy(res[d] - lc, linv.v[d], md), md);
+    }
+    return;
+  }
   double* dst = out + poly * nq * N + k;
 #pragma unroll
   for (int d = 0; d < NS; ++d) {
@@ -767,14 +792,16 @@ void delta_consts(const Context& c, int level, double* qmodt_out, double* neg) {
 }  // namespace
 
 void mac(const Context& c, const MacPlan& p, const double* in, double* out, int level, hipStream_t s, int requests,
-         size_t in_req, size_t out_req, const double* delta_msg, size_t out_ct, size_t out_part, const Basis* basis) {
+         size_t in_req, size_t out_req, const double* delta_msg, size_t out_ct, size_t out_part, const Basis* basis,
+         int parts) {
   if (basis && delta_msg) throw Error(-1, "the delta add needs the Q_level basis");
+  if (parts != 2 && (parts != 3 || delta_msg)) throw Error(-1, "MAC over two parts, or three without a delta add");
   const Basis b = basis ? *basis : c.basis_Q(level);
   const int nl = b.n;
-  const int words = 2 * nl * c.n;
+  const int words = parts * nl * c.n;
   if (out_ct == 0) {
     out_ct = (size_t)words;
-    out_part = (size_t)nl * c.n;
+    out_part = (size_t)(words >> 1);          // contiguous rows
   }
   if (p.n_out == 0 || requests == 0) return;
   DeltaAdd da;
@@ -872,6 +899,17 @@ bool mac_qb(const Context& c, const MacPlan& p, const double* in, double* out, i
   return true;
 }
 
+void sum_slabs(const Context& c, const double* in, int slabs, size_t words, int n_polys, const Basis& b, double* out,
+               hipStream_t s) {
+  if (words == 0) return;
+  if (slabs > 2048) throw Error(-1, "too many slabs to sum exactly");
+  if (words != (size_t)n_polys * b.n * c.n) throw Error(-1, "slab size does not match the basis");
+  ProfScope ps(c, "sum_slabs", s, 8.0 * (double)words * (slabs + 1));
+  hipLaunchKernelGGL(k_sum_slabs, dim3(nblocks(words)), dim3(TPB), 0, s, in, slabs, words, b.n, c.logn, b, c.tab.mods,
+                     out);
+  BCN_HIP(hipGetLastError());
+}
+
 void add_delta(const Context& c, double* ct, int n, int level, const double* m, hipStream_t s) {
   if (n == 0) return;
   const Mod mt = c.mod(c.id_t);
@@ -945,15 +983,21 @@ static const Conv* scale_round_conv(const Context& c, int level) {
   return conv_device(c, "sr" + std::to_string(level), cv);
 }
 
-void scale_round(const Context& c, const double* in, double* out, int n, int level, hipStream_t s, bool only_d2) {
+void scale_round(const Context& c, const double* in, double* out, int n, int level, hipStream_t s, bool only_d2,
+                 bool modsw) {
   if (n == 0) return;
+  if (modsw && level < 2) throw Error(-2, "modulus switch needs at least two primes");
   const Conv* dcv = scale_round_conv(c, level);
   const int npoly = only_d2 ? n : 3 * n;
   const int pmul = only_d2 ? 3 : 1, padd = only_d2 ? 2 : 0;
   const int ns = level + c.m;
-  ProfScope ps(c, "scale_round", s, 8.0 * npoly * (double)c.n * (ns + level));
+  LimbConsts linv{};
+  if (modsw)
+    for (int d = 0; d < level - 1; ++d)
+      linv.v[d] = (double)host::invmod(c.primes[level - 1] % c.primes[d], c.primes[d]);
+  ProfScope ps(c, "scale_round", s, 8.0 * npoly * (double)c.n * (ns + (modsw ? level - 1 : level)));
 #define BCN_SR(NS) hipLaunchKernelGGL(k_scale_round<NS>, dim3(nblocks((size_t)npoly * c.n)), dim3(TPB), 0, s, in, out, \
-                                      npoly, c.logn, level, pmul, padd, dcv, c.tab.mods)
+                                      npoly, c.logn, level, pmul, padd, dcv, c.tab.mods, modsw ? 1 : 0, linv)
   BCN_DISPATCH_NS(ns, BCN_SR)
 #undef BCN_SR
   BCN_HIP(hipGetLastError());

@@ -18,6 +18,8 @@ struct Layer {
   int fclamp = 127;
   int batch = 0, stride_b = 0;
   MacPlan mac;
+  int in_parts = 2;              // 3: inputs are unrelinearised products (relinearised after the MAC)
+  bool defer = false;            // the square's output stays unrelinearised (3 parts)
   bool mac_ext = true;           // slot-batched square layer: the MAC writes the B limbs too (when supported)
   std::vector<int32_t> mac_weights;  // host copy of the MAC matrix (for retuning)
   std::vector<int> mac_order;

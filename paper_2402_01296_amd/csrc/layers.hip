@@ -61,6 +61,14 @@ Layer* layer_create(Context& c, const bcn_layer_desc& d, int level) {
   auto L = std::make_unique<Layer>();
   L->kind = d.kind;
   L->packing = d.packing;
+  if (d.in_parts != 0 && d.in_parts != 2 && d.in_parts != 3) throw Error(-1, "in_parts must be 2 or 3");
+  L->in_parts = d.in_parts == 3 ? 3 : 2;
+  L->defer = d.defer_relin != 0;
+  if (L->in_parts == 3 && (d.packing != BCN_PACK_BATCH || d.kind != BCN_DENSE))
+    throw Error(-1, "three-part inputs need a slot-batched (scalar) dense layer");
+  if (L->defer && !d.square) throw Error(-1, "defer_relin needs a square");
+  if (L->defer && d.packing != BCN_PACK_BATCH && (d.kind != BCN_CONV2D || d.sum))
+    throw Error(-1, "a HW layer defers relinearisation only as a convolution without a global sum");
   if (const char* e = std::getenv("BCN_MAC_EXT")) L->mac_ext = std::atoi(e) != 0;
   L->level = level;
   L->square = d.square != 0;
@@ -120,7 +128,7 @@ Layer* layer_create(Context& c, const bcn_layer_desc& d, int level) {
       if (d.sum < 2 || (d.sum & (d.sum - 1)) || d.sum > N / 2)
         throw Error(-1, "sum span must be a power of two in 2..N/2");
       L->span = d.sum;
-      for (int r = L->span / 2; r >= 1; r /= 2) L->all_steps.push_back(r);
+      for (const auto& rs : rotate_sum_rounds(L->span)) L->all_steps.insert(L->all_steps.end(), rs.begin(), rs.end());
       std::sort(L->all_steps.begin(), L->all_steps.end());
     }
     return L.release();
@@ -191,7 +199,7 @@ Layer* layer_create(Context& c, const bcn_layer_desc& d, int level) {
     if (d.sum) {
       L->span = next_pow2(maxs + 1);
       if (L->span > extent) throw Error(-1, "sum span beyond the image block");
-      for (int r = L->span / 2; r >= 1; r /= 2) L->all_steps.push_back(r);
+      for (const auto& rs : rotate_sum_rounds(L->span)) L->all_steps.insert(L->all_steps.end(), rs.begin(), rs.end());
     }
   } else if (d.method == BCN_DENSE_DIAGONAL) {
     // diagonal method: n1 + n2 - 1 rotations of each input channel (steps 1 - n2 .. n1 - 1), each
@@ -245,7 +253,7 @@ Layer* layer_create(Context& c, const bcn_layer_desc& d, int level) {
     L->span = next_pow2(maxs + 1);
     if (L->span < 2) L->span = 2;
     if (L->span > extent) throw Error(-1, "sum span beyond the image block");
-    for (int r = L->span / 2; r >= 1; r /= 2) L->all_steps.push_back(r);
+    for (const auto& rs : rotate_sum_rounds(L->span)) L->all_steps.insert(L->all_steps.end(), rs.begin(), rs.end());
     if (d.has_features) throw Error(-1, "features are supported on convolutions");
   }
   for (int st : L->steps) L->all_steps.push_back(st);
@@ -256,7 +264,7 @@ Layer* layer_create(Context& c, const bcn_layer_desc& d, int level) {
 
 void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, double* out, const float* features,
                 hipStream_t s, int R) {
-  // R independent requests: in [R][n_in][2][level][N] -> out [R][n_out][2][level_out][N]; every step
+  // R independent requests: in [R][n_in][in_parts][level][N] -> out [R][n_out][out_parts][level_out][N]; every step
   // below runs once over all R requests' ciphertexts (one launch per kernel).
   Arena& ar = *c.arena;
   const size_t N = c.n;
@@ -283,12 +291,26 @@ void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, doub
       bt.id[0] = c.id_t;
       ntt_inverse(c, fm, nout, bt, s);
     }
-    if (qb) {
+    if (L.in_parts == 3) {
+      // unrelinearised inputs: the weighted sums run over the three parts and each output is
+      // relinearised once (then the features, then the square's extension to Q+B)
+      const size_t ct3 = (size_t)3 * level * N;
+      double* M = ar.take((size_t)nout * ct3);
+      mac(c, L.mac, in, M, level, s, R, (size_t)L.n_in * ct3, (size_t)L.n_out * ct3, nullptr, 0, 0, nullptr, 3);
+      double* A2 = qb ? ar.take((size_t)nout * ctw) : A;
+      relinearize3(c, ek, M, A2, nout, level, s);
+      if (fm) add_delta(c, A2, nout, level, fm, s);
+      if (qb) {
+        extend_qb(c, A2, A, nout, level, s);
+        b_filled = true;
+      }
+    } else if (qb) {
       b_filled = L.mac_ext &&
                  mac_qb(c, L.mac, in, A, level, s, R, (size_t)L.n_in * ctw, (size_t)L.n_out * ctq, fm, ctq, ctq / 2);
       if (!b_filled) mac(c, L.mac, in, A, level, s, R, (size_t)L.n_in * ctw, (size_t)L.n_out * ctq, fm, ctq, ctq / 2);
-    } else
+    } else {
       mac(c, L.mac, in, A, level, s, R, (size_t)L.n_in * ctw, (size_t)L.n_out * ctw, fm);
+    }
   } else if (L.diag) {
     // taps [R*n_in][k2] as for a convolution, then all taps times their weight vectors, summed
     double* taps = ar.take((size_t)nin * L.k2 * ctw);
@@ -340,8 +362,14 @@ void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, doub
     }
     return;
   }
-  if (qb) {
+  if (qb && L.defer) {
+    square_defer(c, A, out, nout, level, L.modsw, s, b_filled);
+  } else if (qb) {
     square_relin_qb(c, ek, A, out, nout, level, L.modsw, s, b_filled);
+  } else if (L.square && L.defer) {
+    double* X = ar.take((size_t)nout * ctq);
+    extend_qb(c, A, X, nout, level, s);
+    square_defer(c, X, out, nout, level, L.modsw, s, true);
   } else if (L.square) {
     square_relin(c, ek, A, out, nout, level, L.modsw, s);
   } else {

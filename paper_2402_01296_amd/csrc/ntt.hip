@@ -13,6 +13,7 @@
 // 2^45), which the lazy FP64 product tolerates; one reduction at the end
 // brings them back to [0, q).
 #include <algorithm>
+#include <cstdlib>
 #include <string>
 
 #include "convert.h"
@@ -846,6 +847,89 @@ void launch_ks_split(const Context& c, int part, const double* src, size_t strid
   }
 }
 
+// One round of a rotate-and-sum: block (source i, limb, part) accumulates over every step of
+// the key table u = sum_sel sum_j sigma_sel(D_j^) key_sel,j[part] + P c^part + (part 0, Q limbs)
+// sum_sel P sigma_sel(c0^): the taps of the round kept over Q_l P and already summed.  Each
+// digit limb (and c0^'s limb) is staged once in LDS and read through every step's permutation;
+// the key words are read in storage order.  u is stored in the transform domain
+// ([n][2][level + K][N]).  The sum has at most 1 + nk (dnum + 1) lazy terms below q, exact for
+// nk <= 256.
+template <int LOGN, int LOGE>
+__global__ void __launch_bounds__(1 << (LOGN - LOGE))
+k_ks_sum(const double* __restrict__ D, KeySel ka, int level, int dnum, int L, Basis qp, Tables tb,
+         const double* __restrict__ chat, size_t c_stride, KsExt ext, int groups, double* __restrict__ u) {
+  constexpr int N = 1 << LOGN, E = 1 << LOGE, T = N >> LOGE;
+  extern __shared__ double lds[];
+  const int nb = qp.n;
+  const int n_src = gridDim.x / (nb * 2 * groups);
+  // limb-major: the blocks of one XCD share a limb, whose key words they read in step
+  const int wx = xcd_order(blockIdx.x, gridDim.x);
+  const int part = wx & 1;
+  const int w = (wx >> 1) / groups, grp = (wx >> 1) % groups;
+  const int limb = w / n_src, i = w - limb * n_src;
+  // group grp takes steps [s0, s1) of the table and writes its partial sum to slab grp
+  const int s0 = grp * ka.nk / groups, s1 = (grp + 1) * ka.nk / groups;
+  u += (size_t)grp * n_src * 2 * nb * N;
+  const Mod m = tb.mods[qp.id[limb]];
+  const double* dd = D + (size_t)i * dnum * nb * N + (size_t)limb * N;
+  const int klimb = limb < level ? limb : L + (limb - level);
+  const int KL = nb - level + L;
+  const int tid = threadIdx.x;
+  int ti[E];                                       // transform index of element e (word e T + tid)
+  double acc[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    ti[e] = ntt_index(e * T + tid, LOGN);
+    acc[e] = 0.0;
+  }
+  if (limb < level && grp == 0) {
+    const double* cp = chat + (size_t)i * c_stride + ((size_t)part * level + limb) * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = mul_lazy(cp[e * T + tid], ext.pm[limb], m);
+  }
+  for (int j = 0; j < dnum; ++j) {
+    const double* dj = dd + (size_t)j * nb * N;
+    __syncthreads();
+#pragma unroll 4
+    for (int p = tid; p < N; p += T) lds[p] = dj[p];
+    __syncthreads();
+    for (int sel = s0; sel < s1; ++sel) {
+      const int gal = ka.galois[sel];
+      const double* kp = ka.keys[sel] + ((size_t)(j * 2 + part) * KL + klimb) * N;
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        acc[e] += mul_lazy(lds[ntt_store(ntt_perm(ti[e], gal, LOGN), LOGN)], kp[e * T + tid], m);
+    }
+  }
+  if (part == 0 && limb < level) {
+    const double* c0 = chat + (size_t)i * c_stride + (size_t)limb * N;
+    __syncthreads();
+#pragma unroll 4
+    for (int p = tid; p < N; p += T) lds[p] = c0[p];
+    __syncthreads();
+    const double pm = ext.pm[limb];
+    for (int sel = s0; sel < s1; ++sel) {
+      const int gal = ka.galois[sel];
+#pragma unroll
+      for (int e = 0; e < E; ++e) acc[e] += mul_lazy(lds[ntt_store(ntt_perm(ti[e], gal, LOGN), LOGN)], pm, m);
+    }
+  }
+  double* dst = u + ((size_t)(i * 2 + part) * nb + limb) * N;
+#pragma unroll
+  for (int e = 0; e < E; ++e) dst[e * T + tid] = reduce(acc[e], m);
+}
+
+template <int LOGN, int LOGE>
+void launch_ks_sum(const Context& c, int level, const double* D, const KeySel& ks, int n_src, const double* chat,
+                   size_t c_stride, const KsExt& ext, int groups, double* u, const Basis& qp, hipStream_t s) {
+  constexpr int N = 1 << LOGN;
+  const unsigned blocks = (unsigned)n_src * qp.n * 2 * groups;
+  if (blocks == 0) return;
+  hipLaunchKernelGGL((k_ks_sum<LOGN, LOGE>), dim3(blocks), dim3(N >> LOGE), (size_t)N * sizeof(double), s, D, ks,
+                     level, c.dnum(level), c.L, qp, c.tab, chat, c_stride, ext, groups, u);
+  BCN_HIP(hipGetLastError());
+}
+
 // the extended inner product (no inverse transform) of n_out outputs
 template <int LOGN, int LOGE>
 void launch_ks_ext(const Context& c, int level, const double* D, const KeySel& ks, int n_out, int d_div, double* u,
@@ -891,6 +975,7 @@ void set_attr() {
                               lds));
   BCN_HIP(hipFuncSetAttribute((const void*)k_ks_intt<LOGN, LOGE, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               lds));
+  BCN_HIP(hipFuncSetAttribute((const void*)k_ks_sum<LOGN, LOGE>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
   BCN_HIP(hipFuncSetAttribute((const void*)k_ks_intt<LOGN, LOGE, false, true>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, lds));
   BCN_HIP(hipFuncSetAttribute((const void*)k_ks_intt<LOGN, LOGE, true, true>,
@@ -1100,6 +1185,37 @@ void ks_extended(const Context& c, const double* src, size_t src_stride, int n_s
 #undef BCN_KSE_CASE
     default: throw Error(-1, "unsupported ring degree / transform shape");
   }
+}
+
+void ks_sum_round(const Context& c, const double* src, size_t src_stride, int n, int level, const KeySel& ks,
+                  const double* chat, size_t c_stride, const KsExt& ext, double* D, double* u, hipStream_t s) {
+  if (!ks.keys || ks.nk < 1 || ks.nk > 256) throw Error(-1, "a rotate-and-sum round takes 1..256 keys");
+  ks_split_digits_only(c, src, src_stride, n, level, D, s);
+  const Basis qp = c.basis_QP(level);
+  const int dnum = c.dnum(level);
+  const double units = (double)n * qp.n * 2;
+  // the steps are split into groups so that the launch has about two blocks per CU; the groups'
+  // partial sums are added by sum_slabs
+  double per_cu = 2.0;
+  if (const char* e = std::getenv("BCN_KS_SUM_PER_CU")) per_cu = std::max(0.25, std::atof(e));
+  const int groups = std::max(1, std::min(ks.nk, (int)((per_cu * c.n_cus) / units)));
+  double* part_u = groups > 1 ? c.arena->take((size_t)groups * n * 2 * qp.n * c.n) : u;
+  // digits (once per step pass, from LDS), the steps' key words and the sum out
+  ProfScope ps(c, "ks_sum", s, 8.0 * c.n * units * (dnum + (double)ks.nk * dnum + 2.0),
+               units * ks.nk * (dnum + 1.0) * 7.0 * c.n);
+  const int key = c.logn * 16 + c.ks_loge;
+  switch (key) {
+#define BCN_KSM_CASE(LN, LE) \
+  case LN * 16 + LE: launch_ks_sum<LN, LE>(c, level, D, ks, n, chat, c_stride, ext, groups, part_u, qp, s); break;
+    BCN_KSM_CASE(10, 3) BCN_KSM_CASE(10, 4)
+    BCN_KSM_CASE(11, 3) BCN_KSM_CASE(11, 4)
+    BCN_KSM_CASE(12, 4) BCN_KSM_CASE(12, 5)
+    BCN_KSM_CASE(13, 4) BCN_KSM_CASE(13, 5)
+    BCN_KSM_CASE(14, 4) BCN_KSM_CASE(14, 5)
+#undef BCN_KSM_CASE
+    default: throw Error(-1, "unsupported ring degree / transform shape");
+  }
+  if (groups > 1) sum_slabs(c, part_u, groups, (size_t)n * 2 * qp.n * c.n, n * 2, qp, u, s);
 }
 
 void ks_fused(const Context& c, const double* src, size_t src_stride, int n, int level, const double* key, int galois,

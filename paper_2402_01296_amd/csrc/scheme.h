@@ -74,10 +74,22 @@ void ckks_square_relin_rescale(Context& c, const EvalKeys& ek, const double* in,
 // the same from x [n][2][level+m][N] whose Q limbs hold the input; x's B limbs are filled in place
 void square_relin_qb(Context& c, const EvalKeys& ek, double* x, double* out, int n, int level, bool modsw,
                      hipStream_t s, bool b_filled = false);
+// The square with its relinearisation deferred: x as for square_relin_qb; out [n][3][level'][N]
+// holds (d0, d1, d2) = round(t (x (x) x) / Q_level), then modulus-switched when modsw
+// (level' = level - 1).  Relinearisation is linear, so the next linear layer may run over the
+// three parts and relinearise its outputs (relinearize3).
+void square_defer(Context& c, double* x, double* out, int n, int level, bool modsw, hipStream_t s,
+                  bool b_filled = false);
+// (d0, d1, d2) [n][3][level][N] -> (d0 + KS(d2)_0, d1 + KS(d2)_1) [n][2][level][N]
+void relinearize3(Context& c, const EvalKeys& ek, const double* in, double* out, int n, int level, hipStream_t s);
 // out placement as in moddown (out_div = 0: contiguous [n_in][n_steps])
 void rotate_hoisted(Context& c, EvalKeys& ek, const double* in, int n_in, int level, const std::vector<int>& steps,
                     double* out, hipStream_t s, int out_div = 0, size_t out_outer = 0);
-void rotate_sum(Context& c, const EvalKeys& ek, double* ct, int n, int level, int span, hipStream_t s);
+// In place: the sum of Rot(c, r) over r < span, in two rounds (rotate_sum_rounds: baby steps
+// 1 .. b-1, giant steps b .. (g-1) b, b = 2^ceil(k/2) for span = 2^k), each a hoisted set of
+// rotations kept over Q_level P, summed, and brought down by one ModDown.
+std::vector<std::vector<int>> rotate_sum_rounds(int span);
+void rotate_sum(Context& c, EvalKeys& ek, double* ct, int n, int level, int span, hipStream_t s);
 // The k2 taps of each of n_in inputs kept over Q_level P before ModDown, in the transform
 // domain: X [n_in][k2][2][level + K][N], tap 0 = P * input, tap 1 + r = Rot~(input, steps[r]).
 // in: the inputs (coefficient form), in_hat: the same transformed over Q_level.

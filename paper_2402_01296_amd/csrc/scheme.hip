@@ -277,6 +277,38 @@ void square_relin_tail(Context& c, const EvalKeys& ek, double* X, double* out, i
 }
 }  // namespace
 
+void square_defer(Context& c, double* x, double* out, int n, int level, bool modsw, hipStream_t s, bool b_filled) {
+  if (modsw && level < 2) throw Error(-2, "modulus switch needs two primes");
+  if (n == 0) return;
+  if (!b_filled) extend_qb(c, x, x, n, level, s);
+  const Basis qb = c.basis_QB(level);
+  double* Y = c.arena->take((size_t)n * 3 * qb.n * c.n);
+  if (c.fuse_square) {
+    square_transform_fused(c, x, Y, n, qb, s);
+  } else {
+    ntt_forward(c, x, 2 * n, qb, s);
+    tensor_square(c, x, Y, n, qb, s);
+    ntt_inverse(c, Y, 3 * n, qb, s);
+  }
+  scale_round(c, Y, out, n, level, s, false, modsw);
+}
+
+void relinearize3(Context& c, const EvalKeys& ek, const double* in, double* out, int n, int level, hipStream_t s) {
+  if (!ek.relin) throw Error(-3, "missing relinearisation key");
+  if (n == 0) return;
+  Arena& ar = *c.arena;
+  const size_t N = c.n;
+  const Basis qp = c.basis_QP(level);
+  const size_t ct3 = (size_t)3 * level * N;
+  double* D = ar.take((size_t)n * c.dnum(level) * qp.n * N);
+  double* U = ar.take((size_t)n * 2 * qp.n * N);
+  KeySel ks;
+  ks.key1 = ek.relin;
+  // key switch of d2, then ModDown adds d0 and d1
+  ks_split(c, in + 2 * level * N, ct3, n, level, ks, n, 1, D, U, s);
+  moddown(c, U, n, level, in, 1, ct3, 1, ks, false, out, s);
+}
+
 size_t square_relin_scratch_doubles(const Context& c, int n, int level) {
   // mirrors the arena takes of square_relin and square_relin_tail
   const size_t N = c.n, nb = level + c.m, nbp = level + c.K, dn = c.dnum(level);
@@ -364,43 +396,50 @@ void taps_extended(Context& c, EvalKeys& ek, const double* in, const double* in_
   ks_extended(c, in + level * N, (size_t)2 * level * N, n_in, level, ks, n_in * ns, ns, D, X + ctx, ext, s);
 }
 
-void rotate_sum(Context& c, const EvalKeys& ek, double* ct, int n, int level, int span, hipStream_t s) {
+std::vector<std::vector<int>> rotate_sum_rounds(int span) {
   if (span < 2 || (span & (span - 1))) throw Error(-1, "rotate-and-sum span must be a power of two >= 2");
+  int k = 0;
+  while ((1 << k) < span) ++k;
+  const int b = 1 << ((k + 1) / 2), g = span / b;
+  std::vector<std::vector<int>> rounds(2);
+  for (int r = 1; r < b; ++r) rounds[0].push_back(r);
+  for (int j = 1; j < g; ++j) rounds[1].push_back(j * b);
+  return rounds;
+}
+
+void rotate_sum(Context& c, EvalKeys& ek, double* ct, int n, int level, int span, hipStream_t s) {
+  const auto rounds = rotate_sum_rounds(span);
   if (n == 0) return;
   Arena& ar = *c.arena;
   const size_t N = c.n;
   const Basis qp = c.basis_QP(level);
-  const int nbp = qp.n, dn = c.dnum(level);
-  double* D = ar.take((size_t)n * dn * nbp * N);
-  double* U = ar.take((size_t)n * 2 * nbp * N);
-  double* R = ar.take((size_t)n * 2 * level * N);
-  // S <- S + Rot(S, r) for r = span/2 .. 1; the sum is formed inside ModDown (add mode 3),
-  // alternating between ct and R as source and destination
-  double* cur = ct;
-  double* nxt = R;
-  for (int r = span / 2; r >= 1; r /= 2) {
-    KeySel ks;
-    ks.key1 = ek.rot_key(r);
-    ks.galois1 = galois_element(c, r);
-    ks.kinv1 = galois_inverse(c, ks.galois1);
-    if (c.ks_mode == 1) {
-      ks_fused(c, cur + level * N, (size_t)2 * level * N, n, level, ks.key1, ks.galois1, U, s);
-    } else if (c.ks_mode_rot == 2) {
-      // one Galois element per call: permute the digits as they are stored (scattered
-      // stores) instead of on the inner product's digit reads (scattered loads)
-      KeySel kd = ks;
-      kd.galois1 = 1;
-      ks_split(c, cur + level * N, (size_t)2 * level * N, n, level, kd, n, 1, D, U, s, ks.galois1);
-    } else {
-      decompose_modup(c, cur + level * N, (size_t)2 * level * N, D, n, level, s);
-      ntt_forward(c, D, n * dn, qp, s);
-      ks_inner(c, D, 1, ks, n, level, U, s);
-      ntt_inverse(c, U, 2 * n, qp, s);
-    }
-    moddown(c, U, n, level, cur, 1, (size_t)2 * level * N, 3, ks, false, nxt, s);
-    std::swap(cur, nxt);
+  const size_t ctw = (size_t)2 * level * N, ctx = (size_t)2 * qp.n * N;
+  // each round: S <- ModDown(sum over its taps of Rot~(S, r)), tap 0 = P S; the taps' inner
+  // products run over all of them at once (one digit decomposition of S)
+  KsExt ext;
+  for (int d = 0; d < level; ++d) {
+    const uint64_t q = c.primes[d];
+    uint64_t pm = 1;
+    for (int i = 0; i < c.K; ++i) pm = host::mulmod(pm, c.primes[c.idP(i)] % q, q);
+    ext.pm[d] = (double)pm;
   }
-  if (cur != ct) copy_rows(cur, 0, ct, 0, (size_t)n * 2 * level * N, 1, s);
+  for (const std::vector<int>& steps : rounds) {
+    if (steps.empty()) continue;
+    double* H = ar.take((size_t)n * ctw);
+    copy_rows(ct, 0, H, 0, (size_t)n * ctw, 1, s);
+    ntt_forward(c, H, 2 * n, c.basis_Q(level), s);
+    const KeyTable& tb = ek.table(steps);
+    KeySel ks;
+    ks.keys = tb.keys;
+    ks.galois = tb.galois;
+    ks.kinv = tb.kinv;
+    ks.nk = tb.nk;
+    double* D = ar.take((size_t)n * c.dnum(level) * qp.n * N);
+    double* U = ar.take((size_t)n * ctx);
+    ks_sum_round(c, ct + level * N, ctw, n, level, ks, H, ctw, ext, D, U, s);
+    ntt_inverse(c, U, 2 * n, qp, s);
+    moddown(c, U, n, level, nullptr, 1, 0, 0, KeySel(), false, ct, s);
+  }
 }
 
 MacPlan make_mac_plan(const Context& c, const std::vector<int32_t>& w, int n_out, int n_in,

@@ -242,10 +242,12 @@ std::string autotune_layer_mac(Context& c, Layer& L, hipStream_t s) {
   const bool ext = L.packing != BCN_PACK_BATCH && L.kind == BCN_CONV2D && !L.diag;
   const Basis qp = c.basis_QP(L.level);
   const Basis* basis = ext ? &qp : nullptr;
-  const size_t ctw = (size_t)2 * (ext ? qp.n : L.level) * c.n;
+  // three-part (unrelinearised) inputs: the MAC runs over three parts
+  const int parts = L.in_parts;
+  const size_t ctw = (size_t)parts * (ext ? qp.n : L.level) * c.n;
   // a slot-batched square layer's MAC writes the square's Q+B input: timed with the extension,
   // either fused into the MAC or as the separate kernel
-  const bool qb = L.packing == BCN_PACK_BATCH && L.square;
+  const bool qb = L.packing == BCN_PACK_BATCH && L.square && parts == 2;
   const size_t ctq = (size_t)2 * (L.level + c.m) * c.n;
   const int n_in_mac = L.mac.n_in;
   double* in = c.arena->take((size_t)n_in_mac * ctw);
@@ -268,7 +270,7 @@ std::string autotune_layer_mac(Context& c, Layer& L, hipStream_t s) {
       try {
         ms = time_ms_cold(s, 5, flush, kFlush, [&] {
           if (!qb) {
-            mac(c, p, in, out, L.level, s, 1, 0, 0, nullptr, 0, 0, basis);
+            mac(c, p, in, out, L.level, s, 1, 0, 0, nullptr, 0, 0, basis, parts);
           } else if (fused) {
             mac_qb(c, p, in, out, L.level, s, 1, 0, 0, nullptr, ctq, ctq / 2);
           } else {

@@ -78,6 +78,13 @@ def layer_descs(name: str):
                          out_c=lay["out"], batch=max(1, wl["batch"]), sum=moved_span,
                          features=bool(lay.get("features")))
                 moved_span = 0
+        # a square followed by a scalar dense layer (slot batching, or the dense layer a global sum
+        # was moved after) leaves its products unrelinearised; the dense layer sums over the three
+        # parts and relinearises its outputs
+        if (out and out[-1].get("square") and not out[-1].get("sum") and d["kind"] == bcn.BCN_DENSE
+                and d["packing"] == bcn.BCN_PACK_BATCH):
+            out[-1]["defer_relin"] = True
+            d["in_parts"] = 3
         out.append(d)
     return out
 

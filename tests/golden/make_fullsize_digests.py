@@ -27,7 +27,10 @@ _S = {}
 
 
 def digest(prm, ct) -> str:
-    return hashlib.sha256(np.ascontiguousarray(bfv.ct_to_rns(prm, ct), dtype="<u8").tobytes()).hexdigest()
+    """Of the [parts][level][N] residues (two parts, or three for an unrelinearised product)."""
+    parts = [ct.c0, ct.c1] + ([ct.c2] if hasattr(ct, "c2") else [])
+    res = np.stack([bfv.to_rns(p, prm.q[:ct.level]) for p in parts])
+    return hashlib.sha256(np.ascontiguousarray(res, dtype="<u8").tobytes()).hexdigest()
 
 
 def _encrypt(i):
@@ -65,7 +68,7 @@ def main():
     print("%s: keys ready in %.0fs" % (name, time.time() - t0), flush=True)
     _S.update(O=O, slots=O.input_slots())
     cts = _pool_map(_encrypt, list(range(len(_S["slots"]))), workers)
-    out = {"workload": name, "n": prm.n, "format": "sha256 of the [2][level][N] little-endian uint64 residues",
+    out = {"workload": name, "n": prm.n, "format": "sha256 of the [parts][level][N] little-endian uint64 residues (parts 3: unrelinearised)",
            "layers": [{"what": "encrypted inputs", "level": prm.L,
                        "digests": [digest(prm, cts[i]) for i in sorted(cts)]}]}
     print("%s: %d inputs encrypted at %.0fs" % (name, len(cts), time.time() - t0), flush=True)

@@ -43,3 +43,20 @@ def key_randomness(prm, seed, key_id):
     a = [synthetic.uniform_residues(seed, "ksk_a", (key_id, j), moduli, prm.n) for j in range(d)]
     e = [synthetic.gaussian_error(seed, "ksk_e", (key_id, j), prm.n) for j in range(d)]
     return a, e
+
+
+def export_rows(ctx, t):
+    """Coefficient-form residues of device rows [n][parts][level][N] (parts 2, or 3 for
+    unrelinearised products) as uint64 [n][parts][level][N]."""
+    parts = t.shape[1]
+    if parts == 2:
+        return ctx.export(t)
+    a = ctx.export(t[:, 0:2].contiguous())
+    b = ctx.export(t[:, 1:3].contiguous())
+    return np.concatenate([a, b[:, 1:2]], axis=1)
+
+
+def oracle_rows(prm, ct):
+    """[parts][level][N] residues of an oracle Ct or Ct3."""
+    parts = [ct.c0, ct.c1] + ([ct.c2] if hasattr(ct, "c2") else [])
+    return np.stack([bfv.to_rns(p, prm.q[:ct.level]) for p in parts])

@@ -238,18 +238,17 @@ def test_rotate_sum_parity(env_t2k):
     ev = env_t2k
     prm, ctx = ev["prm"], ev["ctx"]
     from paper_2402_01296_amd import bcn
-    # span 4 needs steps 2 and 1
+    # span 4: baby step 1, giant step 2
+    assert bcn.rotate_sum_steps(4) == [1, 2]
     a, e = key_randomness(prm, 32, 1002)
     ctx.keygen(ev["sk"], ev["ek"], bcn.BCN_KEY_ROTATION, 2, np.stack(a), np.stack(e))
-    g2 = bfv.galois_key(prm, ev["s"], 2, a, e)
+    gks = {1: ev["gk"][1], 2: bfv.galois_key(prm, ev["s"], 2, a, e)}
     res = random_ct_residues(prm, prm.L, 2, 50)
     ct = ctx.import_(res)
     ctx.rotate_sum(ev["ek"], ct, 4)
     got = ctx.export(ct)
     for i in range(2):
-        c = oracle_ct(prm, res[i])
-        c = bfv.add(prm, c, bfv.rotate(prm, c, 2, g2))
-        c = bfv.add(prm, c, bfv.rotate(prm, c, 1, ev["gk"][1]))
+        c = bfv.rotate_sum(prm, oracle_ct(prm, res[i]), 4, gks)
         assert (got[i] == bfv.ct_to_rns(prm, c)).all()
 
 
@@ -336,31 +335,28 @@ def test_square_paths_agree(pname, fuse_sq, ks_mode, sq_loge, fuse_md, monkeypat
         assert (got[i] == bfv.ct_to_rns(prm, ref)).all()
 
 
-@pytest.mark.parametrize("ks_mode", ["0", "1", "2"])
-def test_rotate_sum_paths_agree(ks_mode, monkeypatch):
-    """Rotate-and-sum through every key-switching path (fused: automorphism folded into the
-    digit gather; two kernels: transform-domain permutation in the inner product)."""
+@pytest.mark.parametrize("span", [2, 8, 32])
+def test_rotate_sum_spans(span):
+    """Rotate-and-sum over one round (span 2) and two rounds (baby and giant steps), at the top
+    level and at a level whose last key-switching digit holds one prime, bit-equal to the oracle."""
     torch_cuda()
     from paper_2402_01296_amd import bcn
-    monkeypatch.setenv("BCN_KS_MODE", ks_mode)
     prm, ctx = context("t2k")
     s = synthetic.ternary_secret(33, prm.n)
     sk = ctx.secret_key(s)
     ek = ctx.eval_keys()
     gk = {}
-    for r in (1, 2, 4):
+    for r in bcn.rotate_sum_steps(span):
         a, e = key_randomness(prm, 33, 1000 + r)
         ctx.keygen(sk, ek, bcn.BCN_KEY_ROTATION, r, np.stack(a), np.stack(e))
         gk[r] = bfv.galois_key(prm, [int(v) for v in s], r, a, e)
     for level in (prm.L, 3):
         res = random_ct_residues(prm, level, 2, 90 + level)
         ct = ctx.import_(res)
-        ctx.rotate_sum(ek, ct, 8)
+        ctx.rotate_sum(ek, ct, span)
         got = ctx.export(ct)
         for i in range(2):
-            c = oracle_ct(prm, res[i])
-            for r in (4, 2, 1):
-                c = bfv.add(prm, c, bfv.rotate(prm, c, r, gk[r]))
+            c = bfv.rotate_sum(prm, oracle_ct(prm, res[i]), span, gk)
             assert (got[i] == bfv.ct_to_rns(prm, c)).all(), "ct %d level %d" % (i, level)
 
 

@@ -6,7 +6,7 @@ import pytest
 
 from oracle import bfv, network, programs
 
-from gpu_util import torch_cuda
+from gpu_util import export_rows, oracle_rows, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -34,10 +34,10 @@ def test_program_parity(name):
     for li in range(len(g.layers)):
         cur_g = g.layers[li](g.ek, cur_g, g.features[li])
         cur_o = _oracle_layer(O, li, cur_o)
-        got = g.ctx.export(cur_g)
+        got = export_rows(g.ctx, cur_g)
         assert got.shape[0] == len(cur_o)
         for k in range(len(cur_o)):
-            assert (got[k] == bfv.ct_to_rns(O.prm, cur_o[k])).all(), "layer %d output %d" % (li, k)
+            assert (got[k] == oracle_rows(O.prm, cur_o[k])).all(), "layer %d output %d" % (li, k)
     vals = g.output_values(cur_g)
     want = network.run_mod_t(name, g.inputs, O.prm.t)
     assert (vals == want).all()
@@ -101,6 +101,6 @@ def test_batch_square_layer_mac_tiles(tile, fused, monkeypatch):
     for li in range(2):
         ct = g.layers[li](g.ek, ct, g.features[li])
         cur_o = _oracle_layer(O, li, cur_o)
-        got = g.ctx.export(ct)
+        got = export_rows(g.ctx, ct)
         for k in range(len(cur_o)):
-            assert (got[k] == bfv.ct_to_rns(O.prm, cur_o[k])).all(), "layer %d output %d" % (li, k)
+            assert (got[k] == oracle_rows(O.prm, cur_o[k])).all(), "layer %d output %d" % (li, k)

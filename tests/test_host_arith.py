@@ -80,3 +80,16 @@ def test_library_has_no_unresolved_internal_symbols():
                          check=True).stdout
     unresolved = [ln for ln in out.splitlines() if "bcn::" in ln]
     assert not unresolved, unresolved
+
+
+def test_rotate_sum_steps_match_the_oracle():
+    from oracle import bfv
+    from paper_2402_01296_amd import bcn
+    if not os.path.exists(bcn.LIB_PATH):
+        from paper_2402_01296_amd import build
+        build.build()
+    for k in range(1, 14):
+        span = 1 << k
+        assert bcn.rotate_sum_steps(span) == [r for rs in bfv.rotate_sum_steps(span) for r in rs]
+    with pytest.raises(bcn.BcnError):
+        bcn.rotate_sum_steps(12)

@@ -483,3 +483,75 @@ def test_mod_down_is_exact_on_multiples_of_p():
     # and rounds to nearest: P x + y with |y| < P/2 maps to x
     ys = [P // 2 - 1, -(P // 2) + 1, 1, -1, 0, 5, P // 3, -(P // 3)]
     assert bfv.mod_down(prm, [(P * v + y) % (Q * P) for v, y in zip(x, ys)], 3) == x
+
+
+def test_rotate_sum_known_answer():
+    # sum_{r < 8} Rot(c, r) as baby steps {0,1,2,3} then giant steps {0,4}, each round's taps
+    # kept over Q P (by definition, schoolbook) and rounded once; and the library's step list
+    prm = params.make("rs", 8, 30, 3, 2, 2, 17, insecure=True)
+    assert bfv.rotate_sum_steps(8) == [[1, 2, 3], [4]]
+    assert bfv.rotate_sum_steps(2) == [[1], []]
+    assert bfv.rotate_sum_steps(256) == [list(range(1, 16)), [16 * j for j in range(1, 16)]]
+    keys = {r: _tiny_key(prm, 60 + r) for r in (1, 2, 3, 4)}
+    level = 3
+    Q, P = prm.Q(level), prm.P
+    QP = Q * P
+    c0 = [(i * 0x2545F4914F6CDD1D + 7) % Q for i in range(8)]
+    c1 = [(i * 0x9E3779B97F4A7C15 + 9) % Q for i in range(8)]
+
+    def round_(c0, c1, steps):
+        A0 = [(P * v) % QP for v in c0]
+        A1 = [(P * v) % QP for v in c1]
+        for r in steps:
+            k = pow(3, r, 16)
+            s0, s1 = _sigma_signed(c0, k), [v % Q for v in _sigma_signed(c1, k)]
+            for part, acc in ((0, A0), (1, A1)):
+                u = [0] * 8
+                for j in range(prm.dnum(level)):
+                    Qj = 1
+                    for q in prm.q[j * prm.alpha:min((j + 1) * prm.alpha, level)]:
+                        Qj *= q
+                    D = [_centred(v, Qj) for v in s1]
+                    u = [a + b for a, b in zip(u, _schoolbook(D, [v % QP for v in keys[r].parts[j][part]]))]
+                if part == 0:
+                    u = [a + P * b for a, b in zip(u, s0)]
+                for i in range(8):
+                    acc[i] += u[i]
+        return [_nearest(v % QP, P) % Q for v in A0], [_nearest(v % QP, P) % Q for v in A1]
+
+    w0, w1 = round_(c0, c1, [1, 2, 3])
+    w0, w1 = round_(w0, w1, [4])
+    got = bfv.rotate_sum(prm, bfv.Ct(c0, c1, level), 8, keys)
+    assert list(got.c0) == w0 and list(got.c1) == w1
+
+
+def test_deferred_relinearisation_identity(cx):
+    # relinearising after a weighted sum of unrelinearised squares (and a modulus switch of all
+    # three parts) decrypts to the same slots as squaring, relinearising and summing:
+    # D = sum_i w_i u_i^2 mod t; the three-part product decrypts as d0 + d1 s + d2 s^2
+    prm, t = PRM, PRM.t
+    us = [_vec(prm, 40 + i) for i in range(3)]
+    ws = [3, -5, 7]
+    sq3 = [bfv.modswitch3(prm, bfv.square_unrelinearised(prm, cx.encrypt(u))) for u in us]
+    assert sq3[0].level == prm.L - 1
+    # the three-part product decrypts directly (s^2 term) before any relinearisation
+    Q = prm.Q(sq3[0].level)
+    s2 = ring.negacyclic_mul(cx.s, cx.s)
+    ph = [(a + b + c) % Q for a, b, c in zip(sq3[0].c0, ring.negacyclic_mul(sq3[0].c1, cx.s),
+                                           ring.negacyclic_mul(sq3[0].c2, s2))]
+    m0 = [nt.round_div(t * x, Q) % t for x in ph]
+    assert (cx.enc.decode(m0) == us[0] * us[0] % t).all()
+    out = bfv.relinearize3(prm, bfv.mac3(prm, sq3, ws), cx.rk)
+    want = sum(w * (u * u % t) for w, u in zip(ws, us)) % t
+    assert (cx.dec(out) == want).all()
+
+
+def test_modswitch3_known_answer_every_coefficient():
+    # each of the three parts: nearest integer to c / q_l, mod Q_{l-1}
+    prm = params.make("ms3", 8, 30, 3, 1, 1, 17, insecure=True)
+    Q = prm.Q(3)
+    ql = prm.q[2]
+    parts = [[(i * 0x9E3779B97F4A7C15 + 13 * p) % Q for i in range(8)] for p in range(3)]
+    got = bfv.modswitch3(prm, bfv.Ct3(*parts, 3))
+    for p, part in enumerate((got.c0, got.c1, got.c2)):
+        assert list(part) == [math.floor(Fraction(x, ql) + Fraction(1, 2)) % prm.Q(2) for x in parts[p]]
