@@ -1171,8 +1171,12 @@ void ks_extended(const Context& c, const double* src, size_t src_stride, int n_s
   const Basis qp = c.basis_QP(level);
   const int dnum = c.dnum(level);
   const double u2 = (double)n_out * qp.n;
-  // digits and two key parts in (the source's part 0 on the Q limbs), two parts out
-  ProfScope ps(c, "ks_ext", s, 8.0 * c.n * u2 * (dnum + 2.0 * dnum + 2.0), u2 * dnum * 2.0 * 7.0 * c.n);
+  // algorithmic bytes: each distinct limb once (every source's digits and transformed part 0, every
+  // key's two parts, the outputs); the re-reads of digits and keys by other outputs hit the caches
+  const double nk = ks.keys ? ks.nk : 1.0;
+  ProfScope ps(c, "ks_ext", s,
+               8.0 * c.n * ((double)n_src * (dnum * qp.n + level) + nk * dnum * 2.0 * qp.n + 2.0 * u2),
+               u2 * dnum * 2.0 * 7.0 * c.n);
   const int key = c.logn * 16 + c.ks_loge;
   switch (key) {
 #define BCN_KSE_CASE(LN, LE) \
@@ -1200,8 +1204,11 @@ void ks_sum_round(const Context& c, const double* src, size_t src_stride, int n,
   if (const char* e = std::getenv("BCN_KS_SUM_PER_CU")) per_cu = std::max(0.25, std::atof(e));
   const int groups = std::max(1, std::min(ks.nk, (int)((per_cu * c.n_cus) / units)));
   double* part_u = groups > 1 ? c.arena->take((size_t)groups * n * 2 * qp.n * c.n) : u;
-  // digits (once per step pass, from LDS), the steps' key words and the sum out
-  ProfScope ps(c, "ks_sum", s, 8.0 * c.n * units * (dnum + (double)ks.nk * dnum + 2.0),
+  // algorithmic bytes: each distinct limb once (the sources' digits and transformed parts, the steps'
+  // key parts, the partial sums out); products: every step's digits and P sigma(c0^) terms
+  ProfScope ps(c, "ks_sum", s,
+               8.0 * c.n * ((double)n * (dnum * qp.n + 2.0 * level) + (double)ks.nk * dnum * 2.0 * qp.n +
+                            (double)groups * n * 2.0 * qp.n),
                units * ks.nk * (dnum + 1.0) * 7.0 * c.n);
   const int key = c.logn * 16 + c.ks_loge;
   switch (key) {
