@@ -263,9 +263,11 @@ struct MacPlan {
 // basis: the limbs of each part when they are not Q_level (e.g. Q_level then P); then
 // `level` only selects the delta constants and delta_msg must be null.
 // parts = 3: rows of three-part products [3][level][N] (no delta add)
+// mul_pt: every output word is multiplied by this transform-domain plaintext [limbs][N] (the
+// inputs being in the transform domain); exclusive with delta_msg
 void mac(const Context& c, const MacPlan& p, const double* in, double* out, int level, hipStream_t s, int requests = 1,
          size_t in_req = 0, size_t out_req = 0, const double* delta_msg = nullptr, size_t out_ct = 0,
-         size_t out_part = 0, const Basis* basis = nullptr, int parts = 2);
+         size_t out_part = 0, const Basis* basis = nullptr, int parts = 2, const double* mul_pt = nullptr);
 
 // The MAC of a slot-batched layer feeding a square, writing out rows [2][level + m][N] over
 // Q_level then B (the extension fused into the MAC's stores); out_ct, out_part as for mac.

@@ -31,6 +31,7 @@ struct DeltaAdd {
   double qmodt = 0.0;           // Q_level mod t
   Mod mt{};                     // t
   double negtinv[kMaxBasis];    // -t^-1 mod q_i
+  const double* mulpt = nullptr;  // [limbs][N] transform-domain plaintext multiplied into every output word
 };
 
 template <int TO, bool CENTRE>
@@ -89,10 +90,12 @@ k_mac(const double* __restrict__ in, double* __restrict__ out, int words, int lo
   const int limb = (w >> logn) % level;
   const size_t k = (size_t)w & (((size_t)1 << logn) - 1);
 #pragma unroll
+  const double pmul = da.mulpt ? da.mulpt[((size_t)limb << logn) + k] : 0.0;
   for (int o = 0; o < TO; ++o) {
     const int row = rows[tile * TO + o];
     if (row < 0) continue;
     double r = reduce(acc[o], m);
+    if (da.mulpt) r = mul_mod(r, pmul, m);
     if (add) {
       const double mv = da.msg[blockIdx.z * da.msg_req + ((size_t)row << logn) + k];
       const double rt = mul_mod(da.qmodt, mv, da.mt);                 // [Q m]_t
@@ -793,7 +796,7 @@ void delta_consts(const Context& c, int level, double* qmodt_out, double* neg) {
 
 void mac(const Context& c, const MacPlan& p, const double* in, double* out, int level, hipStream_t s, int requests,
          size_t in_req, size_t out_req, const double* delta_msg, size_t out_ct, size_t out_part, const Basis* basis,
-         int parts) {
+         int parts, const double* mul_pt) {
   if (basis && delta_msg) throw Error(-1, "the delta add needs the Q_level basis");
   if (parts != 2 && (parts != 3 || delta_msg)) throw Error(-1, "MAC over two parts, or three without a delta add");
   const Basis b = basis ? *basis : c.basis_Q(level);
@@ -811,6 +814,8 @@ void mac(const Context& c, const MacPlan& p, const double* in, double* out, int 
     da.mt = c.mod(c.id_t);
     delta_consts(c, level, &da.qmodt, da.negtinv);
   }
+  if (mul_pt && delta_msg) throw Error(-1, "the MAC multiplies by a plaintext or adds one, not both");
+  da.mulpt = mul_pt;
   // algorithmic work: one FMA per word for each nonzero (output, input) weight
   ProfScope ps(c, "mac", s, 8.0 * words * ((double)p.n_in + p.n_out) * requests, (double)words * p.nnz * requests);
   dim3 grid(nblocks(words), p.n_tiles, requests);

@@ -330,8 +330,8 @@ void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, doub
     double* X = ar.take((size_t)nin * L.k2 * ctx);
     taps_extended(c, ek, in, H, nin, level, L.steps, X, s);
     double* U = ar.take((size_t)nout * ctx);
-    mac(c, L.mac, X, U, level, s, R, (size_t)L.n_in * L.k2 * ctx, (size_t)L.n_out * ctx, nullptr, 0, 0, &qp);
-    mul_plain_ntt(c, U, U, nout, level, L.mask_hat_qp, false, s, &qp);
+    mac(c, L.mac, X, U, level, s, R, (size_t)L.n_in * L.k2 * ctx, (size_t)L.n_out * ctx, nullptr, 0, 0, &qp, 2,
+        L.mask_hat_qp);
     ntt_inverse(c, U, 2 * nout, qp, s);
     moddown(c, U, nout, level, nullptr, 1, 0, 0, KeySel(), false, A, s);
   } else {
