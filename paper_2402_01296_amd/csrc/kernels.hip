@@ -89,8 +89,8 @@ k_mac(const double* __restrict__ in, double* __restrict__ out, int words, int lo
   const bool add = da.msg != nullptr && add_part;
   const int limb = (w >> logn) % level;
   const size_t k = (size_t)w & (((size_t)1 << logn) - 1);
-#pragma unroll
   const double pmul = da.mulpt ? da.mulpt[((size_t)limb << logn) + k] : 0.0;
+#pragma unroll
   for (int o = 0; o < TO; ++o) {
     const int row = rows[tile * TO + o];
     if (row < 0) continue;

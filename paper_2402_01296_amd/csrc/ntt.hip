@@ -151,6 +151,21 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Copies n doubles from global memory into LDS with direct global-to-LDS loads (16 bytes per lane,
+// a wave fills 1 KiB of consecutive words; no registers in between, so every load of the copy is
+// in flight at once), then waits for them and for the whole workgroup.  n must be a multiple of
+// 128 times the workgroup's waves; src and lds 16-byte aligned.
+__device__ __forceinline__ void stage_to_lds(double* lds, const double* __restrict__ src, int n, int tid,
+                                             int nthreads) {
+  const int waves = nthreads >> 6;
+  const int lane = tid & 63;
+  for (int base = (tid >> 6) * 128; base < n; base += waves * 128)
+    __builtin_amdgcn_global_load_lds((const void*)(src + base + lane * 2),
+                                     (__attribute__((address_space(3))) void*)(lds + base), 16, 0, 0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+}
+
 // One pass of the transform.  FROM_REGS: the first pass starts from the
 // registers (already in this pass's layout) instead of reading HBM.  TO_REGS:
 // the last pass leaves its results in the registers (lazy form, no final
@@ -713,9 +728,7 @@ k_ks_intt(const double* __restrict__ D, int d_div, KeySel ka, int level, int dnu
     for (int j = 0; j < dnum; ++j) {
       const double* dj = dd + (size_t)j * nb * N;
       __syncthreads();                       // the previous digit's reads are done
-#pragma unroll 4
-      for (int p = tid; p < N; p += T) lds[p] = dj[p];
-      __syncthreads();
+      stage_to_lds(lds, dj, N, tid, T);
       const double* k0 = key + ((size_t)(j * 2 + part) * KL + klimb) * N;
       const double* k1 = key + ((size_t)(j * 2 + 1) * KL + klimb) * N;
 #pragma unroll
@@ -788,9 +801,7 @@ k_ks_intt(const double* __restrict__ D, int d_div, KeySel ka, int level, int dnu
       // P sigma(c0^): the source's part 0 limb staged in LDS, read through the permutation
       const double* c0 = ext.c0hat + (size_t)(o / d_div) * ext.c0_stride + (size_t)limb * N;
       __syncthreads();
-#pragma unroll 4
-      for (int p = tid; p < N; p += T) lds[p] = c0[p];
-      __syncthreads();
+      stage_to_lds(lds, c0, N, tid, T);
       const double pm = ext.pm[limb];
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -890,9 +901,7 @@ k_ks_sum(const double* __restrict__ D, KeySel ka, int level, int dnum, int L, Ba
   for (int j = 0; j < dnum; ++j) {
     const double* dj = dd + (size_t)j * nb * N;
     __syncthreads();
-#pragma unroll 4
-    for (int p = tid; p < N; p += T) lds[p] = dj[p];
-    __syncthreads();
+    stage_to_lds(lds, dj, N, tid, T);
     for (int sel = s0; sel < s1; ++sel) {
       const int gal = ka.galois[sel];
       const double* kp = ka.keys[sel] + ((size_t)(j * 2 + part) * KL + klimb) * N;
@@ -904,9 +913,7 @@ k_ks_sum(const double* __restrict__ D, KeySel ka, int level, int dnum, int L, Ba
   if (part == 0 && limb < level) {
     const double* c0 = chat + (size_t)i * c_stride + (size_t)limb * N;
     __syncthreads();
-#pragma unroll 4
-    for (int p = tid; p < N; p += T) lds[p] = c0[p];
-    __syncthreads();
+    stage_to_lds(lds, c0, N, tid, T);
     const double pm = ext.pm[limb];
     for (int sel = s0; sel < s1; ++sel) {
       const int gal = ka.galois[sel];
