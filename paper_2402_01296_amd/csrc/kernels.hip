@@ -34,6 +34,32 @@ struct DeltaAdd {
   const double* mulpt = nullptr;  // [limbs][N] transform-domain plaintext multiplied into every output word
 };
 
+// Four inputs of a MAC column list: word w of inputs cols[0..3] (xin = in + w).
+__device__ __forceinline__ void mac_load4(double (&x)[4], const double* __restrict__ xin, const int* __restrict__ cols,
+                                          int words) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) x[u] = xin[(size_t)cols[u] * words];
+}
+
+// acc[o] += wr[u * TO + o] * x[u] over a group of four inputs (exact FP64 integer sums; with
+// CENTRE the inputs are centred and the partial sums reduced before `chunk` inputs accumulate).
+template <int TO, bool CENTRE>
+__device__ __forceinline__ void mac_group4(double (&acc)[TO], const double (&x)[4], const double* wr,
+                                           int& cnt, int chunk, Mod m, double halfq) {
+  if (CENTRE && cnt > chunk - 4) {
+#pragma unroll
+    for (int o = 0; o < TO; ++o) acc[o] = reduce_lazy(acc[o], m);
+    cnt = 0;
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const double xv = CENTRE && x[u] > halfq ? x[u] - m.q : x[u];
+#pragma unroll
+    for (int o = 0; o < TO; ++o) acc[o] = fma(wr[u * TO + o], xv, acc[o]);
+  }
+  cnt += 4;
+}
+
 template <int TO, bool CENTRE>
 __global__ void __launch_bounds__(TPB)
 k_mac(const double* __restrict__ in, double* __restrict__ out, int words, int logn, int level,
@@ -54,23 +80,47 @@ k_mac(const double* __restrict__ in, double* __restrict__ out, int words, int lo
   const double* __restrict__ xin = in + w;
   int cnt = 0;
   int e = beg;
-  for (; e + 4 <= end; e += 4) {
-    if (CENTRE && cnt > chunk - 4) {
-#pragma unroll
-      for (int o = 0; o < TO; ++o) acc[o] = reduce_lazy(acc[o], m);
-      cnt = 0;
+  if constexpr (TO <= 16) {
+    // Inputs go in groups of four through two register buffers: the loads of the next group
+    // are issued before the products of the current one, so one group's memory latency
+    // overlaps the other's FMAs.  Wider tiles keep the plain loop: one input's weights already
+    // fill 2 * TO scalar registers, and the second buffer's addresses push them into spills
+    // (and a scratch segment, which costs the launch its occupancy).
+    double xa[4], xb[4];
+    if (e + 4 <= end) mac_load4(xa, xin, tcols + e, words);   // invariant: xa holds group e whenever e + 4 <= end
+    for (; e + 8 <= end; e += 8) {
+      mac_load4(xb, xin, tcols + e + 4, words);
+      __builtin_amdgcn_sched_barrier(0);   // the loads stay ahead of the products
+      mac_group4<TO, CENTRE>(acc, xa, Wp + (size_t)e * TO, cnt, chunk, m, halfq);
+      // unconditional (a repeat of group e at the end): a branch here lets the compiler sink
+      // the products below it and keep every weight of the group live in scalar registers
+      mac_load4(xa, xin, tcols + (e + 12 <= end ? e + 8 : e), words);
+      __builtin_amdgcn_sched_barrier(0);
+      mac_group4<TO, CENTRE>(acc, xb, Wp + (size_t)(e + 4) * TO, cnt, chunk, m, halfq);
     }
-    double x[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) x[u] = xin[(size_t)tcols[e + u] * words];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const double xv = CENTRE && x[u] > halfq ? x[u] - m.q : x[u];
-      const double* __restrict__ wr = Wp + (size_t)(e + u) * TO;
-#pragma unroll
-      for (int o = 0; o < TO; ++o) acc[o] = fma(wr[o], xv, acc[o]);
+    if (e + 4 <= end) {
+      mac_group4<TO, CENTRE>(acc, xa, Wp + (size_t)e * TO, cnt, chunk, m, halfq);
+      e += 4;
     }
-    cnt += 4;
+  } else {
+    for (; e + 4 <= end; e += 4) {
+      if (CENTRE && cnt > chunk - 4) {
+#pragma unroll
+        for (int o = 0; o < TO; ++o) acc[o] = reduce_lazy(acc[o], m);
+        cnt = 0;
+      }
+      double x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[u] = xin[(size_t)tcols[e + u] * words];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double xv = CENTRE && x[u] > halfq ? x[u] - m.q : x[u];
+        const double* __restrict__ wr = Wp + (size_t)(e + u) * TO;
+#pragma unroll
+        for (int o = 0; o < TO; ++o) acc[o] = fma(wr[o], xv, acc[o]);
+      }
+      cnt += 4;
+    }
   }
   for (; e < end; ++e) {
     if (CENTRE && cnt >= chunk) {
@@ -111,6 +161,22 @@ k_mac(const double* __restrict__ in, double* __restrict__ out, int words, int lo
 // NQ limbs of the tile's TO outputs, so after the reduction (and the feature add on part 0) it
 // holds every residue of the coefficient and writes the B limbs of its centred lift too (the
 // steps of k_extend_qb): out row r is [2][NQ + m][N] over Q_level then B.  Uncentred plans only.
+// The NQ limbs of input `col` at coefficient k (xin = in + part * NQ * N + k).
+template <int NQ>
+__device__ __forceinline__ void qb_load(double (&x)[NQ], const double* __restrict__ xin, int col, size_t words,
+                                        size_t N) {
+#pragma unroll
+  for (int l = 0; l < NQ; ++l) x[l] = xin[(size_t)col * words + (size_t)l * N];
+}
+
+template <int TO, int NQ>
+__device__ __forceinline__ void qb_input(double (&acc)[TO][NQ], const double (&x)[NQ], const double* __restrict__ wr) {
+#pragma unroll
+  for (int o = 0; o < TO; ++o)
+#pragma unroll
+    for (int l = 0; l < NQ; ++l) acc[o][l] = fma(wr[o], x[l], acc[o][l]);
+}
+
 template <int TO, int NQ>
 __global__ void __launch_bounds__(TPB)
 k_mac_qb(const double* __restrict__ in, double* __restrict__ out, int logn, const double* __restrict__ Wp,
@@ -134,31 +200,19 @@ k_mac_qb(const double* __restrict__ in, double* __restrict__ out, int logn, cons
   const double* __restrict__ xin = in + (size_t)part * NQ * N + k;
   const int beg = tptr[tile], end = tptr[tile + 1];
   int e = beg;
+  // One input (its NQ limbs) per register buffer, two buffers: the next input's loads are in
+  // flight while the current one's products run.
+  double xa[NQ], xb[NQ];
+  if (e < end) qb_load(xa, xin, tcols[e], words, N);   // invariant: xa holds input e whenever e < end
   for (; e + 2 <= end; e += 2) {
-    double x[2][NQ];
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int l = 0; l < NQ; ++l) x[u][l] = xin[(size_t)tcols[e + u] * words + (size_t)l * N];
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const double* __restrict__ wr = Wp + (size_t)(e + u) * TO;
-#pragma unroll
-      for (int o = 0; o < TO; ++o)
-#pragma unroll
-        for (int l = 0; l < NQ; ++l) acc[o][l] = fma(wr[o], x[u][l], acc[o][l]);
-    }
+    qb_load(xb, xin, tcols[e + 1], words, N);
+    __builtin_amdgcn_sched_barrier(0);   // the loads stay ahead of the products
+    qb_input<TO, NQ>(acc, xa, Wp + (size_t)e * TO);
+    qb_load(xa, xin, tcols[e + 3 <= end ? e + 2 : e], words, N);   // unconditional, as in k_mac
+    __builtin_amdgcn_sched_barrier(0);
+    qb_input<TO, NQ>(acc, xb, Wp + (size_t)(e + 1) * TO);
   }
-  for (; e < end; ++e) {
-    double x[NQ];
-#pragma unroll
-    for (int l = 0; l < NQ; ++l) x[l] = xin[(size_t)tcols[e] * words + (size_t)l * N];
-    const double* __restrict__ wr = Wp + (size_t)e * TO;
-#pragma unroll
-    for (int o = 0; o < TO; ++o)
-#pragma unroll
-      for (int l = 0; l < NQ; ++l) acc[o][l] = fma(wr[o], x[l], acc[o][l]);
-  }
+  if (e < end) qb_input<TO, NQ>(acc, xa, Wp + (size_t)e * TO);
   const Conv& cv = *cvp;
   const bool add = da.msg != nullptr && part == 0;
 #pragma unroll
