@@ -366,6 +366,7 @@ Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uin
   }
   if (const char* env = std::getenv("BCN_NTT_PERSIST")) c->ntt_persist = std::atoi(env) != 0;
   if (const char* env = std::getenv("BCN_NTT_PREFETCH")) c->ntt_prefetch = std::atoi(env) != 0, c->pinned_prefetch = true;
+  if (const char* env = std::getenv("BCN_NTT_XLANE")) c->ntt_xlane = std::atoi(env) != 0, c->pinned_xlane = true;
   {
     hipDeviceProp_t prop;
     BCN_HIP(hipGetDeviceProperties(&prop, device));

@@ -159,6 +159,8 @@ struct Context {
   bool fuse_moddown = true;              // relinearisation's ModDown also scales and rounds d0, d1
   bool ntt_persist = false;              // persistent, prefetching transform kernel
   bool ntt_prefetch = false;             // transform loads the next pass's twiddles before each exchange
+  bool ntt_xlane = false;                // exchanges that are row transposes run on cross-lane moves (2^4 per thread)
+  bool pinned_xlane = false;
   int persist_blocks = 512;              // its grid: workgroups resident at once
   int n_cus = 256;                       // compute units of the device
   int ks_mode = 2;                       // key switching: 0 ModUp + NTT + inner product + INTT (four kernels),

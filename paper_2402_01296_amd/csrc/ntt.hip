@@ -143,6 +143,77 @@ constexpr bool exchange_is_wave_local() {
   return true;
 }
 
+// Transform index of register r of thread tid in pass P, for passes that hold one group
+// (2^LOGE consecutive butterfly positions per thread).
+template <int LOGN, int LOGE, bool INV, int P>
+constexpr int pass_index(int tid, int r) {
+  using S = Shape<LOGN, LOGE>;
+  constexpr int N = S::N;
+  constexpr int C = Sched<LOGN, LOGE, INV>::c(P);
+  constexpr int S0 = Sched<LOGN, LOGE, INV>::s0(P);
+  constexpr int SMIN = INV ? (1 << S0) : (N >> (S0 + C));
+  const int b = tid / SMIN, rr = tid % SMIN;
+  return (INV ? b * (SMIN << C) + rr : b * (N >> S0) + rr) + r * SMIN;
+}
+
+// True when the exchange between passes P and P + 1 is a 16 x 16 transpose inside every row of
+// 16 lanes: register r of lane l in pass P is register (l mod 16) of lane 16 floor(l / 16) + r
+// in pass P + 1.  Such an exchange can run on cross-lane moves instead of LDS.
+template <int LOGN, int LOGE, bool INV, int P>
+constexpr bool exchange_is_row_transpose() {
+  using S = Shape<LOGN, LOGE>;
+  if (LOGE != 4 || P + 1 >= S::NP) return false;
+  if (Sched<LOGN, LOGE, INV>::c(P) != LOGE || Sched<LOGN, LOGE, INV>::c(P + 1) != LOGE) return false;
+  for (int tid = 0; tid < S::T; ++tid)
+    for (int r = 0; r < 16; ++r)
+      if (pass_index<LOGN, LOGE, INV, P + 1>((tid & ~15) | r, tid & 15) != pass_index<LOGN, LOGE, INV, P>(tid, r))
+        return false;
+  return true;
+}
+
+// v of lane (l xor K) inside rows of 16 lanes: DPP quad permutations for K = 1, 2 (a VALU move),
+// the swizzle unit's bit-mask mode for K = 4, 8 (no LDS words touched).
+template <int K>
+__device__ __forceinline__ double lanes_xor(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  int lo = (int)(unsigned)b, hi = (int)(unsigned)(b >> 32);
+  if constexpr (K == 1 || K == 2) {
+    constexpr int ctrl = K == 1 ? 0xB1 : 0x4E;   // quad_perm [1,0,3,2] / [2,3,0,1]
+    lo = __builtin_amdgcn_mov_dpp(lo, ctrl, 0xF, 0xF, true);
+    hi = __builtin_amdgcn_mov_dpp(hi, ctrl, 0xF, 0xF, true);
+  } else {
+    constexpr int pat = 0x1F | (K << 10);          // and 31, or 0, xor K
+    lo = __builtin_amdgcn_ds_swizzle(lo, pat);
+    hi = __builtin_amdgcn_ds_swizzle(hi, pat);
+  }
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// One round of the row transpose: swaps bit K of the lane with bit K of the register index
+// (for each pair of registers differing in bit K, the lane whose bit K is 0 sends its upper one
+// and the other lane its lower one).
+template <int K>
+__device__ __forceinline__ void row_transpose_round(double (&x)[16], int lane) {
+  const bool up = (lane & K) != 0;
+#pragma unroll
+  for (int j0 = 0; j0 < 16; ++j0) {
+    if (j0 & K) continue;
+    const double r = lanes_xor<K>(up ? x[j0] : x[j0 | K]);
+    x[j0] = up ? r : x[j0];
+    x[j0 | K] = up ? x[j0 | K] : r;
+  }
+}
+
+// The row transpose of exchange_is_row_transpose in registers: four rounds, round k swapping
+// bit k of the lane with bit k of the register index.
+__device__ __forceinline__ void row_transpose16(double (&x)[16]) {
+  const int lane = (int)(threadIdx.x & 63);
+  row_transpose_round<1>(x, lane);
+  row_transpose_round<2>(x, lane);
+  row_transpose_round<4>(x, lane);
+  row_transpose_round<8>(x, lane);
+}
+
 // Orders one wave's LDS writes before its later reads.  A wave's LDS operations
 // execute in issue order, so only the compiler has to be kept from moving them.
 __device__ __forceinline__ void wave_sync() {
@@ -172,7 +243,8 @@ __device__ __forceinline__ void stage_to_lds(double* lds, const double* __restri
 // reduction or untwist) instead of writing HBM.  PF: every pass loads the next
 // pass's twiddles before the exchange barriers, so their latency overlaps the
 // exchange (costs registers for one more pass's twiddles).
-template <int LOGN, int LOGE, bool INV, int P, bool FROM_REGS = false, bool TO_REGS = false, bool PF = false>
+template <int LOGN, int LOGE, bool INV, int P, bool FROM_REGS = false, bool TO_REGS = false, bool PF = false,
+          bool XL = false, bool XREG = false>
 __device__ __forceinline__ void run_pass(double (&x)[1 << LOGE], double* lds, const double* __restrict__ src,
                                          double* __restrict__ a, const double* __restrict__ tw,
                                          const double* __restrict__ post, const Mod m, const int tid_in,
@@ -217,7 +289,7 @@ __device__ __forceinline__ void run_pass(double (&x)[1 << LOGE], double* lds, co
           x[g * SZ + j] = src[INV ? ntt_store(gi, LOGN) : gi];   // inverse input is transform-domain
         }
     }
-  } else {
+  } else if constexpr (!XREG) {
 #pragma unroll
     for (int g = 0; g < G; ++g)
 #pragma unroll
@@ -288,6 +360,13 @@ __device__ __forceinline__ void run_pass(double (&x)[1 << LOGE], double* lds, co
     constexpr int NT1 = PassTw<LOGN, LOGE, INV, P + 1>::NT;
     double wn[PF ? NT1 : 1];
     if constexpr (PF) load_tw<LOGN, LOGE, INV, P + 1>(wn, tw, tid);
+    if constexpr (XL && exchange_is_row_transpose<LOGN, LOGE, INV, P>()) {
+      // no LDS words are written, so no earlier reader needs a barrier
+      row_transpose16(x);
+      run_pass<LOGN, LOGE, INV, P + 1, FROM_REGS, TO_REGS, PF, XL, true>(x, lds, src, a, tw, post, m, tid, wn,
+                                                                          store_gal);
+      return;
+    }
     // A wave-local exchange inside one transform (P > 0) overwrites only words the same
     // wave read in this pass; the first exchange may overwrite words other waves read in
     // the caller's previous transform, so it keeps the workgroup barrier.
@@ -306,7 +385,7 @@ __device__ __forceinline__ void run_pass(double (&x)[1 << LOGE], double* lds, co
     } else {
       __syncthreads();
     }
-    run_pass<LOGN, LOGE, INV, P + 1, FROM_REGS, TO_REGS, PF>(x, lds, src, a, tw, post, m, tid, wn, store_gal);
+    run_pass<LOGN, LOGE, INV, P + 1, FROM_REGS, TO_REGS, PF, XL>(x, lds, src, a, tw, post, m, tid, wn, store_gal);
   }
 }
 
@@ -320,7 +399,7 @@ __device__ __forceinline__ int xcd_order(int bid, int total) {
   return x * per + min(x, rem) + bid / X;
 }
 
-template <int LOGN, int LOGE, bool INV, bool PF>
+template <int LOGN, int LOGE, bool INV, bool PF, bool XL = false>
 __global__ void __launch_bounds__(1 << (LOGN - LOGE))
 k_ntt(double* __restrict__ data, Basis basis, Tables tb) {
   constexpr int N = 1 << LOGN;
@@ -334,7 +413,7 @@ k_ntt(double* __restrict__ data, Basis basis, Tables tb) {
   const double* tw = INV ? tb.inv + (size_t)pid * N : tb.fwd + (size_t)pid * N;
   const double* post = tb.post + (size_t)pid * N;
   double x[1 << LOGE];
-  run_pass<LOGN, LOGE, INV, 0, false, false, PF>(x, lds, a, a, tw, post, m, threadIdx.x);
+  run_pass<LOGN, LOGE, INV, 0, false, false, PF, XL>(x, lds, a, a, tw, post, m, threadIdx.x);
 }
 
 // Register positions of the first pass: element (g, j) of a thread sits at
@@ -486,7 +565,9 @@ void launch(const Context& c, double* data, int n_polys, const Basis& b, hipStre
   const size_t lds = (size_t)N * sizeof(double);
   const unsigned blocks = (unsigned)n_polys * b.n;
   if (blocks == 0) return;
-  if (c.ntt_prefetch)
+  if (c.ntt_xlane && LOGE == 4)
+    hipLaunchKernelGGL((k_ntt<LOGN, LOGE, INV, false, true>), dim3(blocks), dim3(N >> LOGE), lds, s, data, b, c.tab);
+  else if (c.ntt_prefetch)
     hipLaunchKernelGGL((k_ntt<LOGN, LOGE, INV, true>), dim3(blocks), dim3(N >> LOGE), lds, s, data, b, c.tab);
   else
     hipLaunchKernelGGL((k_ntt<LOGN, LOGE, INV, false>), dim3(blocks), dim3(N >> LOGE), lds, s, data, b, c.tab);
@@ -966,6 +1047,10 @@ void set_attr() {
   BCN_HIP(hipFuncSetAttribute((const void*)k_ntt<LOGN, LOGE, true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
   BCN_HIP(hipFuncSetAttribute((const void*)k_ntt<LOGN, LOGE, false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
   BCN_HIP(hipFuncSetAttribute((const void*)k_ntt<LOGN, LOGE, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+  BCN_HIP(hipFuncSetAttribute((const void*)k_ntt<LOGN, LOGE, false, false, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+  BCN_HIP(hipFuncSetAttribute((const void*)k_ntt<LOGN, LOGE, true, false, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds));
   BCN_HIP(hipFuncSetAttribute((const void*)k_square_fused<LOGN, LOGE>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               lds));
   BCN_HIP(hipFuncSetAttribute((const void*)k_ks_fused<LOGN, LOGE, 1, false>, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -99,6 +99,21 @@ std::string autotune_ntt(Context& c, hipStream_t s) {
     report += line;
   }
   report += std::string("ntt chosen prefetch=") + (c.ntt_prefetch ? "1" : "0") + "\n";
+  if (!c.pinned_xlane && c.ntt_loge == 4) {
+    float t[2];
+    for (int xl = 0; xl < 2; ++xl) {
+      c.ntt_xlane = xl != 0;
+      t[xl] = time_ms(s, 5, [&] {
+        ntt_forward(c, buf, polys, b, s);
+        ntt_inverse(c, buf, polys, b, s);
+      });
+    }
+    c.ntt_xlane = t[1] < kMargin * t[0];
+    char line[160];
+    std::snprintf(line, sizeof line, "ntt row-transpose exchanges through LDS %.3f ms, cross-lane %.3f ms\n", t[0], t[1]);
+    report += line;
+  }
+  report += std::string("ntt chosen xlane=") + (c.ntt_xlane ? "1" : "0") + "\n";
   {
     float t[2];
     for (int pers = 0; pers < 2; ++pers) {

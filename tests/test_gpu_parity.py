@@ -295,6 +295,32 @@ def test_transform_shapes_agree(pname, persist, monkeypatch):
     assert all((o == outs[0]).all() for o in outs)
 
 
+@pytest.mark.parametrize("pname", ["t1k", "cfg2", "cfg3"])
+def test_transform_cross_lane_exchange_agrees(pname, monkeypatch):
+    """The transform whose row-transpose exchanges run on cross-lane moves (DPP quad permutations
+    and the swizzle unit instead of LDS words) computes the same exact transform, forward and
+    inverse, as the LDS exchange."""
+    torch = torch_cuda()
+    from oracle import params
+    from paper_2402_01296_amd import bcn
+    spec = params.get(pname)
+    for k, v in (("BCN_NTT_PERSIST", "0"), ("BCN_NTT_LOGE", "4"), ("BCN_NTT_PREFETCH", "0")):
+        monkeypatch.setenv(k, v)
+    outs = []
+    for xl in ("0", "1"):
+        monkeypatch.setenv("BCN_NTT_XLANE", xl)
+        ctx = bcn.Context(spec.n, spec.q[0].bit_length(), spec.L, spec.K, spec.alpha, spec.t)
+        x = np.stack([synthetic.test_poly(5, i, ctx.q, spec.n) for i in range(300)])
+        d = torch.from_numpy(x.astype(np.float64)).cuda()
+        ctx.ntt(d, 0)
+        f = d.cpu().numpy().copy()
+        ctx.ntt(d, 0, inverse=True)
+        assert (d.cpu().numpy().astype(np.uint64) == x).all()
+        outs.append(f)
+        ctx.close()
+    assert (outs[0] == outs[1]).all()
+
+
 # (parameter set, fused square, key-switch mode, square transform shape); key-switch modes:
 # 0 four kernels, 1 one fused kernel, 2 digits+NTT and inner product+INTT
 _SQUARE_PATHS = [(p, fs, km, lg) for p in ("t1k", "t2k")
