@@ -5,6 +5,16 @@
 
 namespace bcn {
 
+// Workgroups of a launch go to the eight XCDs in turn (workgroup i to XCD i mod 8) and every
+// XCD has an L2 of its own.  xcd_order renumbers the workgroups so that each XCD walks one
+// contiguous stretch of a work list: in the transforms a limb-major list, so all workgroups of
+// one limb run on one or two XCDs, whose L2 keeps that limb's twiddle (and key) tables resident.
+__device__ __forceinline__ int xcd_order(int bid, int total) {
+  constexpr int X = 8;
+  const int per = total / X, rem = total % X, x = bid % X;
+  return x * per + min(x, rem) + bid / X;
+}
+
 // Mixed-radix digits of x over the first NS limbs of cv.src.
 template <int NS>
 __device__ __forceinline__ void garner(const double (&x)[NS], double (&v)[NS], const Conv& cv, const Mod* mods) {

@@ -66,11 +66,14 @@ k_mac(const double* __restrict__ in, double* __restrict__ out, int words, int lo
       const double* __restrict__ Wp, const int* __restrict__ rows, const int* __restrict__ tptr,
       const int* __restrict__ tcols, int chunk, Basis b, const Mod* __restrict__ mods, size_t in_req,
       size_t out_req, size_t out_ct, size_t out_part, DeltaAdd da) {
-  const int w = blockIdx.x * TPB + threadIdx.x;
+  // word-block-major work list walked per XCD (the tiles of one block of words read the same
+  // inputs and share that XCD's L2); dispatch order is x fastest
+  const int wq = xcd_order(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int bx = wq / gridDim.y, tile = wq - bx * gridDim.y;
+  const int w = bx * TPB + threadIdx.x;
   if (w >= words) return;
   in += blockIdx.z * in_req;     // request blockIdx.z of a batch of independent requests
   out += blockIdx.z * out_req;
-  const int tile = blockIdx.y;
   const Mod m = mods[b.id[(w >> logn) % level]];
   const double halfq = (m.q - 1.0) * 0.5;
   double acc[TO];
@@ -184,6 +187,7 @@ k_mac_qb(const double* __restrict__ in, double* __restrict__ out, int logn, cons
          const Mod* __restrict__ mods, size_t in_req, size_t out_req, size_t out_ct, size_t out_part, DeltaAdd da,
          const Conv* __restrict__ cvp) {
   const size_t N = (size_t)1 << logn;
+  // (the word-block-major order of k_mac measured slower here: dispatch order is kept)
   const size_t w = (size_t)blockIdx.x * TPB + threadIdx.x;
   if (w >= 2 * N) return;
   in += blockIdx.z * in_req;

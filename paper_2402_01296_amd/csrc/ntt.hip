@@ -389,16 +389,6 @@ __device__ __forceinline__ void run_pass(double (&x)[1 << LOGE], double* lds, co
   }
 }
 
-// Workgroups of a launch go to the eight XCDs in turn (workgroup i to XCD i mod 8) and every
-// XCD has an L2 of its own.  xcd_order renumbers the workgroups so that each XCD walks one
-// contiguous stretch of a limb-major work list: all workgroups of one limb then run on one or
-// two XCDs, whose L2 keeps that limb's twiddle (and key) tables resident.
-__device__ __forceinline__ int xcd_order(int bid, int total) {
-  constexpr int X = 8;
-  const int per = total / X, rem = total % X, x = bid % X;
-  return x * per + min(x, rem) + bid / X;
-}
-
 template <int LOGN, int LOGE, bool INV, bool PF, bool XL = false>
 __global__ void __launch_bounds__(1 << (LOGN - LOGE))
 k_ntt(double* __restrict__ data, Basis basis, Tables tb) {
