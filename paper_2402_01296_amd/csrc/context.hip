@@ -367,6 +367,10 @@ Context* create_context(uint32_t n, uint32_t q_bits, uint32_t L, uint32_t K, uin
   if (const char* env = std::getenv("BCN_NTT_PERSIST")) c->ntt_persist = std::atoi(env) != 0;
   if (const char* env = std::getenv("BCN_NTT_PREFETCH")) c->ntt_prefetch = std::atoi(env) != 0, c->pinned_prefetch = true;
   if (const char* env = std::getenv("BCN_NTT_XLANE")) c->ntt_xlane = std::atoi(env) != 0, c->pinned_xlane = true;
+  if (const char* env = std::getenv("BCN_SPLIT_CHAIN")) c->split_chain = std::atoi(env) != 0;
+  BCN_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+  BCN_HIP(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+  BCN_HIP(hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
   {
     hipDeviceProp_t prop;
     BCN_HIP(hipGetDeviceProperties(&prop, device));
@@ -393,6 +397,9 @@ void destroy_context(Context* c) {
       (void)hipEventDestroy(pr.second);
     }
   for (auto e : c->event_pool) (void)hipEventDestroy(e);
+  if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+  if (c->join_ev) (void)hipEventDestroy(c->join_ev);
+  if (c->side) (void)hipStreamDestroy(c->side);
   release_convs(*c);
   if (c->d_tables) (void)hipFree(c->d_tables);
   if (c->d_slot_pos) (void)hipFree(c->d_slot_pos);

@@ -168,6 +168,12 @@ struct Context {
   int ks_mode_rot = 2;                   // the same for hoisted rotations (0 or 2)
   int ks_loge = 4;                       // transform shape of the two-kernel key switch
   bool pinned_ks = false;
+  // A layer's per-ciphertext chain after a slot-batched MAC (square, its relinearisation or
+  // scale-and-round) may run as two halves on two streams, so one half's kernels fill the CUs
+  // the other half's tails leave idle.  Not while profiling (per-kernel times stay serial).
+  bool split_chain = true;
+  hipStream_t side = nullptr;            // the second stream (default priority)
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   std::vector<int> ntt_loge_options() const;
 
   int idQ(int i) const { return i; }

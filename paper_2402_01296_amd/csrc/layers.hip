@@ -262,6 +262,29 @@ Layer* layer_create(Context& c, const bcn_layer_desc& d, int level) {
   return L.release();
 }
 
+namespace {
+
+// fn(first, count, stream) over ciphertexts [0, n): in two halves, the second on the context's
+// side stream (forked after the work already queued on s, joined back into s), when n is large
+// enough for two launches of each kernel to fill the device.
+template <class F>
+void run_halves(Context& c, int n, hipStream_t s, F&& fn) {
+  constexpr int kMinSplit = 32;
+  if (!c.split_chain || c.prof || n < kMinSplit) {
+    fn(0, n, s);
+    return;
+  }
+  const int h = n / 2;
+  BCN_HIP(hipEventRecord(c.fork_ev, s));
+  BCN_HIP(hipStreamWaitEvent(c.side, c.fork_ev, 0));
+  fn(0, h, s);
+  fn(h, n - h, c.side);
+  BCN_HIP(hipEventRecord(c.join_ev, c.side));
+  BCN_HIP(hipStreamWaitEvent(s, c.join_ev, 0));
+}
+
+}  // namespace
+
 void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, double* out, const float* features,
                 hipStream_t s, int R) {
   // R independent requests: in [R][n_in][in_parts][level][N] -> out [R][n_out][out_parts][level_out][N]; every step
@@ -279,6 +302,11 @@ void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, doub
   const size_t ctq = (size_t)2 * (level + c.m) * N;
   double* A = direct ? out : ar.take((size_t)nout * (qb ? ctq : ctw));
   bool b_filled = false;        // the MAC wrote the B limbs of the square's Q+B input
+  // three-part MAC outputs of a square layer: relinearised, features added and extended to Q+B
+  // per ciphertext, inside the square's per-ciphertext chain
+  const double* M3 = nullptr;
+  double* A2q = nullptr;
+  const double* fm3 = nullptr;
   if (L.packing == BCN_PACK_BATCH) {
     // slot batching: the features are quantised straight into the transform domain of R_t,
     // encoded (inverse transform mod t) and added by the MAC's own stores
@@ -297,12 +325,14 @@ void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, doub
       const size_t ct3 = (size_t)3 * level * N;
       double* M = ar.take((size_t)nout * ct3);
       mac(c, L.mac, in, M, level, s, R, (size_t)L.n_in * ct3, (size_t)L.n_out * ct3, nullptr, 0, 0, nullptr, 3);
-      double* A2 = qb ? ar.take((size_t)nout * ctw) : A;
-      relinearize3(c, ek, M, A2, nout, level, s);
-      if (fm) add_delta(c, A2, nout, level, fm, s);
       if (qb) {
-        extend_qb(c, A2, A, nout, level, s);
+        M3 = M;
+        A2q = ar.take((size_t)nout * ctw);
+        fm3 = fm;
         b_filled = true;
+      } else {
+        relinearize3(c, ek, M, A, nout, level, s);
+        if (fm) add_delta(c, A, nout, level, fm, s);
       }
     } else if (qb) {
       b_filled = L.mac_ext &&
@@ -362,10 +392,22 @@ void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, doub
     }
     return;
   }
-  if (qb && L.defer) {
-    square_defer(c, A, out, nout, level, L.modsw, s, b_filled);
-  } else if (qb) {
-    square_relin_qb(c, ek, A, out, nout, level, L.modsw, s, b_filled);
+  if (qb) {
+    const size_t ct3 = (size_t)3 * level * N;
+    const size_t out_ct = (size_t)(L.defer ? 3 : 2) * L.level_out * N;
+    run_halves(c, nout, s, [&](int o0, int cnt, hipStream_t st) {
+      double* a = A + (size_t)o0 * ctq;
+      if (M3) {
+        double* a2 = A2q + (size_t)o0 * ctw;
+        relinearize3(c, ek, M3 + (size_t)o0 * ct3, a2, cnt, level, st);
+        if (fm3) add_delta(c, a2, cnt, level, fm3 + (size_t)o0 * N, st);
+        extend_qb(c, a2, a, cnt, level, st);
+      }
+      if (L.defer)
+        square_defer(c, a, out + (size_t)o0 * out_ct, cnt, level, L.modsw, st, b_filled);
+      else
+        square_relin_qb(c, ek, a, out + (size_t)o0 * out_ct, cnt, level, L.modsw, st, b_filled);
+    });
   } else if (L.square && L.defer) {
     double* X = ar.take((size_t)nout * ctq);
     extend_qb(c, A, X, nout, level, s);
