@@ -365,9 +365,11 @@ void sum_slabs(const Context& c, const double* in, int slabs, size_t words, int 
 // inverse Galois element kinv[o].
 // Output o is written at out + (o / out_div) * out_outer + (o % out_div) * (ciphertext size);
 // out_div = 0 means contiguous outputs.
+// ext_qb (no modulus switch, contiguous outputs): out is [n][2][level+m][N] over Q_level then B,
+// and the B limbs receive the centred lift of the result (the steps of extend_qb).
 void moddown(const Context& c, const double* u, int n, int level, const double* add, int add_div, size_t add_stride,
              int add_mode, const KeySel& ks, bool modswitch, double* out, hipStream_t s, int out_div = 0,
-             size_t out_outer = 0);
+             size_t out_outer = 0, bool ext_qb = false);
 // Relinearisation's ModDown with the addend scaled and rounded inline: out = round(u/P) +
 // round(t y_k / Q_level) for parts k = 0, 1 of the square's tensor y ([n][3][level+m][N], coeff,
 // Q_level then B), optionally modulus-switched.  Returns false (nothing launched) when the

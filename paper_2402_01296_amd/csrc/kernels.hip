@@ -543,7 +543,8 @@ __global__ void __launch_bounds__(TPB)
 k_moddown(const double* __restrict__ u, int n, int logn, const double* __restrict__ add, int add_div,
           size_t add_stride, int add_mode, KeySel ks, int modsw, const Conv* __restrict__ cvp,
           const Mod* __restrict__ mods, double* __restrict__ out, int out_div, size_t out_outer,
-          const double* __restrict__ y = nullptr, const Conv* __restrict__ srcv = nullptr) {
+          const double* __restrict__ y = nullptr, const Conv* __restrict__ srcv = nullptr,
+          const Conv* __restrict__ extv = nullptr) {
   const size_t N = (size_t)1 << logn;
   const size_t idx = (size_t)blockIdx.x * TPB + threadIdx.x;
   if (idx >= (size_t)n * 2 * N) return;
@@ -587,6 +588,27 @@ k_moddown(const double* __restrict__ u, int n, int logn, const double* __restric
       r = add_mod(r, a, md);
     }
     res[d] = r;
+  }
+  if constexpr (NS == 0) {
+    if (extv) {
+      // the result over Q_level then its centred lift to B (as k_extend_qb): out [n][2][NQ+m][N]
+      const Conv& ev = *extv;
+      double* eb = out + ci * out_outer + (size_t)part * (NQ + ev.nd) * N + k;
+#pragma unroll
+      for (int d = 0; d < NQ; ++d) eb[(size_t)d * N] = res[d];
+      double w[NQ];
+      garner<NQ>(res, w, ev, mods);
+      const bool eneg = above_half<NQ>(w, NQ, ev, mods);
+      for (int d = 0; d < ev.nd; ++d) {
+        const Mod md = mods[ev.dst[d]];
+        double acc = w[NQ - 1];
+#pragma unroll
+        for (int kk = NQ - 2; kk >= 0; --kk) acc = mul_lazy(acc, ev.pm[d][kk], md) + w[kk];
+        if (eneg) acc -= ev.Mmod[d];
+        eb[(size_t)(NQ + d) * N] = reduce(acc, md);
+      }
+      return;
+    }
   }
   const int NQO = modsw ? NQ - 1 : NQ;
   double* ob = out + (ci / out_div) * out_outer + (ci % out_div) * 2 * NQO * N + (size_t)part * NQO * N + k;
@@ -1164,16 +1186,25 @@ bool moddown_scale_round(const Context& c, const double* u, int n, int level, co
 }
 
 void moddown(const Context& c, const double* u, int n, int level, const double* add, int add_div, size_t add_stride,
-             int add_mode, const KeySel& ks, bool modsw, double* out, hipStream_t s, int out_div, size_t out_outer) {
+             int add_mode, const KeySel& ks, bool modsw, double* out, hipStream_t s, int out_div, size_t out_outer,
+             bool ext_qb) {
   if (n == 0) return;
   if (modsw && level < 2) throw Error(-2, "modulus switch needs at least two primes");
+  if (ext_qb && (modsw || out_div > 0)) throw Error(-1, "ModDown with the extension to Q+B: contiguous, no switch");
   const Conv* dcv = moddown_conv(c, level);
+  const Conv* ecv = ext_qb ? extend_conv(c, level) : nullptr;
   const size_t work = (size_t)n * 2 * c.n;
-  ProfScope ps(c, "moddown", s, 8.0 * work * ((double)level + c.K + (add_mode ? level : 0) + (modsw ? level - 1 : level)));
+  ProfScope ps(c, "moddown", s,
+               8.0 * work * ((double)level + c.K + (add_mode ? level : 0) + (modsw ? level - 1 : level) + (ext_qb ? c.m : 0)));
+  if (ext_qb) {
+    out_div = 1;
+    out_outer = (size_t)2 * (level + c.m) * c.n;
+  }
 #define BCN_MD(NK, NQ) hipLaunchKernelGGL((k_moddown<NK, NQ>), dim3(nblocks(work)), dim3(TPB), 0, s, u, n, c.logn, add, \
                                           add_div, add_stride, add_mode, ks, modsw ? 1 : 0, dcv, c.tab.mods, out, \
                                           out_div > 0 ? out_div : 1, \
-                                          out_div > 0 ? out_outer : (size_t)2 * (modsw ? level - 1 : level) * c.n)
+                                          out_div > 0 ? out_outer : (size_t)2 * (modsw ? level - 1 : level) * c.n, \
+                                          nullptr, nullptr, ecv)
 #define BCN_MDQ(NK)                                                                                   \
   switch (level) {                                                                                    \
     case 1: BCN_MD(NK, 1); break; case 2: BCN_MD(NK, 2); break; case 3: BCN_MD(NK, 3); break;         \

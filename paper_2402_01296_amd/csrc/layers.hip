@@ -327,7 +327,7 @@ void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, doub
       mac(c, L.mac, in, M, level, s, R, (size_t)L.n_in * ct3, (size_t)L.n_out * ct3, nullptr, 0, 0, nullptr, 3);
       if (qb) {
         M3 = M;
-        A2q = ar.take((size_t)nout * ctw);
+        if (fm) A2q = ar.take((size_t)nout * ctw);
         fm3 = fm;
         b_filled = true;
       } else {
@@ -397,10 +397,13 @@ void layer_eval(Context& c, EvalKeys& ek, const Layer& L, const double* in, doub
     const size_t out_ct = (size_t)(L.defer ? 3 : 2) * L.level_out * N;
     run_halves(c, nout, s, [&](int o0, int cnt, hipStream_t st) {
       double* a = A + (size_t)o0 * ctq;
-      if (M3) {
+      if (M3 && !fm3) {
+        // relinearisation's ModDown writes the square's Q+B input itself
+        relinearize3(c, ek, M3 + (size_t)o0 * ct3, a, cnt, level, st, true);
+      } else if (M3) {
         double* a2 = A2q + (size_t)o0 * ctw;
         relinearize3(c, ek, M3 + (size_t)o0 * ct3, a2, cnt, level, st);
-        if (fm3) add_delta(c, a2, cnt, level, fm3 + (size_t)o0 * N, st);
+        add_delta(c, a2, cnt, level, fm3 + (size_t)o0 * N, st);
         extend_qb(c, a2, a, cnt, level, st);
       }
       if (L.defer)

@@ -81,7 +81,9 @@ void square_relin_qb(Context& c, const EvalKeys& ek, double* x, double* out, int
 void square_defer(Context& c, double* x, double* out, int n, int level, bool modsw, hipStream_t s,
                   bool b_filled = false);
 // (d0, d1, d2) [n][3][level][N] -> (d0 + KS(d2)_0, d1 + KS(d2)_1) [n][2][level][N]
-void relinearize3(Context& c, const EvalKeys& ek, const double* in, double* out, int n, int level, hipStream_t s);
+// ext_qb: out is [n][2][level+m][N] over Q_level then B, the B limbs the result's centred lift
+void relinearize3(Context& c, const EvalKeys& ek, const double* in, double* out, int n, int level, hipStream_t s,
+                  bool ext_qb = false);
 // out placement as in moddown (out_div = 0: contiguous [n_in][n_steps])
 void rotate_hoisted(Context& c, EvalKeys& ek, const double* in, int n_in, int level, const std::vector<int>& steps,
                     double* out, hipStream_t s, int out_div = 0, size_t out_outer = 0);

@@ -293,7 +293,8 @@ void square_defer(Context& c, double* x, double* out, int n, int level, bool mod
   scale_round(c, Y, out, n, level, s, false, modsw);
 }
 
-void relinearize3(Context& c, const EvalKeys& ek, const double* in, double* out, int n, int level, hipStream_t s) {
+void relinearize3(Context& c, const EvalKeys& ek, const double* in, double* out, int n, int level, hipStream_t s,
+                  bool ext_qb) {
   if (!ek.relin) throw Error(-3, "missing relinearisation key");
   if (n == 0) return;
   Arena& ar = *c.arena;
@@ -306,7 +307,7 @@ void relinearize3(Context& c, const EvalKeys& ek, const double* in, double* out,
   ks.key1 = ek.relin;
   // key switch of d2, then ModDown adds d0 and d1
   ks_split(c, in + 2 * level * N, ct3, n, level, ks, n, 1, D, U, s);
-  moddown(c, U, n, level, in, 1, ct3, 1, ks, false, out, s);
+  moddown(c, U, n, level, in, 1, ct3, 1, ks, false, out, s, 0, 0, ext_qb);
 }
 
 size_t square_relin_scratch_doubles(const Context& c, int n, int level) {
