@@ -25,6 +25,11 @@
  *    read before the call returns unless stated otherwise.
  *  - Calls on one context must be issued from one host thread on one stream
  *    (or be externally serialised): they share the context's scratch arena.
+ *  - Work is ordered on the stream passed.  Layer evaluation may fork part of
+ *    its work onto a second stream the context owns (default priority): it
+ *    forks after the work already queued on the caller's stream and joins
+ *    back into it before returning, so stream order and hipGraph capture of
+ *    the caller's stream hold as for single-stream work.
  *  - The secret key lives in client-side objects (bcn_secret_key) used only
  *    by encryption, decryption and key generation; evaluation never sees it.
  */
